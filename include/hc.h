@@ -1,0 +1,222 @@
+/*
+ * hc.h -- C ABI of the MI355X (gfx950) block-decomposed Huffman codec.
+ *
+ * The method is the one of Cloud, Curry, Ward, Skjellum and Bangalore,
+ * "Accelerating Lossless Data Compression with GPUs": the symbols of the input
+ * are counted (section 2), a Huffman code is built from the counts (section 2,
+ * Fig. 2), the input is cut into blocks holding a constant number of symbols
+ * which are encoded independently, each block carrying a 4-byte length
+ * delimiter and padded to a 4-byte boundary (section 2.1, Fig. 3 and 4), and
+ * decoding runs in parallel over the blocks from a table of block offsets
+ * (section 2.1, section 3.2).
+ *
+ * Stream format (one "stream" = the encoding of one input buffer):
+ *   for every block i = 0 .. nb-1, back to back, with no gap:
+ *     u32 little-endian  bits_i   number of payload bits of block i
+ *                                 (the sum of the code lengths of its symbols)
+ *     ceil(bits_i/32) little-endian u32 payload words; the code words of the
+ *                                 block's symbols fill them from bit 31 down to
+ *                                 bit 0, word after word; unused bits are 0.
+ *   Block i holds symbols [i*B, min(n, (i+1)*B)) of the input, nb = ceil(n/B).
+ *   Block offsets: off[0] = 0, off[i+1] = off[i] + 4 + 4*ceil(bits_i/32),
+ *   C = off[nb] is the stream size in bytes.
+ *   Codes are canonical Huffman codes (lengths from the Huffman tree, values
+ *   assigned in order of (length, symbol)), up to 64 bits long.
+ *
+ * Conventions shared by all entry points:
+ *   - Pointers named d_* are device memory owned by the caller; h_* are host
+ *     memory owned by the caller.  The library allocates memory only in
+ *     hc_codebook_upload (freed by hc_codebook_destroy); no other call
+ *     allocates or frees, and only hc_codebook_upload, hc_codebook_update
+ *     (see there) and hc_codebook_destroy wait on the device.
+ *   - 'stream' is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued on it and the call returns without waiting.
+ *   - Errors that the host can see (bad sizes, null or misaligned pointers,
+ *     too small buffers) are returned at once and enqueue nothing.
+ *   - Errors that only the data reveals (a symbol without a code, a block
+ *     longer than 2^32-1 bits, a corrupt stream) are written by the kernels to
+ *     the caller's u32 error word d_err: a kernel writes its code only if the
+ *     word still holds 0, so the word keeps the first error.  Zero it before a
+ *     sequence of calls and read it after synchronising.  After any error the
+ *     outputs of the failing call are unspecified.
+ *   - Results depend only on the inputs (bytes, n, B, S and the codebook),
+ *     never on launch shape or on the order in which atomics land.
+ *   - No call aborts, exits or throws.  Calls on different streams may run
+ *     concurrently as long as they write to different buffers.
+ *   - Alignment: d_in of hc_histogram / hc_encode_blocks, d_out of
+ *     hc_encode_blocks and hc_decode_blocks must be 16-byte aligned; the
+ *     compressed input of hc_decode_blocks / hc_walk_blocks 4-byte aligned;
+ *     u64 arrays 8-byte aligned.
+ *   - Limits: 16 <= B <= 2^26 and B % 16 == 0; sub-block stride S is 0 (no
+ *     sub-block index) or a multiple of 16.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HC_OK = 0,
+    HC_ERR_INVALID_ARG = 1,    /* bad size, null or misaligned pointer, bad codebook */
+    HC_ERR_NO_SPACE = 2,       /* an output or workspace buffer is too small */
+    HC_ERR_HIP = 3,            /* the HIP runtime reported an error */
+    HC_ERR_SYMBOL_ABSENT = 4,  /* the input holds a symbol the codebook has no code for */
+    HC_ERR_BLOCK_OVERFLOW = 5, /* a block's bit count does not fit the 4-byte header */
+    HC_ERR_CORRUPT = 6,        /* the compressed stream is not a valid encoding */
+    HC_ERR_CODE_TOO_LONG = 7   /* a Huffman code would be longer than 64 bits */
+} hc_status;
+
+/* Host description of a code: lengths and canonical code values.
+ * len[v] = 0 means symbol v has no code; code[v] holds len[v] bits,
+ * right-aligned (the first bit of the code word is bit len[v]-1). */
+typedef struct {
+    uint8_t len[256];
+    uint64_t code[256];
+    uint32_t max_len; /* longest code length, 0 if no symbol has a code */
+    uint32_t nsym;    /* number of symbols with a code */
+} hc_codebook;
+
+/* Device-resident copy of a codebook with its encode table and decode lookup
+ * tables.  Owned by the library. */
+typedef struct hc_cb_dev_s *hc_cb_handle;
+
+/* Human-readable name of a status value (static storage, never NULL). */
+const char *hc_status_str(int status);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int hc_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Symbol statistics (section 2: count every distinct symbol).            */
+/* d_hist[v] = number of bytes equal to v among d_in[0 .. n-1].           */
+/* d_in: n bytes, 16-byte aligned (may be NULL if n == 0).                */
+/* d_hist: 256 u64, overwritten (zeroed first, then filled).              */
+/* Errors: INVALID_ARG (null/misaligned pointer), HIP.                    */
+/* ---------------------------------------------------------------------- */
+hc_status hc_histogram(const uint8_t *d_in, uint64_t n, uint64_t *d_hist, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Code construction (section 2, Fig. 2), on the host.                    */
+/* Huffman code lengths from the 256 counts h_hist, then canonical code   */
+/* values.  Ties among equal weights are broken by a key (leaf v has key  */
+/* v, the t-th merged node key 256+t; the two smallest (weight, key) are  */
+/* merged first), so equal counts always give the same code.  A single    */
+/* present symbol gets a 1-bit code; no present symbol gives an empty     */
+/* codebook (max_len = 0).                                                */
+/* Errors: INVALID_ARG (null pointer, counts summing past 2^64-1),        */
+/* CODE_TOO_LONG (a code would exceed 64 bits).                           */
+/* ---------------------------------------------------------------------- */
+hc_status hc_build_codebook(const uint64_t *h_hist, hc_codebook *out);
+
+/* Canonical codebook for given code lengths (for codes built elsewhere).  */
+/* The lengths must satisfy Kraft's inequality (sum 2^-len <= 1).         */
+/* Errors: INVALID_ARG (null pointer, Kraft sum above 1),                 */
+/* CODE_TOO_LONG (a length above 64).                                     */
+hc_status hc_codebook_from_lengths(const uint8_t *h_len, hc_codebook *out);
+
+/* Copies a codebook and its lookup tables to the current device.  The    */
+/* handle stays valid until hc_codebook_destroy.  Synchronous (allocates  */
+/* device memory, a pinned host staging area and an event, and copies     */
+/* with hipMemcpy).                                                       */
+/* Errors: INVALID_ARG (null pointer, inconsistent codebook), HIP.        */
+hc_status hc_codebook_upload(const hc_codebook *cb, hc_cb_handle *out);
+
+/* Replaces the tables of an existing handle with those of another        */
+/* codebook without allocating: the tables are built on the host into a   */
+/* pinned staging area owned by the handle and copied asynchronously on   */
+/* 'stream'.  Work enqueued earlier on that stream still sees the old     */
+/* tables, work enqueued later the new ones; work on other streams that   */
+/* reads the handle must be ordered by the caller.  Waits (host side) for */
+/* the handle's previous update copy to finish before reusing the         */
+/* staging area.                                                          */
+/* Errors: INVALID_ARG (null pointer, inconsistent codebook), HIP.        */
+hc_status hc_codebook_update(hc_cb_handle h, const hc_codebook *cb, void *stream);
+
+/* Frees a handle from hc_codebook_upload (NULL is accepted).  Waits for  */
+/* the device to finish work that may still read it.                      */
+hc_status hc_codebook_destroy(hc_cb_handle cb);
+
+/* ---------------------------------------------------------------------- */
+/* Block encoding (section 2.1, Fig. 3 and 4).                            */
+/* ---------------------------------------------------------------------- */
+
+/* Upper bound of the stream size C for n symbols, block size B and codes */
+/* of at most max_len bits: sum over blocks of 4 + 4*ceil(cnt*max_len/32). */
+/* Returns 0 for B == 0 or max_len > 64.                                  */
+uint64_t hc_encode_bound(uint64_t n, uint32_t block_size, uint32_t max_len);
+
+/* Bytes of device workspace hc_encode_blocks needs for n and B.          */
+uint64_t hc_encode_workspace_bytes(uint64_t n, uint32_t block_size);
+
+/* Number of u32 entries of the sub-block index for n, B and S (0 if S == 0):
+ * nb * ceil(B / S). */
+uint64_t hc_sub_index_entries(uint64_t n, uint32_t block_size, uint32_t sub_block);
+
+/* Encodes d_in[0 .. n-1] into d_out in the stream format above.
+ *   block_size   B, symbols per block.
+ *   cb           device codebook; every symbol of the input needs a code
+ *                (else SYMBOL_ABSENT in *d_err).
+ *   d_out        out_cap bytes, 16-byte aligned; out_cap must be at least
+ *                hc_encode_bound(n, B, cb max_len).  Bytes past C are left
+ *                untouched.
+ *   d_block_off  nb + 1 u64: off[i] = byte offset of block i's header,
+ *                off[nb] = C (the offset table of section 2.1, produced here
+ *                by an exclusive scan of the block sizes).
+ *   d_sub_idx    NULL, or hc_sub_index_entries(n, B, S) u32: for block i and
+ *                chunk c, entry i*ceil(B/S)+c is the payload bit position of
+ *                the block's symbol c*S (the block's bit count if the block
+ *                has no such symbol).  An extension of the offset table that
+ *                lets decoding split a block into chunks of S symbols.
+ *   sub_block    S; must be 0 when d_sub_idx is NULL.
+ *   d_ws         hc_encode_workspace_bytes(n, B) bytes of device scratch,
+ *                8-byte aligned, owned by the caller; contents on entry are
+ *                ignored.
+ *   d_err        u32 error word (see conventions).
+ * Errors returned: INVALID_ARG, NO_SPACE, HIP.  Errors in *d_err:
+ * SYMBOL_ABSENT, BLOCK_OVERFLOW. */
+hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t block_size, hc_cb_handle cb,
+                           uint8_t *d_out, uint64_t out_cap, uint64_t *d_block_off,
+                           uint32_t *d_sub_idx, uint32_t sub_block, void *d_ws, uint64_t ws_bytes,
+                           uint32_t *d_err, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Offset table from the length delimiters (section 2.1), for a stream    */
+/* whose offsets were not kept.  Walks the nb headers one after another   */
+/* (a dependent chain: latency-bound).  d_in: in_bytes of stream, 4-byte  */
+/* aligned.  d_block_off: nb + 1 u64.  CORRUPT in *d_err if a block runs   */
+/* past in_bytes or the last block does not end at in_bytes.               */
+/* ---------------------------------------------------------------------- */
+hc_status hc_walk_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t nb, uint64_t *d_block_off,
+                         uint32_t *d_err, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Parallel block decoding (section 2.1, section 3.2).                    */
+/*   d_in, in_bytes  the stream (4-byte aligned).                          */
+/*   n, block_size   symbol count and B used to encode.                    */
+/*   cb              the encoding's codebook.                              */
+/*   d_block_off     nb + 1 u64 offsets (from hc_encode_blocks or          */
+/*                   hc_walk_blocks).                                      */
+/*   d_sub_idx, sub_block  the sub-block index written by hc_encode_blocks */
+/*                   with the same S, or NULL and 0: then each block is    */
+/*                   decoded as one piece.                                 */
+/*   d_out           n bytes, 16-byte aligned; block i goes to             */
+/*                   d_out[i*B ...].                                       */
+/* Decoding is strict: every block must use exactly its header's bit      */
+/* count (and every chunk exactly the bits the index gives it), pad bits  */
+/* must be zero, headers must agree with the offsets and the blocks must  */
+/* end exactly at in_bytes; otherwise CORRUPT in *d_err.                   */
+/* Errors returned: INVALID_ARG, HIP.                                      */
+/* ---------------------------------------------------------------------- */
+hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t n, uint32_t block_size,
+                           hc_cb_handle cb, const uint64_t *d_block_off, const uint32_t *d_sub_idx,
+                           uint32_t sub_block, uint8_t *d_out, uint32_t *d_err, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HC_H */

@@ -1,0 +1,298 @@
+"""Python binding of libhc.so, the gfx950 block-decomposed Huffman codec.
+
+Argument marshalling only: every step of the coding path runs in the HIP
+kernels of libhc.so (or, for code construction over 256 symbols, in its host
+C++).  PyTorch supplies device memory and streams.  The functions keep the
+names of the C ABI in ``include/hc.h``:
+
+    hc_histogram, hc_build_codebook, hc_codebook_from_lengths,
+    hc_codebook_upload, hc_codebook_update, hc_codebook_destroy, hc_encode_bound,
+    hc_encode_workspace_bytes, hc_sub_index_entries, hc_encode_blocks,
+    hc_walk_blocks, hc_decode_blocks, hc_status_str
+
+and add two conveniences, ``compress`` and ``decompress``, that chain them.
+u64 device buffers are held in int64 tensors and u32 ones in int32 tensors
+(same bits).  If libhc.so has not been built, importing this package fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch  # loads the HIP runtime that libhc.so then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhc.so")
+
+HC_OK = 0
+HC_ERR_INVALID_ARG = 1
+HC_ERR_NO_SPACE = 2
+HC_ERR_HIP = 3
+HC_ERR_SYMBOL_ABSENT = 4
+HC_ERR_BLOCK_OVERFLOW = 5
+HC_ERR_CORRUPT = 6
+HC_ERR_CODE_TOO_LONG = 7
+
+
+class HcError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        super().__init__(f"{what}: {hc_status_str(status)} ({status})" if what else hc_status_str(status))
+
+
+class hc_codebook(ctypes.Structure):
+    _fields_ = [
+        ("len", ctypes.c_uint8 * 256),
+        ("code", ctypes.c_uint64 * 256),
+        ("max_len", ctypes.c_uint32),
+        ("nsym", ctypes.c_uint32),
+    ]
+
+    @property
+    def lengths(self) -> np.ndarray:
+        return np.frombuffer(bytes(self.len), dtype=np.uint8).copy()
+
+    @property
+    def codes(self) -> np.ndarray:
+        return np.ctypeslib.as_array(self.code).astype(np.uint64).copy()
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python paper_1107_1525_amd/build.py` "
+        "(there is no fallback path)"
+    )
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_st = ctypes.c_int
+_sigs = {
+    "hc_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "hc_version": ([], ctypes.c_int),
+    "hc_histogram": ([_vp, _u64, _vp, _vp], _st),
+    "hc_build_codebook": ([_vp, ctypes.POINTER(hc_codebook)], _st),
+    "hc_codebook_from_lengths": ([_vp, ctypes.POINTER(hc_codebook)], _st),
+    "hc_codebook_upload": ([ctypes.POINTER(hc_codebook), ctypes.POINTER(_vp)], _st),
+    "hc_codebook_update": ([_vp, ctypes.POINTER(hc_codebook), _vp], _st),
+    "hc_codebook_destroy": ([_vp], _st),
+    "hc_encode_bound": ([_u64, _u32, _u32], _u64),
+    "hc_encode_workspace_bytes": ([_u64, _u32], _u64),
+    "hc_sub_index_entries": ([_u64, _u32, _u32], _u64),
+    "hc_encode_blocks": ([_vp, _u64, _u32, _vp, _vp, _u64, _vp, _vp, _u32, _vp, _u64, _vp, _vp], _st),
+    "hc_walk_blocks": ([_vp, _u64, _u64, _vp, _vp, _vp], _st),
+    "hc_decode_blocks": ([_vp, _u64, _u64, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp], _st),
+}
+for _name, (_args, _res) in _sigs.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+def hc_status_str(status: int) -> str:
+    return _lib.hc_status_str(int(status)).decode()
+
+
+def hc_version() -> int:
+    return _lib.hc_version()
+
+
+def _check(status: int, what: str):
+    if status != HC_OK:
+        raise HcError(status, what)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ a1: counts
+def hc_histogram(x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Symbol counts of a uint8 device tensor -> int64[256] device tensor (u64 bits)."""
+    assert x.dtype == torch.uint8 and x.is_cuda and x.is_contiguous()
+    if out is None:
+        out = torch.empty(256, dtype=torch.int64, device=x.device)
+    _check(_lib.hc_histogram(_ptr(x), x.numel(), _ptr(out), _stream(stream)), "hc_histogram")
+    return out
+
+
+# ------------------------------------------------------------------ a2: codebook
+def hc_build_codebook(hist) -> hc_codebook:
+    """Huffman lengths + canonical codes from 256 counts (host)."""
+    h = np.ascontiguousarray(np.asarray(hist).astype(np.uint64).reshape(256))
+    cb = hc_codebook()
+    _check(_lib.hc_build_codebook(h.ctypes.data_as(_vp), ctypes.byref(cb)), "hc_build_codebook")
+    return cb
+
+
+def hc_codebook_from_lengths(lengths) -> hc_codebook:
+    L = np.ascontiguousarray(np.asarray(lengths, dtype=np.uint8).reshape(256))
+    cb = hc_codebook()
+    _check(_lib.hc_codebook_from_lengths(L.ctypes.data_as(_vp), ctypes.byref(cb)), "hc_codebook_from_lengths")
+    return cb
+
+
+class DeviceCodebook:
+    """An uploaded codebook (hc_cb_handle); freed by close() or on collection."""
+
+    def __init__(self, cb: hc_codebook):
+        self.host = cb
+        self.max_len = int(cb.max_len)
+        h = ctypes.c_void_p()
+        _check(_lib.hc_codebook_upload(ctypes.byref(cb), ctypes.byref(h)), "hc_codebook_upload")
+        self.handle = h
+
+    def update(self, cb: hc_codebook, stream=None):
+        """Asynchronous table refresh on the stream (hc_codebook_update)."""
+        _check(_lib.hc_codebook_update(self.handle, ctypes.byref(cb), _stream(stream)), "hc_codebook_update")
+        self.host = cb
+        self.max_len = int(cb.max_len)
+
+    def close(self):
+        if self.handle:
+            _check(_lib.hc_codebook_destroy(self.handle), "hc_codebook_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hc_codebook_upload(cb: hc_codebook) -> DeviceCodebook:
+    return DeviceCodebook(cb)
+
+
+def hc_codebook_update(dcb: DeviceCodebook, cb: hc_codebook, stream=None):
+    dcb.update(cb, stream)
+
+
+def hc_codebook_destroy(dcb: DeviceCodebook):
+    dcb.close()
+
+
+# ------------------------------------------------------------------ a3-a5: encode
+def hc_encode_bound(n: int, block_size: int, max_len: int) -> int:
+    return int(_lib.hc_encode_bound(n, block_size, max_len))
+
+
+def hc_encode_workspace_bytes(n: int, block_size: int) -> int:
+    return int(_lib.hc_encode_workspace_bytes(n, block_size))
+
+
+def hc_sub_index_entries(n: int, block_size: int, sub_block: int) -> int:
+    return int(_lib.hc_sub_index_entries(n, block_size, sub_block))
+
+
+def num_blocks(n: int, block_size: int) -> int:
+    return (n + block_size - 1) // block_size
+
+
+def hc_encode_blocks(x: torch.Tensor, block_size: int, dcb: DeviceCodebook, out: torch.Tensor,
+                     block_off: torch.Tensor, sub_idx: Optional[torch.Tensor], sub_block: int,
+                     ws: torch.Tensor, err: torch.Tensor, stream=None) -> None:
+    """Raw call: every buffer is caller-provided (see include/hc.h)."""
+    rc = _lib.hc_encode_blocks(_ptr(x), x.numel(), block_size, dcb.handle, _ptr(out), out.numel(),
+                               _ptr(block_off), _ptr(sub_idx), sub_block, _ptr(ws), ws.numel(),
+                               _ptr(err), _stream(stream))
+    _check(rc, "hc_encode_blocks")
+
+
+def hc_walk_blocks(stream_bytes: torch.Tensor, in_bytes: int, nb: int, block_off: torch.Tensor,
+                   err: torch.Tensor, stream=None) -> None:
+    rc = _lib.hc_walk_blocks(_ptr(stream_bytes), in_bytes, nb, _ptr(block_off), _ptr(err), _stream(stream))
+    _check(rc, "hc_walk_blocks")
+
+
+def hc_decode_blocks(stream_bytes: torch.Tensor, in_bytes: int, n: int, block_size: int, dcb: DeviceCodebook,
+                     block_off: torch.Tensor, sub_idx: Optional[torch.Tensor], sub_block: int,
+                     out: torch.Tensor, err: torch.Tensor, stream=None) -> None:
+    rc = _lib.hc_decode_blocks(_ptr(stream_bytes), in_bytes, n, block_size, dcb.handle, _ptr(block_off),
+                               _ptr(sub_idx), sub_block, _ptr(out), _ptr(err), _stream(stream))
+    _check(rc, "hc_decode_blocks")
+
+
+# ------------------------------------------------------------------ conveniences
+@dataclass
+class Encoded:
+    stream: torch.Tensor      # uint8[C] view of the output buffer
+    block_off: torch.Tensor   # int64[nb + 1] (u64 offsets)
+    sub_idx: Optional[torch.Tensor]  # int32[nb * ceil(B/S)] or None
+    n: int
+    block_size: int
+    sub_block: int
+    codebook: DeviceCodebook
+
+    @property
+    def nbytes(self) -> int:
+        return int(self.stream.numel())
+
+
+def new_error_word(device) -> torch.Tensor:
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+def read_error(err: torch.Tensor) -> int:
+    return int(err.item()) & 0xFFFFFFFF
+
+
+def compress(x: torch.Tensor, block_size: int, sub_block: int = 0, codebook: Optional[DeviceCodebook] = None,
+             check: bool = True) -> Encoded:
+    """hist -> codebook -> encode on the current stream; synchronises twice
+    (histogram read-back, compressed size read-back)."""
+    dev = x.device
+    n = x.numel()
+    if codebook is None:
+        hist = hc_histogram(x).cpu().numpy().view(np.uint64)
+        cb = hc_build_codebook(hist)
+        if cb.max_len == 0:  # empty input: any one-symbol code
+            L = np.zeros(256, np.uint8)
+            L[0] = 1
+            cb = hc_codebook_from_lengths(L)
+        codebook = DeviceCodebook(cb)
+    nb = num_blocks(n, block_size)
+    cap = max(hc_encode_bound(n, block_size, codebook.max_len), 16)
+    out = torch.empty((cap + 15) // 16 * 16, dtype=torch.uint8, device=dev)
+    off = torch.empty(nb + 1, dtype=torch.int64, device=dev)
+    sub = None
+    if sub_block:
+        sub = torch.empty(max(hc_sub_index_entries(n, block_size, sub_block), 1), dtype=torch.int32, device=dev)
+    ws = torch.empty(max(hc_encode_workspace_bytes(n, block_size), 16), dtype=torch.uint8, device=dev)
+    err = new_error_word(dev)
+    hc_encode_blocks(x, block_size, codebook, out, off, sub, sub_block, ws, err)
+    C = int(off[nb].item())
+    if check:
+        e = read_error(err)
+        if e:
+            raise HcError(e, "hc_encode_blocks (device)")
+    return Encoded(out[:C], off, sub, n, block_size, sub_block, codebook)
+
+
+def decompress(enc: Encoded, out: Optional[torch.Tensor] = None, use_offsets: bool = True,
+               check: bool = True) -> torch.Tensor:
+    dev = enc.stream.device
+    if out is None:
+        out = torch.empty(max(enc.n, 16), dtype=torch.uint8, device=dev)[: enc.n]
+    err = new_error_word(dev)
+    off = enc.block_off
+    if not use_offsets:
+        off = torch.empty_like(enc.block_off)
+        hc_walk_blocks(enc.stream, enc.nbytes, num_blocks(enc.n, enc.block_size), off, err)
+    hc_decode_blocks(enc.stream, enc.nbytes, enc.n, enc.block_size, enc.codebook, off, enc.sub_idx,
+                     enc.sub_block, out, err)
+    if check:
+        e = read_error(err)
+        if e:
+            raise HcError(e, "hc_decode_blocks (device)")
+    return out

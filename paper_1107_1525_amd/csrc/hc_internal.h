@@ -1,0 +1,47 @@
+// Library-internal definitions shared by the host glue and the kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include "hc.h"
+
+namespace hc {
+
+constexpr int kNumSym = 256;
+constexpr int kMaxLen = 64;
+constexpr int kLutBits = 12;  // first-level decode table: 4096 entries
+constexpr uint16_t kLutLong = 0;         // the 12-bit prefix starts a longer code
+constexpr uint16_t kLutInvalid = 0xFFFF; // the prefix starts no code
+constexpr int kPackedMaxLen = 24;        // codes up to 24 bits fit (code << 8 | len) in a u32
+
+// Device-resident tables of one codebook (one contiguous allocation).
+struct DevTables {
+    uint32_t enc_packed[kNumSym];  // (code << 8) | len, valid when max_len <= kPackedMaxLen
+    uint64_t enc_code[kNumSym];    // right-aligned canonical code values
+    uint32_t enc_len[kNumSym];     // code lengths, 0 = no code
+    uint16_t lut[1 << kLutBits];   // next lut_bits bits -> (len << 8) | symbol
+    uint64_t first[kMaxLen + 1];   // first canonical code value of each length
+    uint32_t count[kMaxLen + 1];   // number of codes of each length
+    uint32_t base[kMaxLen + 1];    // position in 'sorted' of the first code of each length
+    uint32_t sorted[kNumSym];      // symbols in canonical order (length, value)
+    uint32_t max_len;
+    uint32_t nsym;
+    uint32_t lut_bits;             // min(max_len, kLutBits), at least 1
+    uint32_t pad_;
+};
+
+// Fills the device tables for a (validated) host codebook.
+void build_dev_tables(const hc_codebook &cb, DevTables *t);
+
+// Kraft check and canonical assignment shared by the two codebook constructors.
+hc_status canonical_from_lengths(const uint8_t *len, hc_codebook *out);
+
+}  // namespace hc
+
+struct hc_cb_dev_s {
+    hc_codebook host;
+    hc::DevTables *d_tables;  // device copy read by the kernels
+    hc::DevTables *staging;   // pinned host staging area for updates
+    void *copy_done;          // hipEvent_t recorded after the last update copy
+    int device;
+};

@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work, so the bar is bit-exact equality of histograms, code lengths,
+code values, block bit counts, offsets, sub-block index, stream bytes and
+decoded bytes.  Full-size workloads are checked on sampled blocks (each block
+is an independent encoding, so the oracle can encode a sampled block alone)
+plus properties that hold at any size (round trip, size = sum of block sizes).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KIB, MIB = synth.KIB, synth.MIB
+
+
+@pytest.fixture(scope="module")
+def hc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1107_1525_amd as hc_mod
+
+    return hc_mod
+
+
+def dev(x: np.ndarray) -> torch.Tensor:
+    t = torch.empty(max(x.size, 16), dtype=torch.uint8, device="cuda")[: x.size]
+    t.copy_(torch.from_numpy(np.ascontiguousarray(x)))
+    return t
+
+
+def u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def check_full(hc, oracle, x: np.ndarray, B: int, S: int = 0, tag: str = ""):
+    """Every output against the oracle, element by element."""
+    print(f"[parity] {tag} n={x.size} B={B} S={S}", flush=True)
+    xd = dev(x)
+    h_gpu = u64(hc.hc_histogram(xd))
+    h_or = oracle.histogram(x)
+    assert np.array_equal(h_gpu, h_or)
+    cb = hc.hc_build_codebook(h_gpu)
+    L, C = oracle.codebook(h_or)
+    assert np.array_equal(cb.lengths, L) and np.array_equal(cb.codes, C)
+    enc = hc.compress(xd, B, sub_block=S, codebook=hc.DeviceCodebook(cb))
+    s_or, off_or, bits_or = oracle.encode(x, B, L, C)
+    assert np.array_equal(u64(enc.block_off), off_or)
+    assert enc.nbytes == s_or.size
+    assert np.array_equal(enc.stream.cpu().numpy(), s_or)
+    if S:
+        assert np.array_equal(u32(enc.sub_idx)[: hc.hc_sub_index_entries(x.size, B, S)],
+                              oracle.sub_index(x, B, S, L))
+    y = hc.decompress(enc)
+    assert torch.equal(y, xd)
+    y2 = hc.decompress(enc, use_offsets=False)  # offsets rebuilt by walking the headers
+    assert torch.equal(y2, xd)
+    return enc
+
+
+# ------------------------------------------------------------------ histogram
+@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 4095, 131072 + 5, (1 << 20) + 7, 3 * MIB + 1])
+@pytest.mark.parametrize("kind", ["zipf", "uniform", "skewed", "const"])
+def test_histogram(hc, oracle, n, kind):
+    if kind == "zipf":
+        x = synth.zipf_bytes(n, 1.2, n + 1)
+    elif kind == "uniform":
+        x = synth.uniform_bytes(n, n + 2)
+    elif kind == "skewed":
+        x = synth.skewed_bytes(n, n + 3)
+    else:
+        x = np.full(n, 0xA5, np.uint8)
+    assert np.array_equal(u64(hc.hc_histogram(dev(x))), oracle.histogram(x))
+
+
+# ------------------------------------------------------------------ small full parity
+def test_small_workload_1mib(hc, oracle):
+    spec = synth.WORKLOADS["zipf1.2-1MiB-B4KiB"]
+    x = synth.zipf_bytes(spec["n"], spec["s"], synth.derive_seed(spec["config_id"], 0))
+    check_full(hc, oracle, x, spec["block"], 0, "1MiB zipf1.2 B=4KiB")
+    check_full(hc, oracle, x, spec["block"], 1024, "1MiB zipf1.2 B=4KiB S=1KiB")
+
+
+@pytest.mark.parametrize("B,S", [(16, 0), (48, 16), (4096, 256), (4112, 0), (6016, 512), (16384, 1024),
+                                 (65536, 4096), (262144, 0), (1 << 20, 65536)])
+def test_block_sizes(hc, oracle, B, S):
+    x = synth.zipf_bytes(2 * MIB + 333, 1.1, B)
+    check_full(hc, oracle, x, B, S, "zipf1.1 ragged")
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 4095, 4096, 4097, 8191, 8193, 65535, 65536, 65537])
+def test_ragged_sizes(hc, oracle, n):
+    x = synth.zipf_bytes(n, 1.3, 7 * n)
+    check_full(hc, oracle, x, 4096, 0, "ragged")
+    check_full(hc, oracle, x, 65536, 1024, "ragged multi-tile")
+
+
+@pytest.mark.parametrize("kind", ["uniform", "skewed", "fp32"])
+def test_segment_kinds(hc, oracle, kind):
+    x = synth.segment_bytes(kind, 3 * MIB, 11)
+    for B in (4 * KIB, 16 * KIB, 64 * KIB, 256 * KIB):
+        check_full(hc, oracle, x, B, 1024 if B > 4 * KIB else 0, kind)
+
+
+def test_single_symbol(hc, oracle):
+    x = np.full(100_000, 42, np.uint8)
+    enc = check_full(hc, oracle, x, 4096, 512, "single symbol")
+    assert enc.codebook.max_len == 1
+
+
+def test_all_symbols_equal_counts(hc, oracle):
+    x = np.tile(np.arange(256, dtype=np.uint8), 4096)
+    np.random.default_rng(1).shuffle(x)
+    check_full(hc, oracle, x, 16384, 1024, "all 256 symbols")
+
+
+def _codebook_from_counts(hc, oracle, counts):
+    h = np.zeros(256, np.uint64)
+    h[: len(counts)] = counts
+    cb = hc.hc_build_codebook(h)
+    L, C = oracle.codebook(h)
+    assert np.array_equal(cb.lengths, L) and np.array_equal(cb.codes, C)
+    return cb, L, C
+
+
+@pytest.mark.parametrize("m", [14, 20, 26, 33, 45, 65])
+def test_long_codes(hc, oracle, m):
+    """Fibonacci counts give codes of m-1 bits: the LUT fallback (>12 bits),
+    the 24-bit packed table limit and the 64-bit general path."""
+    fib = [1, 1]
+    while len(fib) < m:
+        fib.append(fib[-1] + fib[-2])
+    cb, L, C = _codebook_from_counts(hc, oracle, fib)
+    assert cb.max_len == m - 1
+    rng = np.random.default_rng(m)
+    x = rng.integers(0, m, size=300_001).astype(np.uint8)  # every symbol, long codes frequent
+    xd = dev(x)
+    for B, S in ((4096, 0), (16384, 1024), (65536, 4096)):
+        enc = hc.compress(xd, B, sub_block=S, codebook=hc.DeviceCodebook(cb))
+        s_or, off_or, _ = oracle.encode(x, B, L, C)
+        assert np.array_equal(u64(enc.block_off), off_or)
+        assert np.array_equal(enc.stream.cpu().numpy(), s_or)
+        if S:
+            assert np.array_equal(u32(enc.sub_idx), oracle.sub_index(x, B, S, L))
+        assert torch.equal(hc.decompress(enc), xd)
+
+
+def test_determinism(hc, oracle):
+    x = synth.skewed_bytes(5 * MIB + 3, 5)
+    xd = dev(x)
+    a = hc.compress(xd, 16384, sub_block=1024)
+    b = hc.compress(xd, 16384, sub_block=1024)
+    assert torch.equal(a.stream, b.stream) and torch.equal(a.block_off, b.block_off)
+    assert torch.equal(a.sub_idx, b.sub_idx)
+
+
+# ------------------------------------------------------------------ errors
+def test_symbol_absent(hc, oracle):
+    L = np.zeros(256, np.uint8)
+    L[[1, 2]] = 1
+    cb = hc.DeviceCodebook(hc.hc_codebook_from_lengths(L))
+    with pytest.raises(hc.HcError) as e:
+        hc.compress(dev(np.array([1, 2, 3] * 100, np.uint8)), 64, codebook=cb)
+    assert e.value.status == hc.HC_ERR_SYMBOL_ABSENT
+
+
+def _decode_status(hc, stream_np, enc, n=None, sub=True):
+    err = hc.new_error_word("cuda")
+    s = dev(stream_np)
+    n = enc.n if n is None else n
+    out = torch.empty(max(n, 16), dtype=torch.uint8, device="cuda")
+    nb = hc.num_blocks(n, enc.block_size)
+    off = torch.zeros(nb + 1, dtype=torch.int64, device="cuda")
+    hc.hc_walk_blocks(s, s.numel(), nb, off, err)
+    if hc.read_error(err):
+        return hc.read_error(err)
+    use_sub = sub and enc.sub_idx is not None and n == enc.n
+    hc.hc_decode_blocks(s, s.numel(), n, enc.block_size, enc.codebook, off,
+                        enc.sub_idx if use_sub else None, enc.sub_block if use_sub else 0, out, err)
+    return hc.read_error(err)
+
+
+def test_corruption_matches_oracle(hc, oracle):
+    x = synth.zipf_bytes(200_000, 1.2, 1)
+    B = 4096
+    enc = hc.compress(dev(x), B, sub_block=1024)
+    L = enc.codebook.host.lengths
+    s0 = enc.stream.cpu().numpy()
+    off = u64(enc.block_off)
+    bits = np.array([int.from_bytes(s0[int(o):int(o) + 4].tobytes(), "little") for o in off[:-1]])
+    assert _decode_status(hc, s0, enc) == 0 and oracle.decode_status(s0, x.size, B, L)[0] == 0
+    cases = {}
+    s = s0.copy(); s[int(off[5])] ^= 1; cases["header bit"] = s
+    s = s0.copy(); s[int(off[-2]) + 3] = 0x7F; cases["header too large"] = s
+    i = next(i for i in range(bits.size) if bits[i] % 32)
+    pb = int(bits[i]); w = int(off[i]) + 4 + 4 * (pb // 32); pos = 31 - pb % 32
+    s = s0.copy(); s[w + pos // 8] |= 1 << (pos % 8); cases["nonzero pad"] = s
+    cases["truncated"] = s0[:-4].copy()
+    cases["trailing"] = np.concatenate([s0, np.zeros(4, np.uint8)])
+    for name, s in cases.items():
+        st_or = oracle.decode_status(s, x.size, B, L)[0]
+        st_gpu = _decode_status(hc, s, enc)
+        assert st_or == oracle.ERR_CORRUPT, name
+        assert st_gpu == hc.HC_ERR_CORRUPT, name
+    # wrong symbol count
+    assert _decode_status(hc, s0, enc, n=x.size + B, sub=False) == hc.HC_ERR_CORRUPT
+    # a sub-block index that disagrees with the stream
+    bad = enc.sub_idx.clone()
+    bad[1] += 1
+    err = hc.new_error_word("cuda")
+    out = torch.empty(x.size, dtype=torch.uint8, device="cuda")
+    hc.hc_decode_blocks(enc.stream, enc.nbytes, enc.n, B, enc.codebook, enc.block_off, bad, 1024, out, err)
+    assert hc.read_error(err) == hc.HC_ERR_CORRUPT
+
+
+def test_invalid_code_foreign_codebook(hc, oracle):
+    L = np.zeros(256, np.uint8)
+    L[[1, 2]] = [1, 2]  # "11" is no code
+    cb = hc.DeviceCodebook(hc.hc_codebook_from_lengths(L))
+    x = np.array([1, 2, 1, 1] * 8, np.uint8)
+    enc = hc.compress(dev(x), 16, codebook=cb)
+    s = enc.stream.cpu().numpy().copy()
+    s[4 + 3] |= 0xC0
+    assert oracle.decode_status(s, x.size, 16, L)[0] == oracle.ERR_CORRUPT
+    assert _decode_status(hc, s, enc, sub=False) == hc.HC_ERR_CORRUPT
+
+
+# ------------------------------------------------------------------ full-size workloads, sampled
+def _sampled_blocks(hc, oracle, x_dev, enc, L, C, nsample, rng):
+    n, B = enc.n, enc.block_size
+    nb = hc.num_blocks(n, B)
+    off = u64(enc.block_off)
+    picks = sorted(set([0, nb - 1] + rng.integers(0, nb, size=nsample).tolist()))
+    for i in picks:
+        a = i * B
+        blk = x_dev[a:a + B].cpu().numpy()
+        s_or, off_or, _ = oracle.encode(blk, B, L, C)
+        got = enc.stream[int(off[i]):int(off[i + 1])].cpu().numpy()
+        assert np.array_equal(got, s_or), f"block {i}"
+        if enc.sub_idx is not None:
+            cpb = (B + enc.sub_block - 1) // enc.sub_block
+            assert np.array_equal(u32(enc.sub_idx[i * cpb:(i + 1) * cpb]),
+                                  oracle.sub_index(blk, B, enc.sub_block, L)), f"index {i}"
+
+
+def test_single_stream_256mib(hc, oracle):
+    spec = synth.WORKLOADS["zipf1.1-256MiB-B64KiB"]
+    n, B = spec["n"], spec["block"]
+    print(f"[parity] 256MiB zipf1.1 B=64KiB", flush=True)
+    x = synth.zipf_bytes_torch(n, spec["s"], synth.derive_seed(spec["config_id"], 0))
+    h = u64(hc.hc_histogram(x))
+    x_host = x.cpu().numpy()
+    assert np.array_equal(h, oracle.histogram(x_host))
+    cb = hc.hc_build_codebook(h)
+    L, C = oracle.codebook(h)
+    assert np.array_equal(cb.lengths, L) and np.array_equal(cb.codes, C)
+    enc = hc.compress(x, B, sub_block=1024, codebook=hc.DeviceCodebook(cb))
+    bits_or = oracle.block_bits(x_host, B, L)
+    off_or = np.concatenate([[0], np.cumsum(4 + 4 * ((bits_or + 31) // 32))]).astype(np.uint64)
+    assert np.array_equal(u64(enc.block_off), off_or)
+    _sampled_blocks(hc, oracle, x, enc, L, C, 24, np.random.default_rng(2))
+    assert torch.equal(hc.decompress(enc), x)
+
+
+def test_mixed_4gib_sampled(hc, oracle):
+    """The 4 GiB mixed workload: 64 segments of 64 MiB with their own codebooks,
+    at every block size the benchmark sweeps, with the launch shapes it uses."""
+    spec = synth.WORKLOADS["mixed-4GiB-64x64MiB"]
+    seg = spec["segment"]
+    nseg = spec["n"] // seg
+    rng = np.random.default_rng(3)
+    x = torch.empty(spec["n"], dtype=torch.uint8, device="cuda")
+    for t in range(nseg):
+        synth.segment_bytes_torch(synth.mixed_kind(t), seg, synth.derive_seed(spec["config_id"], t),
+                                  out=x[t * seg:(t + 1) * seg])
+    checked = {0, 1, 2, nseg - 1}
+    for t in range(nseg):
+        xs = x[t * seg:(t + 1) * seg]
+        h = u64(hc.hc_histogram(xs))
+        assert int(h.sum()) == seg
+        if t in checked:
+            print(f"[parity] 4GiB segment {t} ({synth.mixed_kind(t)})", flush=True)
+            assert np.array_equal(h, oracle.histogram(xs.cpu().numpy()))
+            cb = hc.hc_build_codebook(h)
+            L, C = oracle.codebook(h)
+            assert np.array_equal(cb.lengths, L) and np.array_equal(cb.codes, C)
+            dcb = hc.DeviceCodebook(cb)
+            for B in spec["blocks"]:
+                enc = hc.compress(xs, B, sub_block=1024 if B > 4 * KIB else 0, codebook=dcb)
+                _sampled_blocks(hc, oracle, xs, enc, L, C, 4, rng)
+                assert torch.equal(hc.decompress(enc), xs)
+    del x
+    torch.cuda.empty_cache()
