@@ -1,0 +1,322 @@
+"""Benchmark of the block-decomposed Huffman codec on one MI355X.
+
+One step = the whole coding path over the 4 GiB mixed workload (64 segments of
+64 MiB cycling uniform / skewed / fp32 bytes, one codebook per segment):
+
+  1. symbol counts of every segment                 (hc_histogram, GPU)
+  2. read-back of the 64 histograms (16 KiB)
+  3. Huffman code + canonical codes per segment    (hc_build_codebook, host)
+     and refresh of the device tables              (hc_codebook_update, async)
+  4. block encode of every segment: length pass, offset scan, bit packing
+                                                    (hc_encode_blocks, GPU)
+  5. block decode of every segment from the encoder's offsets and sub-block
+     index                                          (hc_decode_blocks, GPU)
+
+Inputs are resident in HBM before timing starts.  The JSON line reports the
+whole-step throughput in uncompressed GB/s, the per-phase rates, the roofline
+of the dominant kernel (its algorithmic bytes per launch over its average
+launch time, timed with HIP events on the stream it runs on), and the CPU
+oracle timed on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--block B] [--sub-block S]
+  python bench.py --sweep          # block size / sub-block sweep, one line each
+  python bench.py --copy-probe     # plain device copy: achievable HBM GB/s
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "compress/decompress GB/s (uncompressed) and % HBM peak; batched p50/p99 latency"
+WORKLOAD = "mixed-4GiB-64x64MiB"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--block", type=int, default=64 * 1024)
+    ap.add_argument("--sub-block", type=int, default=1024)
+    ap.add_argument("--segments", type=int, default=64, help="number of 64 MiB segments (64 = 4 GiB)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("hc_kernels.hip", "hc_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1107_1525_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+class Workload:
+    """The 4 GiB mixed buffer and every device buffer one step needs."""
+
+    def __init__(self, hc, synth, torch, nseg, B, S):
+        self.hc, self.torch = hc, torch
+        self.seg = synth.WORKLOADS[WORKLOAD]["segment"]
+        self.nseg = nseg
+        self.n = self.seg * nseg
+        self.B, self.S = B, S
+        dev = "cuda"
+        self.x = torch.empty(self.n, dtype=torch.uint8, device=dev)
+        self.kinds = []
+        for t in range(nseg):
+            kind = synth.mixed_kind(t)
+            self.kinds.append(kind)
+            synth.segment_bytes_torch(kind, self.seg, synth.derive_seed(3, t), out=self.x[t * self.seg:(t + 1) * self.seg])
+        self.hist = torch.zeros((nseg, 256), dtype=torch.int64, device=dev)
+        self.hist_host = torch.zeros((nseg, 256), dtype=torch.int64).pin_memory()
+        # codebooks of the data (fixed across steps) size the output buffers
+        for t in range(nseg):
+            hc.hc_histogram(self.xs(t), out=self.hist[t])
+        h = self.hist.cpu().numpy().view("uint64")
+        cbs = [hc.hc_build_codebook(h[t]) for t in range(nseg)]
+        self.dcb = [hc.DeviceCodebook(cb) for cb in cbs]
+        self.nb = hc.num_blocks(self.seg, B)
+        self.cap = [(hc.hc_encode_bound(self.seg, B, cb.max_len) + 255) // 256 * 256 for cb in cbs]
+        self.out_base = [0]
+        for c in self.cap:
+            self.out_base.append(self.out_base[-1] + c)
+        self.out = torch.empty(self.out_base[-1], dtype=torch.uint8, device=dev)
+        self.off = torch.empty((nseg, self.nb + 1), dtype=torch.int64, device=dev)
+        self.nsub = hc.hc_sub_index_entries(self.seg, B, S) if S else 0
+        self.sub = torch.empty((nseg, max(self.nsub, 1)), dtype=torch.int32, device=dev) if S else None
+        self.ws = torch.empty(hc.hc_encode_workspace_bytes(self.seg, B), dtype=torch.uint8, device=dev)
+        self.y = torch.empty(self.n, dtype=torch.uint8, device=dev)
+        self.err = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.C = None
+
+    def xs(self, t):
+        return self.x[t * self.seg:(t + 1) * self.seg]
+
+    def ys(self, t):
+        return self.y[t * self.seg:(t + 1) * self.seg]
+
+    def outs(self, t):
+        return self.out[self.out_base[t]:self.out_base[t] + self.cap[t]]
+
+    def subs(self, t):
+        return self.sub[t] if self.S else None
+
+    def step(self, ev=None):
+        """One pass of the whole path.  ev: optional dict of per-launch event lists."""
+        hc, torch = self.hc, self.torch
+        E = torch.cuda.Event
+        for t in range(self.nseg):
+            hc.hc_histogram(self.xs(t), out=self.hist[t])
+        self.hist_host.copy_(self.hist, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        h = self.hist_host.numpy().view("uint64")
+        for t in range(self.nseg):
+            self.dcb[t].update(hc.hc_build_codebook(h[t]))
+        for t in range(self.nseg):
+            if ev is not None:
+                ev["enc"][t][0].record()
+            hc.hc_encode_blocks(self.xs(t), self.B, self.dcb[t], self.outs(t), self.off[t], self.subs(t), self.S,
+                                self.ws, self.err)
+            if ev is not None:
+                ev["enc"][t][1].record()
+        if self.C is None:
+            self.C = [int(v) for v in self.off[:, self.nb].cpu()]
+        for t in range(self.nseg):
+            if ev is not None:
+                ev["dec"][t][0].record()
+            hc.hc_decode_blocks(self.outs(t), self.C[t], self.seg, self.B, self.dcb[t], self.off[t], self.subs(t),
+                                self.S, self.ys(t), self.err)
+            if ev is not None:
+                ev["dec"][t][1].record()
+
+
+def time_phases(w, torch, reps=3):
+    """Per-phase GPU times (ms per step) from HIP events around each launch."""
+    E = torch.cuda.Event
+    res = {"hist": [], "enc": [], "dec": []}
+    hc = w.hc
+    for _ in range(reps):
+        e_h = [(E(enable_timing=True), E(enable_timing=True)) for _ in range(w.nseg)]
+        for t in range(w.nseg):
+            e_h[t][0].record()
+            hc.hc_histogram(w.xs(t), out=w.hist[t])
+            e_h[t][1].record()
+        ev = {k: [(E(enable_timing=True), E(enable_timing=True)) for _ in range(w.nseg)] for k in ("enc", "dec")}
+        w.step(ev)
+        torch.cuda.synchronize()
+        res["hist"].append([a.elapsed_time(b) for a, b in e_h])
+        res["enc"].append([a.elapsed_time(b) for a, b in ev["enc"]])
+        res["dec"].append([a.elapsed_time(b) for a, b in ev["dec"]])
+    return res
+
+
+def cpu_baseline(w, oracle, np):
+    """The oracle, single-threaded, on segments 0..2 (one of each kind) of the
+    same workload: counts, code, block encode and strict decode."""
+    t_total = 0.0
+    nbytes = 0
+    for t in range(3):
+        x = w.xs(t).cpu().numpy()
+        t0 = time.perf_counter()
+        h = oracle.histogram(x)
+        L, C = oracle.codebook(h)
+        s, off, bits = oracle.encode(x, w.B, L, C)
+        y = oracle.decode(s, x.size, w.B, L)
+        t_total += time.perf_counter() - t0
+        assert np.array_equal(y, x)
+        nbytes += x.size
+    return {
+        "value": round(nbytes / t_total / 1e9, 4),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"segments 0-2 (uniform, skewed, fp32) of the 4 GiB mixed workload, {nbytes >> 20} MiB, "
+                  f"B={w.B}: counts + code + block encode + strict decode, one thread",
+        "seconds": round(t_total, 2),
+    }
+
+
+def load_traffic(kernel: str, B: int, S: int):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
+    were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{WORKLOAD}_B{B}_S{S}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def copy_probe(torch):
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    E = torch.cuda.Event
+    s, e = E(enable_timing=True), E(enable_timing=True)
+    reps = 20
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    print(json.dumps({"probe": "device copy", "bytes_read": n, "bytes_written": n, "ms": round(ms, 4),
+                      "GBps_read_plus_write": round(2 * n / ms / 1e6, 1)}), flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the codec has no multi-GPU path in this build "
+              "(segments shard with no exchange; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1107_1525_amd as hc
+    import synth
+
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
+
+    configs = [(args.block, args.sub_block)]
+    if args.sweep:
+        configs = [(B, S) for B in (4096, 16384, 65536, 262144) for S in ((0,) if B == 4096 else (0, 512, 1024, 4096))]
+
+    for B, S in configs:
+        print(f"[bench] setting up {args.segments} x 64 MiB, B={B} S={S}", file=sys.stderr, flush=True)
+        w = Workload(hc, synth, torch, args.segments, B, S)
+        for _ in range(args.warmup):
+            w.step()
+        torch.cuda.synchronize()
+        if hc.read_error(w.err):
+            raise hc.HcError(hc.read_error(w.err), "warmup")
+        # correctness of the timed configuration: decode must reproduce the input
+        assert torch.equal(w.y, w.x), "round trip failed"
+        print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            w.step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if hc.read_error(w.err):
+            raise hc.HcError(hc.read_error(w.err), "timed steps")
+        ms_step = wall * 1e3 / args.steps
+        ph = time_phases(w, torch)
+        med = lambda v: float(np.median(v))
+        hist_ms = med([sum(r) for r in ph["hist"]])
+        enc_ms = med([sum(r) for r in ph["enc"]])
+        dec_ms = med([sum(r) for r in ph["dec"]])
+        enc_launch_ms = med([m for r in ph["enc"] for m in r])
+        dec_launch_ms = med([m for r in ph["dec"] for m in r])
+        n = w.n
+        C = sum(w.C)
+        off_bytes = 8 * (w.nb + 1) * w.nseg
+        sub_bytes = 4 * w.nsub * w.nseg
+        gb = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
+        # algorithmic bytes: what each step must move, not what it happens to move
+        enc_alg = n + C + off_bytes + sub_bytes
+        dec_alg = C + n + off_bytes + sub_bytes
+        phases = {
+            "hist_GBps": round(gb(n, hist_ms), 1),
+            "encode_GBps": round(gb(n, enc_ms), 1),
+            "decode_GBps": round(gb(n, dec_ms), 1),
+            "compress_GBps": round(gb(n, hist_ms + enc_ms), 1),
+            "hist_ms": round(hist_ms, 3), "encode_ms": round(enc_ms, 3), "decode_ms": round(dec_ms, 3),
+            "encode_pct_hbm": round(100 * gb(enc_alg, enc_ms) / HBM_PEAK_GBPS, 1),
+            "decode_pct_hbm": round(100 * gb(dec_alg, dec_ms) / HBM_PEAK_GBPS, 1),
+            "ratio": round(C / n, 5),
+        }
+        dominant = "k_decode" if dec_ms >= enc_ms else "hc_encode_blocks"
+        if dominant == "k_decode":
+            per_launch = dec_alg / w.nseg
+            launch_ms = dec_launch_ms
+        else:
+            per_launch = enc_alg / w.nseg
+            launch_ms = enc_launch_ms
+        achieved = per_launch / (launch_ms * 1e-3) / 1e9
+        roofline = {
+            "bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": load_traffic(dominant, B, S),
+            "bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4),
+        }
+        line = {
+            "metric": METRIC, "value": round(gb(n, ms_step), 2), "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": WORKLOAD, "bytes": n, "segments": w.nseg, "block_size": B, "sub_block": S,
+                       "parallelism": "single-gpu"},
+            "phases": phases, "roofline": roofline,
+        }
+        if not args.no_cpu_baseline and not args.sweep:
+            print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline(w, __import__("oracle"), np)
+        print(json.dumps(line), flush=True)
+        del w
+        torch.cuda.empty_cache()
+
+
+if __name__ == "__main__":
+    main()

@@ -43,10 +43,10 @@
  *     never on launch shape or on the order in which atomics land.
  *   - No call aborts, exits or throws.  Calls on different streams may run
  *     concurrently as long as they write to different buffers.
- *   - Alignment: d_in of hc_histogram / hc_encode_blocks, d_out of
- *     hc_encode_blocks and hc_decode_blocks must be 16-byte aligned; the
- *     compressed input of hc_decode_blocks / hc_walk_blocks 4-byte aligned;
- *     u64 arrays 8-byte aligned.
+ *   - Alignment: d_in of hc_histogram / hc_encode_blocks / hc_decode_blocks
+ *     and d_out of hc_encode_blocks / hc_decode_blocks must be 16-byte
+ *     aligned; the stream of hc_walk_blocks 4-byte aligned; u64 arrays
+ *     8-byte aligned.
  *   - Limits: 16 <= B <= 2^26 and B % 16 == 0; sub-block stride S is 0 (no
  *     sub-block index) or a multiple of 16.
  */
@@ -195,7 +195,7 @@ hc_status hc_walk_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t nb, ui
 
 /* ---------------------------------------------------------------------- */
 /* Parallel block decoding (section 2.1, section 3.2).                    */
-/*   d_in, in_bytes  the stream (4-byte aligned).                          */
+/*   d_in, in_bytes  the stream (16-byte aligned, in_bytes % 4 == 0).      */
 /*   n, block_size   symbol count and B used to encode.                    */
 /*   cb              the encoding's codebook.                              */
 /*   d_block_off     nb + 1 u64 offsets (from hc_encode_blocks or          */

@@ -164,7 +164,7 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
         if (ws_bytes < encode_ws_bytes(g)) return HC_ERR_NO_SPACE;
         if (g.nb * g.tpb > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;  // grid limit
     }
-    const EncodeWs ws = n > 0 ? carve_encode_ws(d_ws, g) : EncodeWs{nullptr, nullptr, nullptr, nullptr};
+    const EncodeWs ws = n > 0 ? carve_encode_ws(d_ws, g) : EncodeWs{nullptr, nullptr, nullptr};
     return hip_status(launch_encode(d_in, g, cb->d_tables, cb->host.max_len, d_out, d_block_off, d_sub_idx,
                                     sub_block, ws, d_err, static_cast<hipStream_t>(stream)));
 }
@@ -184,13 +184,14 @@ extern "C" hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, ui
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block) || !cb) return HC_ERR_INVALID_ARG;
     if ((d_sub_idx == nullptr) != (sub_block == 0)) return HC_ERR_INVALID_ARG;
     if (n == 0) return HC_OK;
-    if (!d_in || !aligned(d_in, 4) || !d_block_off || !aligned(d_block_off, 8) || !d_out ||
+    if (!d_in || !aligned(d_in, 16) || !d_block_off || !aligned(d_block_off, 8) || !d_out ||
         !aligned(d_out, 16) || (d_sub_idx && !aligned(d_sub_idx, 4)))
         return HC_ERR_INVALID_ARG;
     if (cb->host.max_len == 0) return HC_ERR_INVALID_ARG;
     const uint64_t nb = (n + block_size - 1) / block_size;
     const uint64_t lanes = nb * (d_sub_idx ? (block_size + sub_block - 1) / sub_block : 1);
     if ((lanes + kDecThreads - 1) / kDecThreads > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
-    return hip_status(launch_decode(d_in, in_bytes, n, block_size, cb->d_tables, d_block_off, d_sub_idx,
-                                    sub_block, d_out, d_err, static_cast<hipStream_t>(stream)));
+    if (in_bytes & 3) return HC_ERR_INVALID_ARG;
+    return hip_status(launch_decode(d_in, in_bytes, n, block_size, cb->d_tables, cb->host.max_len, d_block_off,
+                                    d_sub_idx, sub_block, d_out, d_err, static_cast<hipStream_t>(stream)));
 }

@@ -16,10 +16,6 @@ constexpr int kTileThreads = 256;      // encode work-group size (4 waves)
 constexpr int kSymPerThread = 16;      // one 16-byte load per thread
 constexpr uint32_t kTileSyms = kTileThreads * kSymPerThread;  // 4096 symbols per tile
 
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanChunk = kScanThreads * kScanItems;
-
 constexpr int kDecThreads = 256;
 
 struct TileGeom {
@@ -40,10 +36,9 @@ inline TileGeom make_geom(uint64_t n, uint32_t B)
 }
 
 struct EncodeWs {
-    uint32_t *tile_bits;
-    uint32_t *tile_pos;
-    uint32_t *block_bits;
-    uint64_t *partial;
+    uint64_t *counter;  // tile counter (low 32 bits used)
+    uint64_t *tstate;   // look-back state per tile
+    uint64_t *bstate;   // look-back state per block
 };
 
 // Bytes of encode workspace and its carving into arrays.
@@ -57,7 +52,7 @@ hipError_t launch_encode(const uint8_t *in, const TileGeom &g, const DevTables *
 hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64_t *block_off,
                        uint32_t *err, hipStream_t s);
 hipError_t launch_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
-                         const uint64_t *block_off, const uint32_t *sub_idx, uint32_t S, uint8_t *out,
-                         uint32_t *err, hipStream_t s);
+                         uint32_t max_len, const uint64_t *block_off, const uint32_t *sub_idx, uint32_t S,
+                         uint8_t *out, uint32_t *err, hipStream_t s);
 
 }  // namespace hc

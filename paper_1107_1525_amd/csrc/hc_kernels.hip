@@ -2,13 +2,12 @@
 //
 //   k_hist         symbol counts (paper section 2) with LDS-privatised
 //                  sub-histograms, one replica per lane of a wavefront
-//   k_tile_bits    length pass (section 2.1): payload bits of each tile of
-//                  4096 symbols (a tile never crosses a block boundary)
-//   k_block_sums   per block: tile bit prefixes, block bit count, block bytes
-//   k_scan_*       exclusive scan of block bytes -> block offsets (section 2.1)
-//   k_pack         bit packing (section 2.1, Fig. 3-4): each tile's code words
-//                  are OR-ed into LDS words at their final bit alignment and
-//                  stored, coalesced, at the block's offset in the stream
+//   k_encode       one pass per tile of 4096 symbols (a tile never crosses a
+//                  block boundary): length pass (section 2.1), the block-offset
+//                  scan by decoupled look-back (section 2.1: "where the block
+//                  starts and ends"), and bit packing (section 2.1, Fig. 3-4):
+//                  code words OR-ed into LDS words, stored coalesced at the
+//                  block's offset in the stream with the header and zero pad
 //   k_walk         offset table rebuilt from the length delimiters
 //   k_decode       table decode (sections 2.1 and 3.2): one lane per block, or
 //                  per chunk of S symbols when a sub-block index is given
@@ -181,132 +180,6 @@ __device__ __forceinline__ uint32_t sym_at(const uint32_t w[4], uint32_t k)
     return (w[k >> 2] >> (8 * (k & 3))) & 255u;
 }
 
-// Length pass: bits of every tile.
-__global__ __launch_bounds__(kTileThreads) void k_tile_bits(const uint8_t *__restrict__ in, TileGeom g,
-                                                            const DevTables *__restrict__ tb,
-                                                            uint32_t *__restrict__ tile_bits,
-                                                            uint32_t *err)
-{
-    __shared__ uint32_t slen[kNumSym];
-    __shared__ uint32_t sred[kTileThreads / 64];
-    slen[threadIdx.x] = tb->enc_len[threadIdx.x];
-    __syncthreads();
-
-    const uint64_t t = blockIdx.x;
-    const Tile tl = tile_of(g, t);
-    uint32_t w[4];
-    const uint32_t m = load16(in, tl, tl.ts + kSymPerThread * threadIdx.x, w);
-    uint32_t bits = 0;
-    bool absent = false;
-#pragma unroll
-    for (uint32_t k = 0; k < 16; ++k) {
-        if (k < m) {
-            const uint32_t L = slen[sym_at(w, k)];
-            absent |= (L == 0);
-            bits += L;
-        }
-    }
-    if (absent) report(err, HC_ERR_SYMBOL_ABSENT);
-    bits = wave_sum(bits);
-    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = bits;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-#pragma unroll
-        for (int k = 0; k < kTileThreads / 64; ++k) s += sred[k];
-        tile_bits[t] = s;
-    }
-}
-
-// Per block: bit position of each tile inside the block, the block's bit count
-// and its size in bytes (header + payload words), the latter into 'bytes'.
-__global__ void k_block_sums(TileGeom g, const uint32_t *__restrict__ tile_bits,
-                             uint32_t *__restrict__ tile_pos, uint32_t *__restrict__ block_bits,
-                             uint64_t *__restrict__ bytes, uint32_t *err)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.nb) return;
-    uint64_t s = 0;
-    for (uint32_t j = 0; j < g.tpb; ++j) {
-        tile_pos[i * g.tpb + j] = (uint32_t)s;
-        s += tile_bits[i * g.tpb + j];
-    }
-    if (s > 0xFFFFFFFFull) report(err, HC_ERR_BLOCK_OVERFLOW);
-    block_bits[i] = (uint32_t)s;
-    bytes[i] = 4 + 4 * ((s + 31) / 32);
-}
-
-// ---------------------------------------------------------------- scan
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint64_t *__restrict__ v,
-                                                              uint64_t count,
-                                                              uint64_t *__restrict__ partial)
-{
-    __shared__ uint64_t sred[kScanThreads / 64];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
-    uint64_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < count) s += v[base + k];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-#pragma unroll
-        for (int k = 0; k < kScanThreads / 64; ++k) t += sred[k];
-        partial[blockIdx.x] = t;
-    }
-}
-
-// One work-group: exclusive scan of the chunk sums, in place; total -> *total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t *__restrict__ partial,
-                                                                uint64_t nchunks,
-                                                                uint64_t *__restrict__ total)
-{
-    __shared__ uint64_t scratch[kScanThreads / 64];
-    uint64_t carry = 0;
-    for (uint64_t base = 0; base < nchunks; base += kScanChunk) {
-        const uint64_t b = base + (uint64_t)threadIdx.x * kScanItems;
-        uint64_t item[kScanItems];
-        uint64_t s = 0;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            item[k] = (b + k < nchunks) ? partial[b + k] : 0;
-            s += item[k];
-        }
-        uint64_t all;
-        uint64_t run = carry + group_exclusive_scan<uint64_t, kScanThreads>(s, scratch, &all);
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            if (b + k < nchunks) partial[b + k] = run;
-            run += item[k];
-        }
-        carry += all;
-    }
-    if (threadIdx.x == 0) *total = carry;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(uint64_t *__restrict__ v, uint64_t count,
-                                                            const uint64_t *__restrict__ partial)
-{
-    __shared__ uint64_t scratch[kScanThreads / 64];
-    const uint64_t b = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
-    uint64_t item[kScanItems];
-    uint64_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        item[k] = (b + k < count) ? v[b + k] : 0;
-        s += item[k];
-    }
-    uint64_t all;
-    uint64_t run = partial[blockIdx.x] + group_exclusive_scan<uint64_t, kScanThreads>(s, scratch, &all);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (b + k < count) v[b + k] = run;
-        run += item[k];
-    }
-}
-
 // ---------------------------------------------------------------- pack
 // Appends the low L bits of 'code' (L <= 32) to a thread's bit accumulator and
 // flushes every completed 32-bit word into LDS.
@@ -322,59 +195,109 @@ __device__ __forceinline__ void put_bits(uint64_t &acc, uint32_t &nacc, uint32_t
     }
 }
 
-template <bool kPacked>
-__global__ __launch_bounds__(kTileThreads) void k_pack(
-    const uint8_t *__restrict__ in, TileGeom g, const DevTables *__restrict__ tb,
-    const uint32_t *__restrict__ tile_bits, const uint32_t *__restrict__ tile_pos,
-    const uint32_t *__restrict__ block_bits, const uint64_t *__restrict__ block_off,
-    uint32_t *__restrict__ out32, uint32_t *__restrict__ sub_idx, uint32_t S, uint32_t cpb,
-    uint32_t lds_words)
+// ---------------------------------------------------------------- single-pass encode
+// One launch does the length pass, the offset scan and the packing.  Each
+// work-group takes the next tile in dispatch order (an atomic counter), packs
+// its code words into LDS at bit alignment 0, publishes its bit count, and
+// learns where its bits go through two decoupled look-backs:
+//   tile states  (per tile)  bits of the block before the tile,
+//   block states (per block) bytes of the stream before the block.
+// A state word holds a 2-bit flag and a 62-bit value: AGGREGATE = this
+// element's own total, PREFIX = the total through this element (from the
+// start of its segment).  The first tile of every block publishes PREFIX at
+// once, so every look-back ends.  The last tile of a block publishes the
+// block's size, then its offset.  Waves only wait for tiles taken earlier from
+// the counter, which are already running, so the launch always drains.
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStPrefix = 2ull << 62;
+constexpr uint64_t kStValue = (1ull << 62) - 1;
+
+__device__ __forceinline__ void st_publish(uint64_t *p, uint64_t flag, uint64_t v)
 {
-    extern __shared__ uint32_t words[];  // lds_words words: the tile's payload at its bit alignment
+    __hip_atomic_store(p, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t st_peek(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by all 64 lanes of one wave.  Returns the sum of the values of
+// elements [lo, idx) of a segment whose first element lo publishes PREFIX.
+__device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t lo)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    uint64_t acc = 0;
+    uint64_t end = idx;  // the window covers elements end-1-lane
+    for (;;) {
+        const bool inside = end >= lo + 1 + lane;
+        const uint64_t st = inside ? st_peek(&states[end - 1 - lane]) : kStPrefix;
+        const uint64_t flag = st >> 62;
+        const uint64_t prefix_mask = __ballot(flag == 2);
+        const uint64_t missing_mask = __ballot(flag == 0);
+        if (prefix_mask) {
+            const uint32_t first = (uint32_t)__ffsll((unsigned long long)prefix_mask) - 1;
+            const uint64_t before = first ? ((1ull << first) - 1) : 0ull;
+            if (missing_mask & before) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            return acc + wave_sum(lane <= first ? (st & kStValue) : 0ull);
+        }
+        if (missing_mask) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        acc += wave_sum(st & kStValue);
+        end -= 64;
+    }
+}
+
+template <bool kPacked>
+__global__ __launch_bounds__(kTileThreads) void k_encode(
+    const uint8_t *__restrict__ in, TileGeom g, const DevTables *__restrict__ tb, uint64_t *tstate,
+    uint64_t *bstate, uint32_t *counter, uint32_t *__restrict__ out32, uint64_t *__restrict__ block_off,
+    uint32_t *__restrict__ sub_idx, uint32_t S, uint32_t cpb, uint32_t lds_words, uint32_t *err)
+{
+    extern __shared__ uint32_t words[];  // the tile's code bits from bit 0, MSB first
     __shared__ uint32_t s_packed[kNumSym];
     __shared__ uint64_t s_code[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_len[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_scan[kTileThreads / 64];
-    __shared__ uint32_t s_next[32];
-    __shared__ uint32_t s_fill;
+    __shared__ uint32_t s_tile, s_lead, s_bits;
+    __shared__ uint64_t s_P, s_O;
 
-    const uint64_t t = blockIdx.x;
-    const Tile tl = tile_of(g, t);
-    if (tl.ts >= tl.te) return;  // empty tile (uniform over the group)
     const uint32_t tid = threadIdx.x;
-
+    if (tid == 0) s_tile = atomicAdd(counter, 1u);
     if (kPacked) {
         s_packed[tid] = tb->enc_packed[tid];
     } else {
         s_code[tid] = tb->enc_code[tid];
         s_len[tid] = tb->enc_len[tid];
     }
-    const bool last_tile = tl.te == tl.cnt;
-    if (tid < 32) {  // the symbols just past the tile, for the word it shares with the next tile
-        const uint32_t k = tl.te + tid;
-        s_next[tid] = (!last_tile && k < tl.cnt) ? in[tl.blk_start + k] : 0u;
-    }
     for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
+    __syncthreads();
+
+    const uint64_t t = s_tile;
+    const Tile tl = tile_of(g, t);
+    if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
+    const bool last_tile = tl.te == tl.cnt;
 
     const uint32_t s = tl.ts + kSymPerThread * tid;
     uint32_t w[4];
     const uint32_t m = load16(in, tl, s, w);
-    __syncthreads();
-
     uint32_t bits = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < 16; ++k) {
+    for (uint32_t k = 0; k < 16; ++k)
         if (k < m) bits += kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
-    }
     uint32_t tile_total;
     const uint32_t q = group_exclusive_scan<uint32_t, kTileThreads>(bits, s_scan, &tile_total);
 
-    const uint32_t P = tile_pos[t];  // bit position of the tile inside the block's payload
-    const uint32_t a = P & 31u;
-    {
-        const uint32_t start = a + q;
-        uint32_t widx = start >> 5;
-        uint32_t nacc = start & 31u;  // leading zero bits keep the word aligned
+    if (tid == 0) st_publish(&tstate[t], tl.j == 0 ? kStPrefix : kStAgg, tile_total);
+
+    {  // pack at alignment 0
+        uint32_t widx = q >> 5;
+        uint32_t nacc = q & 31u;
         uint64_t acc = 0;
 #pragma unroll
         for (uint32_t k = 0; k < 16; ++k) {
@@ -398,23 +321,16 @@ __global__ __launch_bounds__(kTileThreads) void k_pack(
         if (nacc) atomicOr(&words[widx], (uint32_t)(acc << (32 - nacc)));
     }
 
-    // Word ownership: a stream word is written by the tile that holds its first
-    // bit.  If the tile's last word continues into the next tile of the block,
-    // this tile completes it from the first symbols of that tile (which then
-    // skips the word); at the end of a block the remaining bits are zero pad.
-    const uint32_t e_bits = a + tile_total;     // end of the tile, in LDS bits
-    const uint32_t k_first = (a == 0) ? 0u : 1u;
-    // tile_total is 0 only if a symbol had no code (already reported): store nothing
-    const uint32_t k_last = tile_total ? (e_bits - 1) >> 5 : 0u;
-    const uint32_t k_end = tile_total ? k_last + 1 : 0u;
-    if (tid == 0) {
-        uint64_t fill = 0;
-        if (!last_tile && (e_bits & 31u)) {
-            const uint32_t need = 32 - (e_bits & 31u);
+    if (tid == 64) {
+        // The first 32 bits of the next tile of the block (zero past the block's
+        // end): they complete this tile's last stream word.
+        uint64_t lead = 0;
+        uint32_t got = 0;
+        if (!last_tile) {
             const uint32_t avail = tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32;
-            uint32_t got = 0;
-            for (uint32_t k = 0; k < avail && got < need; ++k) {
-                const uint32_t v = s_next[k];
+            const uint8_t *src = in + tl.blk_start + tl.te;
+            for (uint32_t k = 0; k < avail && got < 32; ++k) {
+                const uint32_t v = src[k];
                 uint32_t L;
                 uint64_t c;
                 if (kPacked) {
@@ -424,36 +340,70 @@ __global__ __launch_bounds__(kTileThreads) void k_pack(
                     L = s_len[v];
                     c = s_code[v];
                 }
-                const uint32_t r = need - got;
+                const uint32_t r = 32 - got;
                 if (L >= r) {
-                    fill = (fill << r) | (c >> (L - r));
-                    got = need;
+                    lead = (lead << r) | (c >> (L - r));
+                    got = 32;
                 } else {
-                    fill = (fill << L) | c;
+                    lead = (lead << L) | c;
                     got += L;
                 }
             }
-            fill <<= (need - got);
         }
-        s_fill = (uint32_t)fill;
+        s_lead = (uint32_t)(lead << (32 - got));
     }
-    __syncthreads();  // all code words are in LDS, s_fill is set
 
-    const uint64_t off = block_off[tl.blk];
-    uint32_t *payload = out32 + (off >> 2) + 1 + (P >> 5);
-    for (uint32_t k = k_first + tid; k < k_end; k += kTileThreads)
-        payload[k] = (k == k_last) ? (words[k] | s_fill) : words[k];
-
-    if (tl.j == 0 && tid == 0) out32[off >> 2] = block_bits[tl.blk];
-    if (sub_idx) {
-        if (m > 0 && (s % S) == 0) sub_idx[tl.blk * cpb + s / S] = P + q;
-        if (last_tile && tid == 0) {
-            const uint32_t bb = block_bits[tl.blk];
-            for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = bb;
+    if (tid < 64) {
+        uint64_t P = 0;
+        if (tl.j > 0) {
+            P = wave_lookback(tstate, t, t - tl.j);
+            if (tid == 0) st_publish(&tstate[t], kStPrefix, P + tile_total);
         }
+        const uint64_t blk_bits = P + tile_total;
+        const uint64_t blk_bytes = 4 + 4 * ((blk_bits + 31) / 32);
+        if (last_tile && tid == 0) {
+            if (blk_bits > 0xFFFFFFFFull) report(err, HC_ERR_BLOCK_OVERFLOW);
+            st_publish(&bstate[tl.blk], tl.blk == 0 ? kStPrefix : kStAgg, blk_bytes);
+        }
+        uint64_t O = 0;
+        if (tl.blk > 0) {
+            O = wave_lookback(bstate, tl.blk, 0);
+            if (last_tile && tid == 0) st_publish(&bstate[tl.blk], kStPrefix, O + blk_bytes);
+        }
+        if (tid == 0) {
+            s_P = P;
+            s_O = O;
+            s_bits = (uint32_t)blk_bits;
+            if (last_tile) {
+                block_off[tl.blk] = O;
+                if (tl.blk + 1 == g.nb) block_off[g.nb] = O + blk_bytes;
+            }
+        }
+    }
+    __syncthreads();
+
+    const uint64_t P = s_P, O = s_O;
+    const uint32_t a = (uint32_t)(P & 31);
+    uint32_t *payload = out32 + (O >> 2) + 1 + (P >> 5);
+    if (tile_total) {
+        // stream word k of the tile holds tile bits [32k - a, 32k - a + 32); it is
+        // written here if its first bit is this tile's (k >= 1 when a > 0)
+        const uint32_t e_bits = a + tile_total;
+        const uint32_t k_last = (e_bits - 1) >> 5;
+        const uint32_t fill = (!last_tile && (e_bits & 31u)) ? (s_lead >> (e_bits & 31u)) : 0u;
+        for (uint32_t k = (a ? 1u : 0u) + tid; k <= k_last; k += kTileThreads) {
+            uint32_t v = a ? ((words[k - 1] << (32 - a)) | (words[k] >> a)) : words[k];
+            if (k == k_last) v |= fill;
+            payload[k] = v;
+        }
+    }
+    if (last_tile && tid == 0) out32[O >> 2] = s_bits;
+    if (sub_idx) {
+        if (m > 0 && (s % S) == 0) sub_idx[tl.blk * cpb + s / S] = (uint32_t)P + q;
+        if (last_tile && tid == 0)
+            for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = s_bits;
     }
 }
-
 
 // ---------------------------------------------------------------- walk
 // The offset table from the length delimiters: each header gives the size of
@@ -641,28 +591,210 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
     }
 }
 
+// ---------------------------------------------------------------- decode, codes of <= 24 bits
+// Same lane mapping and checks as k_decode, but the lane's payload words reach
+// its bit buffer through a private ring of 32 words in LDS (two halves of 16).
+// The ring is filled with 16-byte loads; the half after the ring is loaded into
+// registers one round ahead and written into the ring when the lane has moved
+// past a half, so no symbol waits on a global load.  A round decodes R symbols
+// (R * max_len <= 15 words), the ring always holds what a round can consume.
+constexpr uint32_t kRingHalf = 16;
+constexpr uint32_t kRingWords = 2 * kRingHalf;
+constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
+
+__device__ __forceinline__ uint4 load_quad(const uint32_t *__restrict__ in32, uint64_t q, uint64_t in_words)
+{
+    const uint64_t w = q * 4;
+    if (w + 4 <= in_words) return *reinterpret_cast<const uint4 *>(in32 + w);
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    if (w + 0 < in_words) r.x = in32[w + 0];
+    if (w + 1 < in_words) r.y = in32[w + 1];
+    if (w + 2 < in_words) r.z = in32[w + 2];
+    return r;
+}
+
+template <uint32_t R>
+__global__ __launch_bounds__(kDecThreads) void k_decode_ring(
+    const uint32_t *__restrict__ in32, uint64_t in_bytes, uint64_t n, uint32_t B, uint64_t nb,
+    const DevTables *__restrict__ tb, const uint64_t *__restrict__ off,
+    const uint32_t *__restrict__ sub_idx, uint32_t S_eff, uint32_t cpb, uint8_t *__restrict__ out,
+    uint32_t *err)
+{
+    __shared__ uint16_t s_lut[1 << kLutBits];
+    __shared__ uint32_t s_ring[kDecThreads * kRingStride];
+    __shared__ uint32_t s_first[kPackedMaxLen + 1];
+    __shared__ uint32_t s_count[kPackedMaxLen + 1];
+    __shared__ uint32_t s_base[kPackedMaxLen + 1];
+    __shared__ uint32_t s_sorted[kNumSym];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t K = tb->lut_bits;
+    const uint32_t max_len = tb->max_len;
+    for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
+    if (tid <= (uint32_t)kPackedMaxLen) {
+        s_first[tid] = (uint32_t)tb->first[tid];
+        s_count[tid] = tb->count[tid];
+        s_base[tid] = tb->base[tid];
+    }
+    s_sorted[tid] = tb->sorted[tid];
+    __syncthreads();  // the last barrier: lanes may leave early from here on
+
+    const uint64_t g = (uint64_t)blockIdx.x * kDecThreads + tid;
+    const uint64_t i = g / cpb;
+    const uint32_t c = (uint32_t)(g - i * cpb);
+    if (i >= nb) return;
+    const uint64_t blk_start = i * (uint64_t)B;
+    const uint64_t left = n - blk_start;
+    const uint32_t cnt = (uint32_t)(left < B ? left : B);
+    const uint32_t s0 = c * S_eff;
+    if (s0 >= cnt) return;
+    const uint32_t s1 = (cnt - s0 < S_eff) ? cnt : s0 + S_eff;
+
+    const uint64_t o = off[i], o1 = off[i + 1];
+    if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
+        report(err, HC_ERR_CORRUPT);
+        return;
+    }
+    if (c == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
+    const uint32_t hdr = in32[o >> 2];
+    if (o + 4 + 4 * (((uint64_t)hdr + 31) / 32) != o1) {
+        report(err, HC_ERR_CORRUPT);
+        return;
+    }
+    const uint32_t nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
+    uint64_t p0 = 0, p1 = hdr;
+    if (sub_idx) {
+        p0 = sub_idx[i * cpb + c];
+        if (s1 < cnt) p1 = sub_idx[i * cpb + c + 1];
+    }
+    if (p0 > p1 || p1 > hdr) {
+        report(err, HC_ERR_CORRUPT);
+        return;
+    }
+
+    // ring: stream words [kRingHalf*h, kRingHalf*h + kRingWords) at slot (word mod kRingWords)
+    const uint64_t in_words = in_bytes >> 2;
+    const uint64_t pw0 = (o >> 2) + 1;  // stream word of payload bit 0
+    uint32_t *ring = s_ring + tid * kRingStride;
+    const uint64_t sw = pw0 + (p0 >> 5);
+    uint64_t h = sw / kRingHalf;
+    constexpr uint32_t kQuadsPerHalf = kRingHalf / 4;
+#pragma unroll
+    for (uint32_t j = 0; j < 2 * kQuadsPerHalf; ++j) {
+        const uint4 v = load_quad(in32, h * kQuadsPerHalf + j, in_words);
+        const uint32_t base = (uint32_t)((h * kRingHalf + 4 * j) & (kRingWords - 1));
+        ring[base + 0] = v.x;
+        ring[base + 1] = v.y;
+        ring[base + 2] = v.z;
+        ring[base + 3] = v.w;
+    }
+    uint4 f[kQuadsPerHalf];  // in flight: stream words of half h + 2
+#pragma unroll
+    for (uint32_t j = 0; j < kQuadsPerHalf; ++j) f[j] = load_quad(in32, (h + 2) * kQuadsPerHalf + j, in_words);
+
+    const uint32_t r = (uint32_t)(p0 & 31);
+    uint64_t buf = (((uint64_t)ring[sw & (kRingWords - 1)] << 32) | ring[(sw + 1) & (kRingWords - 1)]) << r;
+    uint32_t nbits = 64 - r;
+    uint64_t nxt = sw + 2;  // next stream word to enter the bit buffer
+    uint32_t pre = ring[nxt & (kRingWords - 1)];
+
+    bool bad = false;
+    uint8_t *dst = out + blk_start + s0;
+    const uint32_t nsym = s1 - s0;
+    for (uint32_t k = 0; k < nsym; k += R) {
+        if (nxt >= kRingHalf * h + kRingHalf) {
+            // the lane has left half h: its slots receive half h + 2
+#pragma unroll
+            for (uint32_t j = 0; j < kQuadsPerHalf; ++j) {
+                const uint32_t base = (uint32_t)(((h + 2) * kRingHalf + 4 * j) & (kRingWords - 1));
+                ring[base + 0] = f[j].x;
+                ring[base + 1] = f[j].y;
+                ring[base + 2] = f[j].z;
+                ring[base + 3] = f[j].w;
+            }
+            h += 1;
+#pragma unroll
+            for (uint32_t j = 0; j < kQuadsPerHalf; ++j)
+                f[j] = load_quad(in32, (h + 2) * kQuadsPerHalf + j, in_words);
+        }
+        uint32_t o4[R / 4];
+#pragma unroll
+        for (uint32_t q = 0; q < R / 4; ++q) o4[q] = 0;
+        const uint32_t m = (nsym - k < R) ? nsym - k : R;
+#pragma unroll
+        for (uint32_t q = 0; q < R; ++q) {
+            if (q < m) {
+                const uint32_t e = s_lut[buf >> (64 - K)];
+                uint32_t L = e >> 8;
+                uint32_t sym = e & 255u;
+                if (L == 0 || e == kLutInvalid) {
+                    // longer than the table: canonical ranges on the (>= 32) buffered bits
+                    L = 0;
+                    if (e != kLutInvalid) {
+                        for (uint32_t l = K + 1; l <= max_len; ++l) {
+                            const uint32_t cv = (uint32_t)(buf >> (64 - l));
+                            const uint32_t d = cv - s_first[l];
+                            if (d < s_count[l]) {
+                                L = l;
+                                sym = s_sorted[s_base[l] + d];
+                                break;
+                            }
+                        }
+                    }
+                    if (L == 0) {
+                        bad = true;
+                        L = 1;
+                        sym = 0;
+                    }
+                }
+                buf <<= L;
+                nbits -= L;
+                if (nbits < 32) {
+                    buf |= (uint64_t)pre << (32 - nbits);
+                    nbits += 32;
+                    nxt += 1;
+                    pre = ring[nxt & (kRingWords - 1)];
+                }
+                o4[q >> 2] |= sym << (8 * (q & 3));
+            }
+        }
+        if (m == R) {
+#pragma unroll
+            for (uint32_t q = 0; q < R / 16; ++q)
+                *reinterpret_cast<uint4 *>(dst + k + 16 * q) =
+                    make_uint4(o4[4 * q], o4[4 * q + 1], o4[4 * q + 2], o4[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (uint32_t q = 0; q < R; ++q)
+                if (q < m) dst[k + q] = (uint8_t)(o4[q >> 2] >> (8 * (q & 3)));
+        }
+    }
+    const uint64_t pos = 32 * (nxt - pw0) - nbits;
+    if (bad || pos != p1) {
+        report(err, HC_ERR_CORRUPT);
+        return;
+    }
+    if (s1 == cnt && (hdr & 31u)) {
+        const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
+        if (in32[pw0 + nwords - 1] & mask) report(err, HC_ERR_CORRUPT);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 static inline uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
 
 uint64_t encode_ws_bytes(const TileGeom &g)
 {
     const uint64_t ntiles = g.nb * g.tpb;
-    const uint64_t nchunks = (g.nb + kScanChunk - 1) / kScanChunk;
-    return align16(4 * ntiles) * 2 + align16(4 * g.nb) + align16(8 * (nchunks ? nchunks : 1));
+    return 8 * (2 + ntiles + g.nb);
 }
 
 EncodeWs carve_encode_ws(void *ws, const TileGeom &g)
 {
-    const uint64_t ntiles = g.nb * g.tpb;
-    char *p = static_cast<char *>(ws);
     EncodeWs w;
-    w.tile_bits = reinterpret_cast<uint32_t *>(p);
-    p += align16(4 * ntiles);
-    w.tile_pos = reinterpret_cast<uint32_t *>(p);
-    p += align16(4 * ntiles);
-    w.block_bits = reinterpret_cast<uint32_t *>(p);
-    p += align16(4 * g.nb);
-    w.partial = reinterpret_cast<uint64_t *>(p);
+    w.counter = static_cast<uint64_t *>(ws);     // word 0: tile counter; word 1: spare
+    w.tstate = w.counter + 2;
+    w.bstate = w.tstate + g.nb * g.tpb;
     return w;
 }
 
@@ -689,24 +821,18 @@ hipError_t launch_encode(const uint8_t *in, const TileGeom &g, const DevTables *
         return hipGetLastError();
     }
     const uint64_t ntiles = g.nb * g.tpb;
-    const uint64_t nchunks = (g.nb + kScanChunk - 1) / kScanChunk;
-    k_tile_bits<<<dim3((uint32_t)ntiles), kTileThreads, 0, s>>>(in, g, tb, ws.tile_bits, err);
-    k_block_sums<<<dim3((uint32_t)((g.nb + 255) / 256)), 256, 0, s>>>(g, ws.tile_bits, ws.tile_pos,
-                                                                      ws.block_bits, block_off, err);
-    k_scan_reduce<<<dim3((uint32_t)nchunks), kScanThreads, 0, s>>>(block_off, g.nb, ws.partial);
-    k_scan_partials<<<1, kScanThreads, 0, s>>>(ws.partial, nchunks, block_off + g.nb);
-    k_scan_down<<<dim3((uint32_t)nchunks), kScanThreads, 0, s>>>(block_off, g.nb, ws.partial);
-    const uint32_t lds_words = (uint32_t)((31ull + (uint64_t)kTileSyms * max_len + 31ull) / 32ull + 1);
+    const uint64_t nstate = 2 + ntiles + g.nb;
+    k_fill_u64<<<dim3((uint32_t)((nstate + 255) / 256)), 256, 0, s>>>(ws.counter, nstate, 0);
+    const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * max_len + 31ull) / 32ull + 2);
     const uint32_t cpb = S ? (g.B + S - 1) / S : 1;
     uint32_t *out32 = reinterpret_cast<uint32_t *>(out);
+    uint32_t *counter = reinterpret_cast<uint32_t *>(ws.counter);
     if (max_len <= (uint32_t)kPackedMaxLen)
-        k_pack<true><<<dim3((uint32_t)ntiles), kTileThreads, lds_words * 4, s>>>(
-            in, g, tb, ws.tile_bits, ws.tile_pos, ws.block_bits, block_off, out32, sub_idx, S, cpb,
-            lds_words);
+        k_encode<true><<<dim3((uint32_t)ntiles), kTileThreads, lds_words * 4, s>>>(
+            in, g, tb, ws.tstate, ws.bstate, counter, out32, block_off, sub_idx, S, cpb, lds_words, err);
     else
-        k_pack<false><<<dim3((uint32_t)ntiles), kTileThreads, lds_words * 4, s>>>(
-            in, g, tb, ws.tile_bits, ws.tile_pos, ws.block_bits, block_off, out32, sub_idx, S, cpb,
-            lds_words);
+        k_encode<false><<<dim3((uint32_t)ntiles), kTileThreads, lds_words * 4, s>>>(
+            in, g, tb, ws.tstate, ws.bstate, counter, out32, block_off, sub_idx, S, cpb, lds_words, err);
     return hipGetLastError();
 }
 
@@ -718,8 +844,8 @@ hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64
 }
 
 hipError_t launch_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
-                         const uint64_t *block_off, const uint32_t *sub_idx, uint32_t S, uint8_t *out,
-                         uint32_t *err, hipStream_t s)
+                         uint32_t max_len, const uint64_t *block_off, const uint32_t *sub_idx, uint32_t S,
+                         uint8_t *out, uint32_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const uint64_t nb = (n + B - 1) / B;
@@ -727,9 +853,16 @@ hipError_t launch_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint3
     const uint32_t cpb = sub_idx ? (B + S - 1) / S : 1;
     const uint64_t lanes = nb * cpb;
     const uint64_t groups = (lanes + kDecThreads - 1) / kDecThreads;
-    k_decode<<<dim3((uint32_t)groups), kDecThreads, 0, s>>>(reinterpret_cast<const uint32_t *>(in),
-                                                           in_bytes, n, B, nb, tb, block_off, sub_idx,
-                                                           S_eff, cpb, out, err);
+    const uint32_t *in32 = reinterpret_cast<const uint32_t *>(in);
+    if (max_len <= 15)
+        k_decode_ring<32><<<dim3((uint32_t)groups), kDecThreads, 0, s>>>(in32, in_bytes, n, B, nb, tb, block_off,
+                                                                         sub_idx, S_eff, cpb, out, err);
+    else if (max_len <= (uint32_t)kPackedMaxLen)
+        k_decode_ring<16><<<dim3((uint32_t)groups), kDecThreads, 0, s>>>(in32, in_bytes, n, B, nb, tb, block_off,
+                                                                         sub_idx, S_eff, cpb, out, err);
+    else
+        k_decode<<<dim3((uint32_t)groups), kDecThreads, 0, s>>>(in32, in_bytes, n, B, nb, tb, block_off, sub_idx,
+                                                               S_eff, cpb, out, err);
     return hipGetLastError();
 }
 
