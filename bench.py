@@ -3,14 +3,14 @@
 One step = the whole coding path over the 4 GiB mixed workload (64 segments of
 64 MiB cycling uniform / skewed / fp32 bytes, one codebook per segment):
 
-  1. symbol counts of every segment                 (hc_histogram, GPU)
+  1. symbol counts of every segment            (hc_histogram_batch, one launch)
   2. read-back of the 64 histograms (16 KiB)
-  3. Huffman code + canonical codes per segment    (hc_build_codebook, host)
-     and refresh of the device tables              (hc_codebook_update, async)
-  4. block encode of every segment: length pass, offset scan, bit packing
-                                                    (hc_encode_blocks, GPU)
+  3. Huffman code + canonical codes per segment (hc_build_codebook, host)
+     and refresh of the device tables           (hc_codebook_update, async)
+  4. block encode of every segment: length pass, offset scan by look-back,
+     bit packing                                (hc_encode_batch, one launch)
   5. block decode of every segment from the encoder's offsets and sub-block
-     index                                          (hc_decode_blocks, GPU)
+     index                                      (hc_decode_batch, one launch)
 
 Inputs are resident in HBM before timing starts.  The JSON line reports the
 whole-step throughput in uncompressed GB/s, the per-phase rates, the roofline
@@ -63,7 +63,11 @@ def kernel_source_hash() -> str:
 
 
 class Workload:
-    """The 4 GiB mixed buffer and every device buffer one step needs."""
+    """The 4 GiB mixed buffer and every device buffer one step needs.
+
+    Each phase is one batched launch over all segments (hc_histogram_batch,
+    hc_encode_batch, hc_decode_batch); the segment table lives in hc_item
+    arrays built once."""
 
     def __init__(self, hc, synth, torch, nseg, B, S):
         self.hc, self.torch = hc, torch
@@ -73,16 +77,18 @@ class Workload:
         self.B, self.S = B, S
         dev = "cuda"
         self.x = torch.empty(self.n, dtype=torch.uint8, device=dev)
-        self.kinds = []
         for t in range(nseg):
-            kind = synth.mixed_kind(t)
-            self.kinds.append(kind)
-            synth.segment_bytes_torch(kind, self.seg, synth.derive_seed(3, t), out=self.x[t * self.seg:(t + 1) * self.seg])
+            synth.segment_bytes_torch(synth.mixed_kind(t), self.seg, synth.derive_seed(3, t),
+                                      out=self.x[t * self.seg:(t + 1) * self.seg])
         self.hist = torch.zeros((nseg, 256), dtype=torch.int64, device=dev)
         self.hist_host = torch.zeros((nseg, 256), dtype=torch.int64).pin_memory()
-        # codebooks of the data (fixed across steps) size the output buffers
+        self.hist_items = hc.make_items(nseg)
         for t in range(nseg):
-            hc.hc_histogram(self.xs(t), out=self.hist[t])
+            hc.set_item(self.hist_items, t, x=self.xs(t), hist=self.hist[t])
+        self.hist_ws = torch.empty(max(hc.hc_batch_workspace_bytes(self.hist_items, B), 256),
+                                   dtype=torch.uint8, device=dev)
+        # codebooks of the data (fixed across steps) size the output buffers
+        hc.hc_histogram_batch(self.hist_items, self.hist_ws)
         h = self.hist.cpu().numpy().view("uint64")
         cbs = [hc.hc_build_codebook(h[t]) for t in range(nseg)]
         self.dcb = [hc.DeviceCodebook(cb) for cb in cbs]
@@ -95,10 +101,19 @@ class Workload:
         self.off = torch.empty((nseg, self.nb + 1), dtype=torch.int64, device=dev)
         self.nsub = hc.hc_sub_index_entries(self.seg, B, S) if S else 0
         self.sub = torch.empty((nseg, max(self.nsub, 1)), dtype=torch.int32, device=dev) if S else None
-        self.ws = torch.empty(hc.hc_encode_workspace_bytes(self.seg, B), dtype=torch.uint8, device=dev)
         self.y = torch.empty(self.n, dtype=torch.uint8, device=dev)
         self.err = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.C = None
+        self.enc_items = hc.make_items(nseg)
+        for t in range(nseg):
+            hc.set_item(self.enc_items, t, x=self.xs(t), dcb=self.dcb[t], out=self.outs(t), block_off=self.off[t],
+                        sub_idx=self.subs(t))
+        self.ws = torch.empty(hc.hc_batch_workspace_bytes(self.enc_items, B), dtype=torch.uint8, device=dev)
+        hc.hc_encode_batch(self.enc_items, B, S, self.ws, self.err)
+        self.C = [int(v) for v in self.off[:, self.nb].cpu()]
+        self.dec_items = hc.make_items(nseg)
+        for t in range(nseg):
+            hc.set_item(self.dec_items, t, x=self.outs(t), n=self.seg, in_bytes=self.C[t], dcb=self.dcb[t],
+                        out=self.ys(t), block_off=self.off[t], sub_idx=self.subs(t))
 
     def xs(self, t):
         return self.x[t * self.seg:(t + 1) * self.seg]
@@ -113,51 +128,40 @@ class Workload:
         return self.sub[t] if self.S else None
 
     def step(self, ev=None):
-        """One pass of the whole path.  ev: optional dict of per-launch event lists."""
+        """One pass of the whole path.  ev: optional dict of (start, end) events per phase."""
         hc, torch = self.hc, self.torch
-        E = torch.cuda.Event
-        for t in range(self.nseg):
-            hc.hc_histogram(self.xs(t), out=self.hist[t])
+
+        def mark(k, i):
+            if ev is not None:
+                ev[k][i].record()
+
+        mark("hist", 0)
+        hc.hc_histogram_batch(self.hist_items, self.hist_ws)
+        mark("hist", 1)
         self.hist_host.copy_(self.hist, non_blocking=True)
         torch.cuda.current_stream().synchronize()
         h = self.hist_host.numpy().view("uint64")
         for t in range(self.nseg):
             self.dcb[t].update(hc.hc_build_codebook(h[t]))
-        for t in range(self.nseg):
-            if ev is not None:
-                ev["enc"][t][0].record()
-            hc.hc_encode_blocks(self.xs(t), self.B, self.dcb[t], self.outs(t), self.off[t], self.subs(t), self.S,
-                                self.ws, self.err)
-            if ev is not None:
-                ev["enc"][t][1].record()
-        if self.C is None:
-            self.C = [int(v) for v in self.off[:, self.nb].cpu()]
-        for t in range(self.nseg):
-            if ev is not None:
-                ev["dec"][t][0].record()
-            hc.hc_decode_blocks(self.outs(t), self.C[t], self.seg, self.B, self.dcb[t], self.off[t], self.subs(t),
-                                self.S, self.ys(t), self.err)
-            if ev is not None:
-                ev["dec"][t][1].record()
+        mark("enc", 0)
+        hc.hc_encode_batch(self.enc_items, self.B, self.S, self.ws, self.err)
+        mark("enc", 1)
+        mark("dec", 0)
+        hc.hc_decode_batch(self.dec_items, self.B, self.S, self.ws, self.err)
+        mark("dec", 1)
 
 
-def time_phases(w, torch, reps=3):
-    """Per-phase GPU times (ms per step) from HIP events around each launch."""
+def time_phases(w, torch, reps=5):
+    """GPU time (ms) of each phase's launch, from HIP events recorded on the
+    stream the library launches on (torch's current stream)."""
     E = torch.cuda.Event
     res = {"hist": [], "enc": [], "dec": []}
-    hc = w.hc
     for _ in range(reps):
-        e_h = [(E(enable_timing=True), E(enable_timing=True)) for _ in range(w.nseg)]
-        for t in range(w.nseg):
-            e_h[t][0].record()
-            hc.hc_histogram(w.xs(t), out=w.hist[t])
-            e_h[t][1].record()
-        ev = {k: [(E(enable_timing=True), E(enable_timing=True)) for _ in range(w.nseg)] for k in ("enc", "dec")}
+        ev = {k: (E(enable_timing=True), E(enable_timing=True)) for k in res}
         w.step(ev)
         torch.cuda.synchronize()
-        res["hist"].append([a.elapsed_time(b) for a, b in e_h])
-        res["enc"].append([a.elapsed_time(b) for a, b in ev["enc"]])
-        res["dec"].append([a.elapsed_time(b) for a, b in ev["dec"]])
+        for k in res:
+            res[k].append(ev[k][0].elapsed_time(ev[k][1]))
     return res
 
 
@@ -265,17 +269,14 @@ def main():
         ms_step = wall * 1e3 / args.steps
         ph = time_phases(w, torch)
         med = lambda v: float(np.median(v))
-        hist_ms = med([sum(r) for r in ph["hist"]])
-        enc_ms = med([sum(r) for r in ph["enc"]])
-        dec_ms = med([sum(r) for r in ph["dec"]])
-        enc_launch_ms = med([m for r in ph["enc"] for m in r])
-        dec_launch_ms = med([m for r in ph["dec"] for m in r])
+        hist_ms, enc_ms, dec_ms = med(ph["hist"]), med(ph["enc"]), med(ph["dec"])
         n = w.n
         C = sum(w.C)
         off_bytes = 8 * (w.nb + 1) * w.nseg
         sub_bytes = 4 * w.nsub * w.nseg
         gb = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
-        # algorithmic bytes: what each step must move, not what it happens to move
+        # algorithmic bytes: what each phase must move, not what it happens to move
+        hist_alg = n + 8 * 256 * w.nseg
         enc_alg = n + C + off_bytes + sub_bytes
         dec_alg = C + n + off_bytes + sub_bytes
         phases = {
@@ -284,17 +285,14 @@ def main():
             "decode_GBps": round(gb(n, dec_ms), 1),
             "compress_GBps": round(gb(n, hist_ms + enc_ms), 1),
             "hist_ms": round(hist_ms, 3), "encode_ms": round(enc_ms, 3), "decode_ms": round(dec_ms, 3),
+            "hist_pct_hbm": round(100 * gb(hist_alg, hist_ms) / HBM_PEAK_GBPS, 1),
             "encode_pct_hbm": round(100 * gb(enc_alg, enc_ms) / HBM_PEAK_GBPS, 1),
             "decode_pct_hbm": round(100 * gb(dec_alg, dec_ms) / HBM_PEAK_GBPS, 1),
             "ratio": round(C / n, 5),
         }
-        dominant = "k_decode" if dec_ms >= enc_ms else "hc_encode_blocks"
-        if dominant == "k_decode":
-            per_launch = dec_alg / w.nseg
-            launch_ms = dec_launch_ms
-        else:
-            per_launch = enc_alg / w.nseg
-            launch_ms = enc_launch_ms
+        cands = {"k_decode_ring": (dec_ms, dec_alg), "k_encode": (enc_ms, enc_alg), "k_hist": (hist_ms, hist_alg)}
+        dominant = max(cands, key=lambda k: cands[k][0])
+        launch_ms, per_launch = cands[dominant]
         achieved = per_launch / (launch_ms * 1e-3) / 1e9
         roofline = {
             "bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,

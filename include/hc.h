@@ -215,6 +215,51 @@ hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t n, u
                            hc_cb_handle cb, const uint64_t *d_block_off, const uint32_t *d_sub_idx,
                            uint32_t sub_block, uint8_t *d_out, uint32_t *d_err, void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* Batches: many independent buffers, each with its own codebook, in one  */
+/* launch per step (the blocks of all buffers are independent units of    */
+/* work, section 2.1: "concurrent compression and decompression on        */
+/* multiple processors").  Every buffer follows the contract of the       */
+/* single-buffer call; B and S are common to the batch.                   */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    const uint8_t *in;    /* histogram / encode: the n bytes (16-byte aligned); decode: the stream */
+    uint64_t n;           /* symbols (uncompressed bytes) */
+    uint64_t in_bytes;    /* decode: stream bytes C (multiple of 4); ignored otherwise */
+    hc_cb_handle cb;      /* encode / decode: this buffer's codebook */
+    uint8_t *out;         /* encode: stream buffer; decode: n output bytes (16-byte aligned) */
+    uint64_t out_cap;     /* encode: bytes at out, at least hc_encode_bound(n, B, max_len) */
+    uint64_t *block_off;  /* encode: nb + 1 offsets written; decode: read */
+    uint32_t *sub_idx;    /* sub-block index (written by encode, read by decode) when S > 0, else NULL */
+    uint64_t *hist;       /* histogram: 256 u64 written */
+} hc_item;
+
+/* Device workspace (256-byte aligned, caller-owned) any of the three batch */
+/* calls needs for these items and block size: the job table copied from  */
+/* the host, then the encoder's look-back states.                          */
+uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size);
+
+/* hc_histogram for every item (uses in, n, hist).  The item table is       */
+/* copied into d_ws with an asynchronous host-to-device copy on 'stream';  */
+/* 'items' may be reused when the call returns.                            */
+/* Errors returned: INVALID_ARG, NO_SPACE, HIP.                            */
+hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* hc_encode_blocks for every item (uses in, n, cb, out, out_cap,          */
+/* block_off, sub_idx) with block size B and sub-block stride S.  One      */
+/* launch: tiles of all items are packed by the same kernel; each item's   */
+/* offsets start at 0 in its own stream.                                   */
+/* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: SYMBOL_ABSENT,   */
+/* BLOCK_OVERFLOW.                                                          */
+hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                          void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
+
+/* hc_decode_blocks for every item (uses in, in_bytes, n, cb, block_off,   */
+/* sub_idx, out).  One launch.                                             */
+/* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: CORRUPT.         */
+hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                          void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,8 @@ names of the C ABI in ``include/hc.h``:
     hc_histogram, hc_build_codebook, hc_codebook_from_lengths,
     hc_codebook_upload, hc_codebook_update, hc_codebook_destroy, hc_encode_bound,
     hc_encode_workspace_bytes, hc_sub_index_entries, hc_encode_blocks,
-    hc_walk_blocks, hc_decode_blocks, hc_status_str
+    hc_walk_blocks, hc_decode_blocks, hc_status_str, hc_batch_workspace_bytes,
+    hc_histogram_batch, hc_encode_batch, hc_decode_batch
 
 and add two conveniences, ``compress`` and ``decompress``, that chain them.
 u64 device buffers are held in int64 tensors and u32 ones in int32 tensors
@@ -60,6 +61,21 @@ class hc_codebook(ctypes.Structure):
         return np.ctypeslib.as_array(self.code).astype(np.uint64).copy()
 
 
+class hc_item(ctypes.Structure):
+    """One buffer of a batch call (see hc_item in include/hc.h)."""
+    _fields_ = [
+        ("in_", ctypes.c_void_p),
+        ("n", ctypes.c_uint64),
+        ("in_bytes", ctypes.c_uint64),
+        ("cb", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("out_cap", ctypes.c_uint64),
+        ("block_off", ctypes.c_void_p),
+        ("sub_idx", ctypes.c_void_p),
+        ("hist", ctypes.c_void_p),
+    ]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build it with `python paper_1107_1525_amd/build.py` "
@@ -86,6 +102,10 @@ _sigs = {
     "hc_encode_blocks": ([_vp, _u64, _u32, _vp, _vp, _u64, _vp, _vp, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_walk_blocks": ([_vp, _u64, _u64, _vp, _vp, _vp], _st),
     "hc_decode_blocks": ([_vp, _u64, _u64, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp], _st),
+    "hc_batch_workspace_bytes": ([ctypes.POINTER(hc_item), _u32, _u32], _u64),
+    "hc_histogram_batch": ([ctypes.POINTER(hc_item), _u32, _vp, _u64, _vp], _st),
+    "hc_encode_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
+    "hc_decode_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
 }
 for _name, (_args, _res) in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -296,3 +316,49 @@ def decompress(enc: Encoded, out: Optional[torch.Tensor] = None, use_offsets: bo
         if e:
             raise HcError(e, "hc_decode_blocks (device)")
     return out
+
+
+# ------------------------------------------------------------------ batches
+def make_items(count: int):
+    """A zeroed hc_item array of the given length, to fill field by field."""
+    return (hc_item * count)()
+
+
+def _item_ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def set_item(items, k: int, x: Optional[torch.Tensor] = None, n: Optional[int] = None, in_bytes: int = 0,
+             dcb: Optional[DeviceCodebook] = None, out: Optional[torch.Tensor] = None,
+             block_off: Optional[torch.Tensor] = None, sub_idx: Optional[torch.Tensor] = None,
+             hist: Optional[torch.Tensor] = None):
+    it = items[k]
+    it.in_ = _item_ptr(x)
+    it.n = x.numel() if n is None else n
+    it.in_bytes = in_bytes
+    it.cb = dcb.handle.value if dcb is not None else None
+    it.out = _item_ptr(out)
+    it.out_cap = 0 if out is None else out.numel()
+    it.block_off = _item_ptr(block_off)
+    it.sub_idx = _item_ptr(sub_idx)
+    it.hist = _item_ptr(hist)
+
+
+def hc_batch_workspace_bytes(items, block_size: int) -> int:
+    return int(_lib.hc_batch_workspace_bytes(items, len(items), block_size))
+
+
+def hc_histogram_batch(items, ws: torch.Tensor, stream=None) -> None:
+    _check(_lib.hc_histogram_batch(items, len(items), _ptr(ws), ws.numel(), _stream(stream)), "hc_histogram_batch")
+
+
+def hc_encode_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, err: torch.Tensor,
+                    stream=None) -> None:
+    _check(_lib.hc_encode_batch(items, len(items), block_size, sub_block, _ptr(ws), ws.numel(), _ptr(err),
+                                _stream(stream)), "hc_encode_batch")
+
+
+def hc_decode_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, err: torch.Tensor,
+                    stream=None) -> None:
+    _check(_lib.hc_decode_batch(items, len(items), block_size, sub_block, _ptr(ws), ws.numel(), _ptr(err),
+                                _stream(stream)), "hc_decode_batch")

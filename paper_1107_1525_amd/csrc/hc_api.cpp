@@ -5,6 +5,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <vector>
+
 #include "hc_internal.h"
 #include "hc_kernels.h"
 
@@ -38,13 +40,6 @@ extern "C" const char *hc_status_str(int status)
 }
 
 extern "C" int hc_version(void) { return 100; }
-
-extern "C" hc_status hc_histogram(const uint8_t *d_in, uint64_t n, uint64_t *d_hist, void *stream)
-{
-    if (!d_hist || !aligned(d_hist, 8)) return HC_ERR_INVALID_ARG;
-    if (n > 0 && (!d_in || !aligned(d_in, 16))) return HC_ERR_INVALID_ARG;
-    return hip_status(launch_histogram(d_in, n, d_hist, static_cast<hipStream_t>(stream)));
-}
 
 namespace {
 
@@ -135,14 +130,95 @@ extern "C" uint64_t hc_encode_bound(uint64_t n, uint32_t block_size, uint32_t ma
 extern "C" uint64_t hc_encode_workspace_bytes(uint64_t n, uint32_t block_size)
 {
     if (block_size == 0) return 0;
-    return encode_ws_bytes(make_geom(n, block_size));
+    const uint64_t nb = num_blocks(n, block_size);
+    return 8 * encode_state_words(nb * tiles_per_block(block_size), nb);
 }
 
 extern "C" uint64_t hc_sub_index_entries(uint64_t n, uint32_t block_size, uint32_t sub_block)
 {
     if (block_size == 0 || sub_block == 0) return 0;
-    const uint64_t nb = (n + block_size - 1) / block_size;
-    return nb * ((block_size + sub_block - 1) / sub_block);
+    return num_blocks(n, block_size) * ((block_size + sub_block - 1) / sub_block);
+}
+
+namespace {
+
+Job empty_job()
+{
+    Job j;
+    memset(&j, 0, sizeof(j));
+    return j;
+}
+
+JobList single(const Job &j)
+{
+    JobList jl;
+    jl.jobs = nullptr;
+    jl.count = 1;
+    jl.one = j;
+    return jl;
+}
+
+uint64_t decode_groups(uint64_t n, uint32_t B, uint32_t S)
+{
+    const uint64_t lanes = num_blocks(n, B) * (S ? (B + S - 1) / S : 1);
+    return (lanes + kDecThreads - 1) / kDecThreads;
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Checks of one encode input; the same for the single and the batched call.
+hc_status check_encode(const uint8_t *in, uint64_t n, uint32_t B, hc_cb_handle cb, const uint8_t *out,
+                       uint64_t out_cap, const uint64_t *block_off, const uint32_t *sub_idx, uint32_t S)
+{
+    if (!cb || !block_off || !aligned(block_off, 8)) return HC_ERR_INVALID_ARG;
+    if ((sub_idx == nullptr) != (S == 0)) return HC_ERR_INVALID_ARG;
+    if (sub_idx && !aligned(sub_idx, 4)) return HC_ERR_INVALID_ARG;
+    if (n > 0) {
+        if (!in || !aligned(in, 16) || !out || !aligned(out, 16)) return HC_ERR_INVALID_ARG;
+        if (cb->host.max_len == 0) return HC_ERR_INVALID_ARG;  // no code for any symbol
+        if (out_cap < hc_encode_bound(n, B, cb->host.max_len)) return HC_ERR_NO_SPACE;
+    }
+    return HC_OK;
+}
+
+hc_status check_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, hc_cb_handle cb, const uint64_t *block_off,
+                       const uint32_t *sub_idx, uint32_t S, const uint8_t *out)
+{
+    if (!cb) return HC_ERR_INVALID_ARG;
+    if ((sub_idx == nullptr) != (S == 0)) return HC_ERR_INVALID_ARG;
+    if (n == 0) return HC_OK;
+    if (!in || !aligned(in, 16) || (in_bytes & 3) || !block_off || !aligned(block_off, 8) || !out ||
+        !aligned(out, 16) || (sub_idx && !aligned(sub_idx, 4)))
+        return HC_ERR_INVALID_ARG;
+    if (cb->host.max_len == 0) return HC_ERR_INVALID_ARG;
+    return HC_OK;
+}
+
+// Copies a job list into the head of the caller's workspace.
+hc_status upload_jobs(const std::vector<Job> &jobs, void *ws, hipStream_t s, JobList *jl)
+{
+    if (hipMemcpyAsync(ws, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice, s) != hipSuccess)
+        return HC_ERR_HIP;
+    jl->jobs = static_cast<const Job *>(ws);
+    jl->count = (uint32_t)jobs.size();
+    jl->one = empty_job();
+    return HC_OK;
+}
+
+}  // namespace
+
+extern "C" hc_status hc_histogram(const uint8_t *d_in, uint64_t n, uint64_t *d_hist, void *stream)
+{
+    if (!d_hist || !aligned(d_hist, 8)) return HC_ERR_INVALID_ARG;
+    if (n > 0 && (!d_in || !aligned(d_in, 16))) return HC_ERR_INVALID_ARG;
+    Job j = empty_job();
+    j.in = d_in;
+    j.n = n;
+    j.hist = d_hist;
+    const uint64_t chunk = hist_chunk(n);
+    const uint64_t units = (n + chunk - 1) / chunk;
+    if (units > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    return hip_status(launch_histogram(single(j), units, chunk, static_cast<hipStream_t>(stream)));
 }
 
 extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t block_size, hc_cb_handle cb,
@@ -150,23 +226,25 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
                                       uint32_t *d_sub_idx, uint32_t sub_block, void *d_ws,
                                       uint64_t ws_bytes, uint32_t *d_err, void *stream)
 {
-    if (!valid_block_size(block_size) || !valid_sub_block(sub_block) || !cb || !d_block_off ||
-        !aligned(d_block_off, 8))
-        return HC_ERR_INVALID_ARG;
-    if ((d_sub_idx == nullptr) != (sub_block == 0)) return HC_ERR_INVALID_ARG;
-    if (d_sub_idx && !aligned(d_sub_idx, 4)) return HC_ERR_INVALID_ARG;
-    const TileGeom g = make_geom(n, block_size);
-    if (n > 0) {
-        if (!d_in || !aligned(d_in, 16) || !d_out || !aligned(d_out, 16) || !d_ws || !aligned(d_ws, 8))
-            return HC_ERR_INVALID_ARG;
-        if (cb->host.max_len == 0) return HC_ERR_INVALID_ARG;  // no code for any symbol
-        if (out_cap < hc_encode_bound(n, block_size, cb->host.max_len)) return HC_ERR_NO_SPACE;
-        if (ws_bytes < encode_ws_bytes(g)) return HC_ERR_NO_SPACE;
-        if (g.nb * g.tpb > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;  // grid limit
-    }
-    const EncodeWs ws = n > 0 ? carve_encode_ws(d_ws, g) : EncodeWs{nullptr, nullptr, nullptr};
-    return hip_status(launch_encode(d_in, g, cb->d_tables, cb->host.max_len, d_out, d_block_off, d_sub_idx,
-                                    sub_block, ws, d_err, static_cast<hipStream_t>(stream)));
+    if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
+    hc_status st = check_encode(d_in, n, block_size, cb, d_out, out_cap, d_block_off, d_sub_idx, sub_block);
+    if (st != HC_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n == 0) return hip_status(launch_encode_empty(d_block_off, s));
+    const uint64_t nb = num_blocks(n, block_size);
+    const uint64_t tiles = nb * tiles_per_block(block_size);
+    if (!d_ws || !aligned(d_ws, 8)) return HC_ERR_INVALID_ARG;
+    if (ws_bytes < 8 * encode_state_words(tiles, nb)) return HC_ERR_NO_SPACE;
+    if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;  // grid limit
+    Job j = empty_job();
+    j.in = d_in;
+    j.n = n;
+    j.tb = cb->d_tables;
+    j.out = d_out;
+    j.block_off = d_block_off;
+    j.sub_idx = d_sub_idx;
+    return hip_status(launch_encode(single(j), tiles, nb, block_size, cb->host.max_len, sub_block,
+                                    static_cast<uint64_t *>(d_ws), d_err, s));
 }
 
 extern "C" hc_status hc_walk_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t nb, uint64_t *d_block_off,
@@ -181,17 +259,140 @@ extern "C" hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, ui
                                       hc_cb_handle cb, const uint64_t *d_block_off, const uint32_t *d_sub_idx,
                                       uint32_t sub_block, uint8_t *d_out, uint32_t *d_err, void *stream)
 {
-    if (!valid_block_size(block_size) || !valid_sub_block(sub_block) || !cb) return HC_ERR_INVALID_ARG;
-    if ((d_sub_idx == nullptr) != (sub_block == 0)) return HC_ERR_INVALID_ARG;
-    if (n == 0) return HC_OK;
-    if (!d_in || !aligned(d_in, 16) || !d_block_off || !aligned(d_block_off, 8) || !d_out ||
-        !aligned(d_out, 16) || (d_sub_idx && !aligned(d_sub_idx, 4)))
-        return HC_ERR_INVALID_ARG;
-    if (cb->host.max_len == 0) return HC_ERR_INVALID_ARG;
-    const uint64_t nb = (n + block_size - 1) / block_size;
-    const uint64_t lanes = nb * (d_sub_idx ? (block_size + sub_block - 1) / sub_block : 1);
-    if ((lanes + kDecThreads - 1) / kDecThreads > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
-    if (in_bytes & 3) return HC_ERR_INVALID_ARG;
-    return hip_status(launch_decode(d_in, in_bytes, n, block_size, cb->d_tables, cb->host.max_len, d_block_off,
-                                    d_sub_idx, sub_block, d_out, d_err, static_cast<hipStream_t>(stream)));
+    if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
+    hc_status st = check_decode(d_in, in_bytes, n, cb, d_block_off, d_sub_idx, sub_block, d_out);
+    if (st != HC_OK || n == 0) return st;
+    const uint64_t groups = decode_groups(n, block_size, sub_block);
+    if (groups > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    Job j = empty_job();
+    j.in = d_in;
+    j.in_bytes = in_bytes;
+    j.n = n;
+    j.tb = cb->d_tables;
+    j.out = d_out;
+    j.block_off = const_cast<uint64_t *>(d_block_off);
+    j.sub_idx = const_cast<uint32_t *>(d_sub_idx);
+    return hip_status(launch_decode(single(j), groups, block_size, cb->host.max_len, sub_block, d_sub_idx != nullptr,
+                                    d_err, static_cast<hipStream_t>(stream)));
+}
+
+// ---------------------------------------------------------------------- batches
+extern "C" uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size)
+{
+    if (!items || block_size == 0) return 0;
+    uint64_t tiles = 0, blocks = 0;
+    for (uint32_t k = 0; k < count; ++k) {
+        const uint64_t nb = num_blocks(items[k].n, block_size);
+        blocks += nb;
+        tiles += nb * tiles_per_block(block_size);
+    }
+    return align256((uint64_t)count * sizeof(Job)) + 8 * encode_state_words(tiles, blocks);
+}
+
+extern "C" hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes,
+                                        void *stream)
+{
+    if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
+    if (ws_bytes < align256((uint64_t)count * sizeof(Job))) return HC_ERR_NO_SPACE;
+    uint64_t total = 0;
+    for (uint32_t k = 0; k < count; ++k) {
+        const hc_item &it = items[k];
+        if (!it.hist || !aligned(it.hist, 8)) return HC_ERR_INVALID_ARG;
+        if (it.n > 0 && (!it.in || !aligned(it.in, 16))) return HC_ERR_INVALID_ARG;
+        total += it.n;
+    }
+    const uint64_t chunk = hist_chunk(total);
+    std::vector<Job> jobs(count);
+    uint64_t units = 0;
+    for (uint32_t k = 0; k < count; ++k) {
+        Job j = empty_job();
+        j.in = items[k].in;
+        j.n = items[k].n;
+        j.hist = items[k].hist;
+        j.unit_begin = units;
+        units += (items[k].n + chunk - 1) / chunk;
+        jobs[k] = j;
+    }
+    if (units > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    JobList jl;
+    hc_status st = upload_jobs(jobs, d_ws, s, &jl);
+    if (st != HC_OK) return st;
+    return hip_status(launch_histogram(jl, units, chunk, s));
+}
+
+extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                                     void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream)
+{
+    if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
+    if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
+    std::vector<Job> jobs(count);
+    uint64_t tiles = 0, blocks = 0;
+    uint32_t max_len = 1;
+    const uint32_t tpb = tiles_per_block(block_size);
+    for (uint32_t k = 0; k < count; ++k) {
+        const hc_item &it = items[k];
+        hc_status st = check_encode(it.in, it.n, block_size, it.cb, it.out, it.out_cap, it.block_off, it.sub_idx,
+                                    sub_block);
+        if (st != HC_OK) return st;
+        Job j = empty_job();
+        j.in = it.in;
+        j.n = it.n;
+        j.tb = it.cb->d_tables;
+        j.out = it.out;
+        j.block_off = it.block_off;
+        j.sub_idx = it.sub_idx;
+        j.unit_begin = tiles;
+        j.block_begin = blocks;
+        const uint64_t nb = num_blocks(it.n, block_size);
+        tiles += nb * tpb;
+        blocks += nb;
+        if (it.n > 0 && it.cb->host.max_len > max_len) max_len = it.cb->host.max_len;
+        jobs[k] = j;
+    }
+    if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    const uint64_t head = align256((uint64_t)count * sizeof(Job));
+    if (ws_bytes < head + 8 * encode_state_words(tiles, blocks)) return HC_ERR_NO_SPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    JobList jl;
+    hc_status st = upload_jobs(jobs, d_ws, s, &jl);
+    if (st != HC_OK) return st;
+    for (uint32_t k = 0; k < count; ++k)
+        if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
+    uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(d_ws) + head);
+    return hip_status(launch_encode(jl, tiles, blocks, block_size, max_len, sub_block, state, d_err, s));
+}
+
+extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                                     void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream)
+{
+    if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
+    if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
+    if (ws_bytes < align256((uint64_t)count * sizeof(Job))) return HC_ERR_NO_SPACE;
+    std::vector<Job> jobs(count);
+    uint64_t groups = 0;
+    uint32_t max_len = 1;
+    for (uint32_t k = 0; k < count; ++k) {
+        const hc_item &it = items[k];
+        hc_status st = check_decode(it.in, it.in_bytes, it.n, it.cb, it.block_off, it.sub_idx, sub_block, it.out);
+        if (st != HC_OK) return st;
+        Job j = empty_job();
+        j.in = it.in;
+        j.in_bytes = it.in_bytes;
+        j.n = it.n;
+        j.tb = it.cb->d_tables;
+        j.out = it.out;
+        j.block_off = it.block_off;
+        j.sub_idx = it.sub_idx;
+        j.unit_begin = groups;
+        groups += it.n ? decode_groups(it.n, block_size, sub_block) : 0;
+        if (it.n > 0 && it.cb->host.max_len > max_len) max_len = it.cb->host.max_len;
+        jobs[k] = j;
+    }
+    if (groups > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    JobList jl;
+    hc_status st = upload_jobs(jobs, d_ws, s, &jl);
+    if (st != HC_OK) return st;
+    return hip_status(launch_decode(jl, groups, block_size, max_len, sub_block, sub_block != 0, d_err, s));
 }

@@ -1,4 +1,4 @@
-// Launch geometry shared by the kernels and the host glue.
+// Launch geometry and job descriptors shared by the kernels and the host glue.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -18,41 +18,50 @@ constexpr uint32_t kTileSyms = kTileThreads * kSymPerThread;  // 4096 symbols pe
 
 constexpr int kDecThreads = 256;
 
-struct TileGeom {
-    uint64_t n;    // symbols
-    uint64_t nb;   // blocks
-    uint32_t B;    // symbols per block
-    uint32_t tpb;  // tiles per block: ceil(B / kTileSyms)
+// One buffer of a launch.  A launch covers one or more jobs; its launch units
+// (histogram chunks, encode tiles, decode work-groups) are numbered job after
+// job, and unit_begin is the first unit of this job.
+struct Job {
+    const uint8_t *in;     // histogram/encode: the symbols; decode: the stream
+    uint64_t n;            // symbols
+    uint64_t in_bytes;     // decode: stream bytes
+    const DevTables *tb;   // encode/decode: the job's code tables
+    uint8_t *out;          // encode: the stream; decode: the symbols
+    uint64_t *block_off;   // encode: written; decode: read
+    uint32_t *sub_idx;     // sub-block index or null
+    uint64_t *hist;        // histogram: 256 counts
+    uint64_t unit_begin;   // first launch unit of the job
+    uint64_t block_begin;  // encode: first entry of the job in the block states
 };
 
-inline TileGeom make_geom(uint64_t n, uint32_t B)
+// The jobs of a launch: a device array, or a single job passed by value.
+struct JobList {
+    const Job *jobs;  // device array of 'count' jobs, or null when count == 1
+    uint32_t count;
+    Job one;
+};
+
+inline uint64_t num_blocks(uint64_t n, uint32_t B) { return (n + B - 1) / B; }
+inline uint32_t tiles_per_block(uint32_t B) { return (B + kTileSyms - 1) / kTileSyms; }
+inline uint64_t hist_chunk(uint64_t total)
 {
-    TileGeom g;
-    g.n = n;
-    g.B = B;
-    g.nb = (n + B - 1) / B;
-    g.tpb = (B + kTileSyms - 1) / kTileSyms;
-    return g;
+    uint64_t chunk = (total + kHistTargetGroups - 1) / kHistTargetGroups;
+    chunk = (chunk + 15) & ~uint64_t(15);
+    if (chunk < kHistMinChunk) chunk = kHistMinChunk;
+    if (chunk > (1ull << 30)) chunk = 1ull << 30;  // keeps every LDS counter below 2^32
+    return chunk;
 }
 
-struct EncodeWs {
-    uint64_t *counter;  // tile counter (low 32 bits used)
-    uint64_t *tstate;   // look-back state per tile
-    uint64_t *bstate;   // look-back state per block
-};
+// Encode scratch: tile counter, then one look-back state per tile and per block.
+inline uint64_t encode_state_words(uint64_t tiles, uint64_t blocks) { return 2 + tiles + blocks; }
 
-// Bytes of encode workspace and its carving into arrays.
-uint64_t encode_ws_bytes(const TileGeom &g);
-EncodeWs carve_encode_ws(void *ws, const TileGeom &g);
-
-hipError_t launch_histogram(const uint8_t *in, uint64_t n, uint64_t *hist, hipStream_t s);
-hipError_t launch_encode(const uint8_t *in, const TileGeom &g, const DevTables *tb, uint32_t max_len,
-                         uint8_t *out, uint64_t *block_off, uint32_t *sub_idx, uint32_t S,
-                         const EncodeWs &ws, uint32_t *err, hipStream_t s);
+hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, hipStream_t s);
+hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uint32_t B, uint32_t max_len,
+                         uint32_t S, uint64_t *state, uint32_t *err, hipStream_t s);
+hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s);
 hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64_t *block_off,
                        uint32_t *err, hipStream_t s);
-hipError_t launch_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
-                         uint32_t max_len, const uint64_t *block_off, const uint32_t *sub_idx, uint32_t S,
-                         uint8_t *out, uint32_t *err, hipStream_t s);
+hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_t max_len, uint32_t S,
+                         bool with_index, uint32_t *err, hipStream_t s);
 
 }  // namespace hc

@@ -68,9 +68,25 @@ __device__ __forceinline__ T group_exclusive_scan(T v, T *scratch, T *total)
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t count, uint64_t value)
 {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = value;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
 }
+
+// The job owning launch unit u (the last job whose unit_begin <= u).
+__device__ __forceinline__ uint32_t job_of_unit(const JobList &jl, uint64_t u)
+{
+    if (jl.count == 1) return 0;
+    uint32_t lo = 0, hi = jl.count;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (jl.jobs[mid].unit_begin <= u) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ Job job_at(const JobList &jl, uint32_t k) { return jl.jobs ? jl.jobs[k] : jl.one; }
 
 // ---------------------------------------------------------------- histogram
 // Each work-group counts a contiguous chunk into 64 LDS sub-histograms laid
@@ -79,16 +95,24 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t count, uint64_t value)
 // consecutive words whatever the data (no bank conflicts, no same-address
 // serialisation on skewed inputs).  The group then folds the 64 copies and adds
 // its counts to the global u64 histogram.
-__global__ __launch_bounds__(kHistThreads) void k_hist(const uint8_t *__restrict__ in, uint64_t n,
-                                                       uint64_t chunk,
-                                                       unsigned long long *__restrict__ hist)
+__global__ void k_hist_zero(JobList jl)
+{
+    const Job jb = job_at(jl, blockIdx.x);
+    if (threadIdx.x < (uint32_t)kNumSym) jb.hist[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kHistThreads) void k_hist(JobList jl, uint64_t chunk)
 {
     __shared__ uint32_t sh[kNumSym * 64];
+    __shared__ Job s_job;
+    if (threadIdx.x == 0) s_job = job_at(jl, job_of_unit(jl, blockIdx.x));
     for (int k = threadIdx.x; k < kNumSym * 64; k += kHistThreads) sh[k] = 0;
     __syncthreads();
 
+    const uint8_t *__restrict__ in = s_job.in;
+    const uint64_t n = s_job.n;
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t beg = (uint64_t)blockIdx.x * chunk;
+    const uint64_t beg = (blockIdx.x - s_job.unit_begin) * chunk;
     const uint64_t end = beg + chunk < n ? beg + chunk : n;
     const uint64_t nvec = (end - beg) >> 4;
     const uint4 *p = reinterpret_cast<const uint4 *>(in + beg);
@@ -127,11 +151,13 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(const uint8_t *__restrict
         uint64_t s = 0;
 #pragma unroll 8
         for (uint32_t r = 0; r < 64; ++r) s += sh[b * 64 + ((r + b) & 63u)];  // rotated: no conflicts
-        if (s) atomicAdd(&hist[b], (unsigned long long)s);
+        if (s) atomicAdd(reinterpret_cast<unsigned long long *>(&s_job.hist[b]), (unsigned long long)s);
     }
 }
 
 // ---------------------------------------------------------------- tiles
+__device__ __forceinline__ uint64_t num_blocks_dev(uint64_t n, uint32_t B) { return (n + B - 1) / B; }
+
 struct Tile {
     uint64_t blk;       // block index
     uint32_t j;         // tile index inside the block
@@ -140,14 +166,15 @@ struct Tile {
     uint32_t ts, te;    // symbol range of the tile, relative to the block
 };
 
-__device__ __forceinline__ Tile tile_of(const TileGeom &g, uint64_t t)
+// Tile t (counted from the job's first tile) of a job of n symbols.
+__device__ __forceinline__ Tile tile_of(uint64_t n, uint32_t B, uint32_t tpb, uint64_t t)
 {
     Tile r;
-    r.blk = t / g.tpb;
-    r.j = (uint32_t)(t - r.blk * g.tpb);
-    r.blk_start = r.blk * (uint64_t)g.B;
-    const uint64_t left = g.n - r.blk_start;
-    r.cnt = (uint32_t)(left < g.B ? left : g.B);
+    r.blk = t / tpb;
+    r.j = (uint32_t)(t - r.blk * tpb);
+    r.blk_start = r.blk * (uint64_t)B;
+    const uint64_t left = n - r.blk_start;
+    r.cnt = (uint32_t)(left < B ? left : B);
     r.ts = r.j * kTileSyms;
     const uint32_t e = r.ts + kTileSyms;
     r.te = e < r.cnt ? e : r.cnt;
@@ -254,42 +281,61 @@ __device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t
 }
 
 template <bool kPacked>
-__global__ __launch_bounds__(kTileThreads) void k_encode(
-    const uint8_t *__restrict__ in, TileGeom g, const DevTables *__restrict__ tb, uint64_t *tstate,
-    uint64_t *bstate, uint32_t *counter, uint32_t *__restrict__ out32, uint64_t *__restrict__ block_off,
-    uint32_t *__restrict__ sub_idx, uint32_t S, uint32_t cpb, uint32_t lds_words, uint32_t *err)
+__global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B, uint32_t tpb,
+                                                         uint64_t *tstate, uint64_t *bstate_all,
+                                                         uint32_t *counter, uint32_t S, uint32_t cpb,
+                                                         uint32_t lds_words, uint32_t *err)
 {
     extern __shared__ uint32_t words[];  // the tile's code bits from bit 0, MSB first
     __shared__ uint32_t s_packed[kNumSym];
     __shared__ uint64_t s_code[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_len[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_scan[kTileThreads / 64];
-    __shared__ uint32_t s_tile, s_lead, s_bits;
-    __shared__ uint64_t s_P, s_O;
+    __shared__ uint32_t s_lead, s_bits;
+    __shared__ uint64_t s_tile, s_P, s_O;
+    __shared__ Job s_job;
 
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_tile = atomicAdd(counter, 1u);
+    if (tid == 0) {
+        const uint64_t t = atomicAdd(counter, 1u);
+        s_tile = t;
+        s_job = job_at(jl, job_of_unit(jl, t));
+    }
+    for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
+    __syncthreads();
+    const DevTables *__restrict__ tb = s_job.tb;
     if (kPacked) {
         s_packed[tid] = tb->enc_packed[tid];
     } else {
         s_code[tid] = tb->enc_code[tid];
         s_len[tid] = tb->enc_len[tid];
     }
-    for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
-    __syncthreads();
 
+    const uint8_t *__restrict__ in = s_job.in;
+    uint32_t *__restrict__ out32 = reinterpret_cast<uint32_t *>(s_job.out);
+    uint32_t *__restrict__ sub_idx = s_job.sub_idx;
+    uint64_t *bstate = bstate_all + s_job.block_begin;
+    const uint64_t nb = num_blocks_dev(s_job.n, B);
     const uint64_t t = s_tile;
-    const Tile tl = tile_of(g, t);
+    const Tile tl = tile_of(s_job.n, B, tpb, t - s_job.unit_begin);
     if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
     const bool last_tile = tl.te == tl.cnt;
 
     const uint32_t s = tl.ts + kSymPerThread * tid;
     uint32_t w[4];
     const uint32_t m = load16(in, tl, s, w);
+    __syncthreads();  // code tables are in LDS
     uint32_t bits = 0;
+    bool absent = false;
 #pragma unroll
-    for (uint32_t k = 0; k < 16; ++k)
-        if (k < m) bits += kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
+    for (uint32_t k = 0; k < 16; ++k) {
+        if (k < m) {
+            const uint32_t L = kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
+            absent |= (L == 0);
+            bits += L;
+        }
+    }
+    if (absent) report(err, HC_ERR_SYMBOL_ABSENT);
     uint32_t tile_total;
     const uint32_t q = group_exclusive_scan<uint32_t, kTileThreads>(bits, s_scan, &tile_total);
 
@@ -375,8 +421,8 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(
             s_O = O;
             s_bits = (uint32_t)blk_bits;
             if (last_tile) {
-                block_off[tl.blk] = O;
-                if (tl.blk + 1 == g.nb) block_off[g.nb] = O + blk_bytes;
+                s_job.block_off[tl.blk] = O;
+                if (tl.blk + 1 == nb) s_job.block_off[nb] = O + blk_bytes;
             }
         }
     }
@@ -505,19 +551,26 @@ __device__ __forceinline__ uint32_t decode_one(BitReader &br, const uint32_t *__
     return 0;
 }
 
-__global__ __launch_bounds__(kDecThreads) void k_decode(
-    const uint32_t *__restrict__ in32, uint64_t in_bytes, uint64_t n, uint32_t B, uint64_t nb,
-    const DevTables *__restrict__ tb, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ sub_idx, uint32_t S_eff, uint32_t cpb, uint8_t *__restrict__ out,
-    uint32_t *err)
+__global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
+                                                        uint32_t *err)
 {
     __shared__ uint16_t s_lut[1 << kLutBits];
     __shared__ uint64_t s_first[kMaxLen + 1];
     __shared__ uint32_t s_count[kMaxLen + 1];
     __shared__ uint32_t s_base[kMaxLen + 1];
     __shared__ uint32_t s_sorted[kNumSym];
+    __shared__ Job s_job;
 
     const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_job = job_at(jl, job_of_unit(jl, blockIdx.x));
+    __syncthreads();
+    const DevTables *__restrict__ tb = s_job.tb;
+    const uint32_t *__restrict__ in32 = reinterpret_cast<const uint32_t *>(s_job.in);
+    const uint64_t in_bytes = s_job.in_bytes, n = s_job.n;
+    const uint64_t nb = num_blocks_dev(n, B);
+    const uint64_t *__restrict__ off = s_job.block_off;
+    const uint32_t *__restrict__ sub_idx = s_job.sub_idx;
+    uint8_t *__restrict__ out = s_job.out;
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
     for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
@@ -529,7 +582,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
     s_sorted[tid] = tb->sorted[tid];
     __syncthreads();
 
-    const uint64_t g = (uint64_t)blockIdx.x * kDecThreads + tid;
+    const uint64_t g = (uint64_t)(blockIdx.x - s_job.unit_begin) * kDecThreads + tid;
     const uint64_t i = g / cpb;
     const uint32_t c = (uint32_t)(g - i * cpb);
     if (i >= nb) return;
@@ -614,11 +667,8 @@ __device__ __forceinline__ uint4 load_quad(const uint32_t *__restrict__ in32, ui
 }
 
 template <uint32_t R>
-__global__ __launch_bounds__(kDecThreads) void k_decode_ring(
-    const uint32_t *__restrict__ in32, uint64_t in_bytes, uint64_t n, uint32_t B, uint64_t nb,
-    const DevTables *__restrict__ tb, const uint64_t *__restrict__ off,
-    const uint32_t *__restrict__ sub_idx, uint32_t S_eff, uint32_t cpb, uint8_t *__restrict__ out,
-    uint32_t *err)
+__global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
+                                                             uint32_t *err)
 {
     __shared__ uint16_t s_lut[1 << kLutBits];
     __shared__ uint32_t s_ring[kDecThreads * kRingStride];
@@ -626,8 +676,18 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(
     __shared__ uint32_t s_count[kPackedMaxLen + 1];
     __shared__ uint32_t s_base[kPackedMaxLen + 1];
     __shared__ uint32_t s_sorted[kNumSym];
+    __shared__ Job s_job;
 
     const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_job = job_at(jl, job_of_unit(jl, blockIdx.x));
+    __syncthreads();
+    const DevTables *__restrict__ tb = s_job.tb;
+    const uint32_t *__restrict__ in32 = reinterpret_cast<const uint32_t *>(s_job.in);
+    const uint64_t in_bytes = s_job.in_bytes, n = s_job.n;
+    const uint64_t nb = num_blocks_dev(n, B);
+    const uint64_t *__restrict__ off = s_job.block_off;
+    const uint32_t *__restrict__ sub_idx = s_job.sub_idx;
+    uint8_t *__restrict__ out = s_job.out;
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
     for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
@@ -639,7 +699,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(
     s_sorted[tid] = tb->sorted[tid];
     __syncthreads();  // the last barrier: lanes may leave early from here on
 
-    const uint64_t g = (uint64_t)blockIdx.x * kDecThreads + tid;
+    const uint64_t g = (uint64_t)(blockIdx.x - s_job.unit_begin) * kDecThreads + tid;
     const uint64_t i = g / cpb;
     const uint32_t c = (uint32_t)(g - i * cpb);
     if (i >= nb) return;
@@ -781,58 +841,32 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(
 }
 
 // ---------------------------------------------------------------- launchers
-static inline uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
-
-uint64_t encode_ws_bytes(const TileGeom &g)
+hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, hipStream_t s)
 {
-    const uint64_t ntiles = g.nb * g.tpb;
-    return 8 * (2 + ntiles + g.nb);
-}
-
-EncodeWs carve_encode_ws(void *ws, const TileGeom &g)
-{
-    EncodeWs w;
-    w.counter = static_cast<uint64_t *>(ws);     // word 0: tile counter; word 1: spare
-    w.tstate = w.counter + 2;
-    w.bstate = w.tstate + g.nb * g.tpb;
-    return w;
-}
-
-hipError_t launch_histogram(const uint8_t *in, uint64_t n, uint64_t *hist, hipStream_t s)
-{
-    k_fill_u64<<<1, kNumSym, 0, s>>>(hist, kNumSym, 0);
-    if (n == 0) return hipGetLastError();
-    uint64_t chunk = (n + kHistTargetGroups - 1) / kHistTargetGroups;
-    chunk = (chunk + 15) & ~uint64_t(15);
-    if (chunk < kHistMinChunk) chunk = kHistMinChunk;
-    if (chunk > (1ull << 30)) chunk = 1ull << 30;  // keeps every LDS counter below 2^32
-    const uint64_t groups = (n + chunk - 1) / chunk;
-    k_hist<<<dim3((uint32_t)groups), kHistThreads, 0, s>>>(in, n, chunk,
-                                                           reinterpret_cast<unsigned long long *>(hist));
+    k_hist_zero<<<dim3(jl.count), kNumSym, 0, s>>>(jl);
+    if (units) k_hist<<<dim3((uint32_t)units), kHistThreads, 0, s>>>(jl, chunk);
     return hipGetLastError();
 }
 
-hipError_t launch_encode(const uint8_t *in, const TileGeom &g, const DevTables *tb, uint32_t max_len,
-                         uint8_t *out, uint64_t *block_off, uint32_t *sub_idx, uint32_t S,
-                         const EncodeWs &ws, uint32_t *err, hipStream_t s)
+hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uint32_t B, uint32_t max_len,
+                         uint32_t S, uint64_t *state, uint32_t *err, hipStream_t s)
 {
-    if (g.n == 0) {
-        k_fill_u64<<<1, 64, 0, s>>>(block_off, 1, 0);
-        return hipGetLastError();
-    }
-    const uint64_t ntiles = g.nb * g.tpb;
-    const uint64_t nstate = 2 + ntiles + g.nb;
-    k_fill_u64<<<dim3((uint32_t)((nstate + 255) / 256)), 256, 0, s>>>(ws.counter, nstate, 0);
+    const uint64_t words = encode_state_words(tiles, blocks);
+    uint64_t fill_groups = (words + 255) / 256;
+    if (fill_groups > 4096) fill_groups = 4096;
+    k_fill_u64<<<dim3((uint32_t)fill_groups), 256, 0, s>>>(state, words, 0);
+    if (tiles == 0) return hipGetLastError();
+    const uint32_t tpb = tiles_per_block(B);
     const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * max_len + 31ull) / 32ull + 2);
-    const uint32_t cpb = S ? (g.B + S - 1) / S : 1;
-    uint32_t *out32 = reinterpret_cast<uint32_t *>(out);
-    uint32_t *counter = reinterpret_cast<uint32_t *>(ws.counter);
+    const uint32_t cpb = S ? (B + S - 1) / S : 1;
+    uint32_t *counter = reinterpret_cast<uint32_t *>(state);
+    uint64_t *tstate = state + 2, *bstate = state + 2 + tiles;
     if (max_len <= (uint32_t)kPackedMaxLen)
-        k_encode<true><<<dim3((uint32_t)ntiles), kTileThreads, lds_words * 4, s>>>(
-            in, g, tb, ws.tstate, ws.bstate, counter, out32, block_off, sub_idx, S, cpb, lds_words, err);
+        k_encode<true><<<dim3((uint32_t)tiles), kTileThreads, lds_words * 4, s>>>(jl, B, tpb, tstate, bstate,
+                                                                                 counter, S, cpb, lds_words, err);
     else
-        k_encode<false><<<dim3((uint32_t)ntiles), kTileThreads, lds_words * 4, s>>>(
-            in, g, tb, ws.tstate, ws.bstate, counter, out32, block_off, sub_idx, S, cpb, lds_words, err);
+        k_encode<false><<<dim3((uint32_t)tiles), kTileThreads, lds_words * 4, s>>>(jl, B, tpb, tstate, bstate,
+                                                                                  counter, S, cpb, lds_words, err);
     return hipGetLastError();
 }
 
@@ -843,26 +877,25 @@ hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
-                         uint32_t max_len, const uint64_t *block_off, const uint32_t *sub_idx, uint32_t S,
-                         uint8_t *out, uint32_t *err, hipStream_t s)
+hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    const uint64_t nb = (n + B - 1) / B;
-    const uint32_t S_eff = sub_idx ? S : B;
-    const uint32_t cpb = sub_idx ? (B + S - 1) / S : 1;
-    const uint64_t lanes = nb * cpb;
-    const uint64_t groups = (lanes + kDecThreads - 1) / kDecThreads;
-    const uint32_t *in32 = reinterpret_cast<const uint32_t *>(in);
+    k_fill_u64<<<1, 64, 0, s>>>(block_off, 1, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_t max_len, uint32_t S,
+                         bool with_index, uint32_t *err, hipStream_t s)
+{
+    if (groups == 0) return hipSuccess;
+    const uint32_t S_eff = with_index ? S : B;
+    const uint32_t cpb = with_index ? (B + S - 1) / S : 1;
+    const dim3 grid((uint32_t)groups);
     if (max_len <= 15)
-        k_decode_ring<32><<<dim3((uint32_t)groups), kDecThreads, 0, s>>>(in32, in_bytes, n, B, nb, tb, block_off,
-                                                                         sub_idx, S_eff, cpb, out, err);
+        k_decode_ring<32><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     else if (max_len <= (uint32_t)kPackedMaxLen)
-        k_decode_ring<16><<<dim3((uint32_t)groups), kDecThreads, 0, s>>>(in32, in_bytes, n, B, nb, tb, block_off,
-                                                                         sub_idx, S_eff, cpb, out, err);
+        k_decode_ring<16><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     else
-        k_decode<<<dim3((uint32_t)groups), kDecThreads, 0, s>>>(in32, in_bytes, n, B, nb, tb, block_off, sub_idx,
-                                                               S_eff, cpb, out, err);
+        k_decode<<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     return hipGetLastError();
 }
 

@@ -298,3 +298,104 @@ def test_mixed_4gib_sampled(hc, oracle):
                 assert torch.equal(hc.decompress(enc), xs)
     del x
     torch.cuda.empty_cache()
+
+
+def test_codebook_update_in_place(hc, oracle):
+    """hc_codebook_update swaps the tables of a handle on the stream: work
+    enqueued before sees the old code, work enqueued after the new one."""
+    xa = synth.zipf_bytes(300_000, 1.2, 21)
+    xb = synth.skewed_bytes(300_000, 22)
+    La, Ca = oracle.codebook(oracle.histogram(xa))
+    Lb, Cb = oracle.codebook(oracle.histogram(xb))
+    dcb = hc.DeviceCodebook(hc.hc_build_codebook(oracle.histogram(xa)))
+    enc_a = hc.compress(dev(xa), 4096, codebook=dcb, check=False)
+    dcb.update(hc.hc_build_codebook(oracle.histogram(xb)))
+    enc_b = hc.compress(dev(xb), 4096, codebook=dcb)
+    assert np.array_equal(enc_a.stream.cpu().numpy(), oracle.encode(xa, 4096, La, Ca)[0])
+    assert np.array_equal(enc_b.stream.cpu().numpy(), oracle.encode(xb, 4096, Lb, Cb)[0])
+    assert torch.equal(hc.decompress(enc_b), dev(xb))
+    for _ in range(3):  # repeated updates reuse the staging area
+        dcb.update(hc.hc_build_codebook(oracle.histogram(xa)))
+        dcb.update(hc.hc_build_codebook(oracle.histogram(xb)))
+    enc_b2 = hc.compress(dev(xb), 4096, codebook=dcb)
+    assert torch.equal(enc_b2.stream, enc_b.stream)
+
+
+def test_walk_matches_encoder_offsets(hc, oracle):
+    x = synth.zipf_bytes(1_000_003, 1.1, 23)
+    enc = hc.compress(dev(x), 4096)
+    nb = hc.num_blocks(x.size, 4096)
+    off = torch.zeros(nb + 1, dtype=torch.int64, device="cuda")
+    err = hc.new_error_word("cuda")
+    hc.hc_walk_blocks(enc.stream, enc.nbytes, nb, off, err)
+    assert hc.read_error(err) == 0
+    assert torch.equal(off, enc.block_off)
+    assert np.array_equal(u64(off), oracle.walk(enc.stream.cpu().numpy(), nb))
+
+
+# ------------------------------------------------------------------ batches
+@pytest.mark.parametrize("B,S", [(4096, 0), (65536, 1024), (16384, 512)])
+def test_batch_matches_single_and_oracle(hc, oracle, B, S):
+    """Buffers of uneven sizes (empty and tiny included), each with its own
+    codebook, in one launch per step: every result equals the single-buffer
+    call and the oracle."""
+    rng = np.random.default_rng(B + S)
+    sizes = [0, 1, 17, 4096, 70_001, 333_333, 1 << 20, 5]
+    kinds = ["zipf", "uniform", "skewed", "fp32"]
+    xs = []
+    for k, n in enumerate(sizes):
+        kind = kinds[k % 4]
+        if kind == "zipf":
+            xs.append(synth.zipf_bytes(n, float(rng.uniform(0.8, 1.6)), k))
+        elif kind == "fp32":
+            xs.append(synth.fp32_bytes((n + 3) // 4 * 4, k)[:n])
+        else:
+            xs.append(synth.segment_bytes(kind, n, k))
+    xd = [dev(x) for x in xs]
+    cnt = len(xs)
+    items = hc.make_items(cnt)
+    hists = [torch.empty(256, dtype=torch.int64, device="cuda") for _ in xs]
+    for k in range(cnt):
+        hc.set_item(items, k, x=xd[k], hist=hists[k])
+    ws = torch.empty(max(hc.hc_batch_workspace_bytes(items, B), 256), dtype=torch.uint8, device="cuda")
+    hc.hc_histogram_batch(items, ws)
+    dcbs, outs, offs, subs = [], [], [], []
+    for k in range(cnt):
+        h = u64(hists[k])
+        assert np.array_equal(h, oracle.histogram(xs[k])), k
+        cb = hc.hc_build_codebook(h)
+        if cb.max_len == 0:
+            L0 = np.zeros(256, np.uint8)
+            L0[0] = 1
+            cb = hc.hc_codebook_from_lengths(L0)
+        dcbs.append(hc.DeviceCodebook(cb))
+        n = xs[k].size
+        outs.append(torch.empty(max(hc.hc_encode_bound(n, B, cb.max_len), 16), dtype=torch.uint8, device="cuda"))
+        offs.append(torch.empty(hc.num_blocks(n, B) + 1, dtype=torch.int64, device="cuda"))
+        subs.append(torch.empty(max(hc.hc_sub_index_entries(n, B, S), 1), dtype=torch.int32, device="cuda")
+                    if S else None)
+        hc.set_item(items, k, x=xd[k], dcb=dcbs[k], out=outs[k], block_off=offs[k], sub_idx=subs[k])
+    ws = torch.empty(max(hc.hc_batch_workspace_bytes(items, B), 256), dtype=torch.uint8, device="cuda")
+    err = hc.new_error_word("cuda")
+    hc.hc_encode_batch(items, B, S, ws, err)
+    assert hc.read_error(err) == 0
+    ys = []
+    for k in range(cnt):
+        n = xs[k].size
+        C = int(offs[k][-1].item())
+        single = hc.compress(xd[k], B, sub_block=S, codebook=dcbs[k])
+        assert torch.equal(outs[k][:C], single.stream), k
+        assert torch.equal(offs[k], single.block_off), k
+        if S:
+            m = hc.hc_sub_index_entries(n, B, S)
+            assert torch.equal(subs[k][:m], single.sub_idx[:m]), k
+        if n:
+            L = dcbs[k].host.lengths
+            s_or, off_or, _ = oracle.encode(xs[k], B, L, oracle.canonical_codes(L))
+            assert np.array_equal(outs[k][:C].cpu().numpy(), s_or), k
+        ys.append(torch.empty(max(n, 16), dtype=torch.uint8, device="cuda"))
+        hc.set_item(items, k, x=outs[k], n=n, in_bytes=C, dcb=dcbs[k], out=ys[k], block_off=offs[k], sub_idx=subs[k])
+    hc.hc_decode_batch(items, B, S, ws, err)
+    assert hc.read_error(err) == 0
+    for k in range(cnt):
+        assert torch.equal(ys[k][: xs[k].size], xd[k]), k
