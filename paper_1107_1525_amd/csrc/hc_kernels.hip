@@ -646,12 +646,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 
 // ---------------------------------------------------------------- decode, codes of <= 24 bits
 // Same lane mapping and checks as k_decode, but the lane's payload words reach
-// its bit buffer through a private ring of 32 words in LDS (two halves of 16).
+// its bit buffer through a private ring of 16 words in LDS (two halves of 8).
 // The ring is filled with 16-byte loads; the half after the ring is loaded into
 // registers one round ahead and written into the ring when the lane has moved
 // past a half, so no symbol waits on a global load.  A round decodes R symbols
-// (R * max_len <= 15 words), the ring always holds what a round can consume.
-constexpr uint32_t kRingHalf = 16;
+// with R * max_len <= 8 words (one half), so the ring always holds what a round
+// can consume.
+constexpr uint32_t kRingHalf = 8;
 constexpr uint32_t kRingWords = 2 * kRingHalf;
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
 
@@ -666,7 +667,7 @@ __device__ __forceinline__ uint4 load_quad(const uint32_t *__restrict__ in32, ui
     return r;
 }
 
-template <uint32_t R>
+template <uint32_t R>  // 8 or 16
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
                                                              uint32_t *err)
 {
@@ -819,10 +820,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             }
         }
         if (m == R) {
-#pragma unroll
-            for (uint32_t q = 0; q < R / 16; ++q)
-                *reinterpret_cast<uint4 *>(dst + k + 16 * q) =
-                    make_uint4(o4[4 * q], o4[4 * q + 1], o4[4 * q + 2], o4[4 * q + 3]);
+            if (R == 16)
+                *reinterpret_cast<uint4 *>(dst + k) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+            else
+                *reinterpret_cast<uint2 *>(dst + k) = make_uint2(o4[0], o4[1]);
         } else {
 #pragma unroll
             for (uint32_t q = 0; q < R; ++q)
@@ -890,10 +891,10 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     const uint32_t S_eff = with_index ? S : B;
     const uint32_t cpb = with_index ? (B + S - 1) / S : 1;
     const dim3 grid((uint32_t)groups);
-    if (max_len <= 15)
-        k_decode_ring<32><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
-    else if (max_len <= (uint32_t)kPackedMaxLen)
+    if (max_len <= 16)  // a round of 16 symbols uses at most 8 words
         k_decode_ring<16><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+    else if (max_len <= (uint32_t)kPackedMaxLen)  // 8 symbols, at most 6 words
+        k_decode_ring<8><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     else
         k_decode<<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     return hipGetLastError();
