@@ -292,6 +292,7 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     __shared__ uint32_t s_len[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_scan[kTileThreads / 64];
     __shared__ uint32_t s_lead, s_bits;
+    __shared__ uint32_t s_next[32];  // the first symbols of the next tile of the block
     __shared__ uint64_t s_tile, s_P, s_O;
     __shared__ Job s_job;
 
@@ -319,12 +320,14 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     const uint64_t t = s_tile;
     const Tile tl = tile_of(s_job.n, B, tpb, t - s_job.unit_begin);
     if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
-    const bool last_tile = tl.te == tl.cnt;
 
+    const bool last_tile = tl.te == tl.cnt;
+    const uint32_t avail = last_tile ? 0u : (tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32u);
+    if (tid < 32) s_next[tid] = tid < avail ? in[tl.blk_start + tl.te + tid] : 0u;
     const uint32_t s = tl.ts + kSymPerThread * tid;
     uint32_t w[4];
     const uint32_t m = load16(in, tl, s, w);
-    __syncthreads();  // code tables are in LDS
+    __syncthreads();  // code tables and the next tile's first symbols are in LDS
     uint32_t bits = 0;
     bool absent = false;
 #pragma unroll
@@ -367,33 +370,34 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
         if (nacc) atomicOr(&words[widx], (uint32_t)(acc << (32 - nacc)));
     }
 
-    if (tid == 64) {
-        // The first 32 bits of the next tile of the block (zero past the block's
-        // end): they complete this tile's last stream word.
+    // The first 32 bits of the next tile of the block (zero past the block's
+    // end): they complete this tile's last stream word.
+    if (kPacked) {
+        if (tid >= 64 && tid < 128) {  // wave 1: one symbol per lane, placed by a scan of lengths
+            const uint32_t l = tid - 64;
+            const uint32_t e = (l < avail) ? s_packed[s_next[l]] : 0u;
+            const uint32_t L = e & 255u;
+            const uint32_t pos = wave_inclusive_scan(L) - L;
+            // L <= 24: the code fits the 64-bit window when it starts in the first 32 bits
+            uint64_t v = (L && pos < 32) ? ((uint64_t)(e >> 8) << (64 - pos - L)) : 0ull;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
+            if (l == 0) s_lead = (uint32_t)(v >> 32);
+        }
+    } else if (tid == 64) {
         uint64_t lead = 0;
         uint32_t got = 0;
-        if (!last_tile) {
-            const uint32_t avail = tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32;
-            const uint8_t *src = in + tl.blk_start + tl.te;
-            for (uint32_t k = 0; k < avail && got < 32; ++k) {
-                const uint32_t v = src[k];
-                uint32_t L;
-                uint64_t c;
-                if (kPacked) {
-                    L = s_packed[v] & 255u;
-                    c = s_packed[v] >> 8;
-                } else {
-                    L = s_len[v];
-                    c = s_code[v];
-                }
-                const uint32_t r = 32 - got;
-                if (L >= r) {
-                    lead = (lead << r) | (c >> (L - r));
-                    got = 32;
-                } else {
-                    lead = (lead << L) | c;
-                    got += L;
-                }
+        for (uint32_t k = 0; k < avail && got < 32; ++k) {
+            const uint32_t v = s_next[k];
+            const uint32_t L = s_len[v];
+            const uint64_t c = s_code[v];
+            const uint32_t r = 32 - got;
+            if (L >= r) {
+                lead = (lead << r) | (c >> (L - r));
+                got = 32;
+            } else {
+                lead = (lead << L) | c;
+                got += L;
             }
         }
         s_lead = (uint32_t)(lead << (32 - got));
