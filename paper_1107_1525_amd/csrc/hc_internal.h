@@ -10,8 +10,11 @@ namespace hc {
 constexpr int kNumSym = 256;
 constexpr int kMaxLen = 64;
 constexpr int kLutBits = 12;  // first-level decode table: 4096 entries
-constexpr uint16_t kLutLong = 0;         // the 12-bit prefix starts a longer code
-constexpr uint16_t kLutInvalid = 0xFFFF; // the prefix starts no code
+// Decode table entry: (len << 8) | symbol for a code of len <= lut_bits bits;
+// kLutLong if the prefix starts a longer code; kLutInvalid (bit 15, length 1)
+// if no code starts with it.
+constexpr uint16_t kLutLong = 0;
+constexpr uint16_t kLutInvalid = 0x8100;
 constexpr int kPackedMaxLen = 24;        // codes up to 24 bits fit (code << 8 | len) in a u32
 
 // Device-resident tables of one codebook (one contiguous allocation).

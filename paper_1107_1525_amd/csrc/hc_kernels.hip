@@ -16,6 +16,14 @@
 #include "hc_internal.h"
 #include "hc_kernels.h"
 
+// Global address space.  Buffer pointers read from a job descriptor are
+// otherwise generic, and generic (flat) loads also count against the LDS wait
+// counter, which would make every LDS wait also wait for in-flight HBM loads.
+#define HC_G __attribute__((address_space(1)))
+
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte global loads/stores
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
 namespace hc {
 
 // ---------------------------------------------------------------- helpers
@@ -109,13 +117,13 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(JobList jl, uint64_t chun
     for (int k = threadIdx.x; k < kNumSym * 64; k += kHistThreads) sh[k] = 0;
     __syncthreads();
 
-    const uint8_t *__restrict__ in = s_job.in;
+    const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
     const uint64_t n = s_job.n;
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t beg = (blockIdx.x - s_job.unit_begin) * chunk;
     const uint64_t end = beg + chunk < n ? beg + chunk : n;
     const uint64_t nvec = (end - beg) >> 4;
-    const uint4 *p = reinterpret_cast<const uint4 *>(in + beg);
+    const HC_G v4u *p = (const HC_G v4u *)(in + beg);
 
     auto add_word = [&](uint32_t w) {
         atomicAdd(&sh[((w)&255u) * 64 + lane], 1u);
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(JobList jl, uint64_t chun
         atomicAdd(&sh[((w >> 16) & 255u) * 64 + lane], 1u);
         atomicAdd(&sh[(w >> 24) * 64 + lane], 1u);
     };
-    auto add_vec = [&](uint4 q) {
+    auto add_vec = [&](v4u q) {
         add_word(q.x);
         add_word(q.y);
         add_word(q.z);
@@ -132,10 +140,10 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(JobList jl, uint64_t chun
 
     uint64_t v = threadIdx.x;
     for (; v + 3 * kHistThreads < nvec; v += 4 * kHistThreads) {
-        uint4 a = p[v];
-        uint4 b = p[v + kHistThreads];
-        uint4 c = p[v + 2 * kHistThreads];
-        uint4 d = p[v + 3 * kHistThreads];
+        v4u a = p[v];
+        v4u b = p[v + kHistThreads];
+        v4u c = p[v + 2 * kHistThreads];
+        v4u d = p[v + 3 * kHistThreads];
         add_vec(a);
         add_vec(b);
         add_vec(c);
@@ -183,14 +191,14 @@ __device__ __forceinline__ Tile tile_of(uint64_t n, uint32_t B, uint32_t tpb, ui
 }
 
 // Loads the (up to) 16 symbols of this thread; returns how many there are.
-__device__ __forceinline__ uint32_t load16(const uint8_t *__restrict__ in, const Tile &tl, uint32_t s,
+__device__ __forceinline__ uint32_t load16(const HC_G uint8_t *__restrict__ in, const Tile &tl, uint32_t s,
                                            uint32_t w[4])
 {
     w[0] = w[1] = w[2] = w[3] = 0;
     if (s >= tl.te) return 0;
-    const uint8_t *src = in + tl.blk_start + s;
+    const HC_G uint8_t *src = in + tl.blk_start + s;
     if (s + 16 <= tl.te) {
-        uint4 q = *reinterpret_cast<const uint4 *>(src);
+        v4u q = *(const HC_G v4u *)src;
         w[0] = q.x;
         w[1] = q.y;
         w[2] = q.z;
@@ -304,7 +312,7 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     }
     for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
     __syncthreads();
-    const DevTables *__restrict__ tb = s_job.tb;
+    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
     if (kPacked) {
         s_packed[tid] = tb->enc_packed[tid];
     } else {
@@ -312,9 +320,9 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
         s_len[tid] = tb->enc_len[tid];
     }
 
-    const uint8_t *__restrict__ in = s_job.in;
-    uint32_t *__restrict__ out32 = reinterpret_cast<uint32_t *>(s_job.out);
-    uint32_t *__restrict__ sub_idx = s_job.sub_idx;
+    const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
+    HC_G uint32_t *__restrict__ out32 = (HC_G uint32_t *)s_job.out;
+    HC_G uint32_t *__restrict__ sub_idx = (HC_G uint32_t *)s_job.sub_idx;
     uint64_t *bstate = bstate_all + s_job.block_begin;
     const uint64_t nb = num_blocks_dev(s_job.n, B);
     const uint64_t t = s_tile;
@@ -425,8 +433,9 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
             s_O = O;
             s_bits = (uint32_t)blk_bits;
             if (last_tile) {
-                s_job.block_off[tl.blk] = O;
-                if (tl.blk + 1 == nb) s_job.block_off[nb] = O + blk_bytes;
+                HC_G uint64_t *block_off = (HC_G uint64_t *)s_job.block_off;
+                block_off[tl.blk] = O;
+                if (tl.blk + 1 == nb) block_off[nb] = O + blk_bytes;
             }
         }
     }
@@ -434,7 +443,7 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
 
     const uint64_t P = s_P, O = s_O;
     const uint32_t a = (uint32_t)(P & 31);
-    uint32_t *payload = out32 + (O >> 2) + 1 + (P >> 5);
+    HC_G uint32_t *payload = out32 + (O >> 2) + 1 + (P >> 5);
     if (tile_total) {
         // stream word k of the tile holds tile bits [32k - a, 32k - a + 32); it is
         // written here if its first bit is this tile's (k >= 1 when a > 0)
@@ -481,14 +490,14 @@ __global__ void k_walk(const uint32_t *__restrict__ in32, uint64_t in_bytes, uin
 }
 
 // ---------------------------------------------------------------- decode
-__device__ __forceinline__ uint32_t ld_word(const uint32_t *__restrict__ payload, uint32_t nwords,
+__device__ __forceinline__ uint32_t ld_word(const HC_G uint32_t *__restrict__ payload, uint32_t nwords,
                                             uint32_t w)
 {
     return w < nwords ? payload[w] : 0u;
 }
 
 // 64 payload bits starting at bit p (bits past the payload read as 0).
-__device__ __forceinline__ uint64_t window64(const uint32_t *__restrict__ payload, uint32_t nwords,
+__device__ __forceinline__ uint64_t window64(const HC_G uint32_t *__restrict__ payload, uint32_t nwords,
                                              uint64_t p)
 {
     const uint32_t w = (uint32_t)(p >> 5), r = (uint32_t)(p & 31);
@@ -505,7 +514,7 @@ struct BitReader {
     uint32_t nbits;
     uint32_t wi;
 
-    __device__ __forceinline__ void seek(const uint32_t *payload, uint32_t nwords, uint64_t p)
+    __device__ __forceinline__ void seek(const HC_G uint32_t *payload, uint32_t nwords, uint64_t p)
     {
         wi = (uint32_t)(p >> 5);
         const uint32_t r = (uint32_t)(p & 31);
@@ -519,7 +528,7 @@ struct BitReader {
 // Decodes one symbol.  Fast path: the next lut_bits bits index the LDS table.
 // Codes longer than lut_bits are resolved by comparing the next 64 bits with
 // the canonical code range of every longer length.
-__device__ __forceinline__ uint32_t decode_one(BitReader &br, const uint32_t *__restrict__ payload,
+__device__ __forceinline__ uint32_t decode_one(BitReader &br, const HC_G uint32_t *__restrict__ payload,
                                                uint32_t nwords, const uint16_t *lut, uint32_t K,
                                                uint32_t max_len, const uint64_t *first,
                                                const uint32_t *count, const uint32_t *base,
@@ -531,15 +540,15 @@ __device__ __forceinline__ uint32_t decode_one(BitReader &br, const uint32_t *__
         br.wi += 1;
     }
     const uint32_t e = lut[br.buf >> (64 - K)];
-    const uint32_t L = e >> 8;
-    if (L != 0 && e != kLutInvalid) {
+    const uint32_t L = (e >> 8) & 0x7Fu;
+    if (e & 0x8000u) {  // no code starts with these bits
+        bad = true;
+        return 0;
+    }
+    if (L != 0) {
         br.buf <<= L;
         br.nbits -= L;
         return e & 255u;
-    }
-    if (e == kLutInvalid) {
-        bad = true;
-        return 0;
     }
     const uint64_t p = br.pos();
     const uint64_t W = window64(payload, nwords, p);
@@ -568,13 +577,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
     const uint32_t tid = threadIdx.x;
     if (tid == 0) s_job = job_at(jl, job_of_unit(jl, blockIdx.x));
     __syncthreads();
-    const DevTables *__restrict__ tb = s_job.tb;
-    const uint32_t *__restrict__ in32 = reinterpret_cast<const uint32_t *>(s_job.in);
+    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
+    const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)s_job.in;
     const uint64_t in_bytes = s_job.in_bytes, n = s_job.n;
     const uint64_t nb = num_blocks_dev(n, B);
-    const uint64_t *__restrict__ off = s_job.block_off;
-    const uint32_t *__restrict__ sub_idx = s_job.sub_idx;
-    uint8_t *__restrict__ out = s_job.out;
+    const HC_G uint64_t *__restrict__ off = (const HC_G uint64_t *)s_job.block_off;
+    const HC_G uint32_t *__restrict__ sub_idx = (const HC_G uint32_t *)s_job.sub_idx;
+    HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)s_job.out;
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
     for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
@@ -608,7 +617,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
         report(err, HC_ERR_CORRUPT);
         return;
     }
-    const uint32_t *payload = in32 + (o >> 2) + 1;
+    const HC_G uint32_t *payload = in32 + (o >> 2) + 1;
     const uint32_t nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
     uint64_t p0 = 0, p1 = hdr;
     if (sub_idx) {
@@ -623,7 +632,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
     BitReader br;
     br.seek(payload, nwords, p0);
     bool bad = false;
-    uint8_t *dst = out + blk_start;
+    HC_G uint8_t *dst = out + blk_start;
     uint32_t k = s0;
     for (; k + 16 <= s1 && !bad; k += 16) {
         uint32_t o4[4] = {0u, 0u, 0u, 0u};
@@ -633,7 +642,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
                                             s_base, s_sorted, bad);
             o4[q >> 2] |= sym << (8 * (q & 3));
         }
-        *reinterpret_cast<uint4 *>(dst + k) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+        *(HC_G v4u *)(dst + k) = v4u{o4[0], o4[1], o4[2], o4[3]};
     }
     for (; k < s1 && !bad; ++k)
         dst[k] = (uint8_t)decode_one(br, payload, nwords, s_lut, K, max_len, s_first, s_count, s_base,
@@ -660,18 +669,20 @@ constexpr uint32_t kRingHalf = 8;
 constexpr uint32_t kRingWords = 2 * kRingHalf;
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
 
-__device__ __forceinline__ uint4 load_quad(const uint32_t *__restrict__ in32, uint64_t q, uint64_t in_words)
+__device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32, uint64_t q, uint64_t in_words)
 {
     const uint64_t w = q * 4;
-    if (w + 4 <= in_words) return *reinterpret_cast<const uint4 *>(in32 + w);
-    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    if (w + 4 <= in_words) return *(const HC_G v4u *)(in32 + w);
+    v4u r = {0u, 0u, 0u, 0u};
     if (w + 0 < in_words) r.x = in32[w + 0];
     if (w + 1 < in_words) r.y = in32[w + 1];
     if (w + 2 < in_words) r.z = in32[w + 2];
     return r;
 }
 
-template <uint32_t R>  // 8 or 16
+// R symbols per round (8 or 16), SPR symbols between buffer refills
+// (SPR * max_len <= 32), kLong: codes may be longer than the table.
+template <uint32_t R, uint32_t SPR, bool kLong>
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
                                                              uint32_t *err)
 {
@@ -686,13 +697,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     const uint32_t tid = threadIdx.x;
     if (tid == 0) s_job = job_at(jl, job_of_unit(jl, blockIdx.x));
     __syncthreads();
-    const DevTables *__restrict__ tb = s_job.tb;
-    const uint32_t *__restrict__ in32 = reinterpret_cast<const uint32_t *>(s_job.in);
+    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
+    const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)s_job.in;
     const uint64_t in_bytes = s_job.in_bytes, n = s_job.n;
     const uint64_t nb = num_blocks_dev(n, B);
-    const uint64_t *__restrict__ off = s_job.block_off;
-    const uint32_t *__restrict__ sub_idx = s_job.sub_idx;
-    uint8_t *__restrict__ out = s_job.out;
+    const HC_G uint64_t *__restrict__ off = (const HC_G uint64_t *)s_job.block_off;
+    const HC_G uint32_t *__restrict__ sub_idx = (const HC_G uint32_t *)s_job.sub_idx;
+    HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)s_job.out;
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
     for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
@@ -746,14 +757,14 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     constexpr uint32_t kQuadsPerHalf = kRingHalf / 4;
 #pragma unroll
     for (uint32_t j = 0; j < 2 * kQuadsPerHalf; ++j) {
-        const uint4 v = load_quad(in32, h * kQuadsPerHalf + j, in_words);
+        const v4u v = load_quad(in32, h * kQuadsPerHalf + j, in_words);
         const uint32_t base = (uint32_t)((h * kRingHalf + 4 * j) & (kRingWords - 1));
         ring[base + 0] = v.x;
         ring[base + 1] = v.y;
         ring[base + 2] = v.z;
         ring[base + 3] = v.w;
     }
-    uint4 f[kQuadsPerHalf];  // in flight: stream words of half h + 2
+    v4u f[kQuadsPerHalf];  // in flight: stream words of half h + 2
 #pragma unroll
     for (uint32_t j = 0; j < kQuadsPerHalf; ++j) f[j] = load_quad(in32, (h + 2) * kQuadsPerHalf + j, in_words);
 
@@ -763,10 +774,49 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     uint64_t nxt = sw + 2;  // next stream word to enter the bit buffer
     uint32_t pre = ring[nxt & (kRingWords - 1)];
 
-    bool bad = false;
-    uint8_t *dst = out + blk_start + s0;
+    uint32_t bad = 0;  // bit 15: an invalid prefix was met
+    HC_G uint8_t *dst = out + blk_start + s0;
     const uint32_t nsym = s1 - s0;
-    for (uint32_t k = 0; k < nsym; k += R) {
+
+    // One symbol from the buffer (which holds >= max_len bits here).  Table
+    // entries of invalid prefixes carry bit 15 and length 1, so codes of at
+    // most lut_bits bits need no test; longer codes (kLong) take the
+    // canonical-range search on the buffered bits.
+    auto decode_sym = [&]() -> uint32_t {
+        const uint32_t e = s_lut[(uint32_t)(buf >> 32) >> (32 - K)];
+        uint32_t L = (e >> 8) & 0x7Fu;
+        uint32_t sym = e & 255u;
+        bad |= e;
+        if (kLong && L == 0) {
+            for (uint32_t l = K + 1; l <= max_len; ++l) {
+                const uint32_t cv = (uint32_t)(buf >> (64 - l));
+                const uint32_t d = cv - s_first[l];
+                if (d < s_count[l]) {
+                    L = l;
+                    sym = s_sorted[s_base[l] + d];
+                    break;
+                }
+            }
+            if (L == 0) {
+                bad |= 0x8000u;
+                L = 1;
+            }
+        }
+        buf <<= L;
+        nbits -= L;
+        return sym;
+    };
+    // Tops the buffer up to >= 32 bits with the prefetched next word, without
+    // a branch; the ring word after it is read for the next refill.
+    auto refill = [&]() {
+        const uint32_t need = nbits < 32 ? 1u : 0u;
+        const uint64_t add = (uint64_t)pre << ((32 - nbits) & 63u);
+        buf |= need ? add : 0ull;
+        nbits += need << 5;
+        nxt += need;
+        pre = ring[(uint32_t)nxt & (kRingWords - 1)];
+    };
+    auto advance_ring = [&]() {
         if (nxt >= kRingHalf * h + kRingHalf) {
             // the lane has left half h: its slots receive half h + 2
 #pragma unroll
@@ -782,60 +832,38 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             for (uint32_t j = 0; j < kQuadsPerHalf; ++j)
                 f[j] = load_quad(in32, (h + 2) * kQuadsPerHalf + j, in_words);
         }
+    };
+
+    uint32_t k = 0;
+    for (; k + R <= nsym; k += R) {  // full rounds: SPR symbols between refills
+        advance_ring();
         uint32_t o4[R / 4];
 #pragma unroll
         for (uint32_t q = 0; q < R / 4; ++q) o4[q] = 0;
-        const uint32_t m = (nsym - k < R) ? nsym - k : R;
+#pragma unroll
+        for (uint32_t q = 0; q < R; q += SPR) {
+#pragma unroll
+            for (uint32_t j = 0; j < SPR; ++j) o4[(q + j) >> 2] |= decode_sym() << (8 * ((q + j) & 3));
+            refill();
+        }
+        if (R == 16)
+            *(HC_G v4u *)(dst + k) = v4u{o4[0], o4[1], o4[2], o4[3]};
+        else
+            *(HC_G v2u *)(dst + k) = v2u{o4[0], o4[1]};
+    }
+    if (k < nsym) {  // the ragged last round: one symbol between refills
+        advance_ring();
+        const uint32_t m = nsym - k;
 #pragma unroll
         for (uint32_t q = 0; q < R; ++q) {
             if (q < m) {
-                const uint32_t e = s_lut[buf >> (64 - K)];
-                uint32_t L = e >> 8;
-                uint32_t sym = e & 255u;
-                if (L == 0 || e == kLutInvalid) {
-                    // longer than the table: canonical ranges on the (>= 32) buffered bits
-                    L = 0;
-                    if (e != kLutInvalid) {
-                        for (uint32_t l = K + 1; l <= max_len; ++l) {
-                            const uint32_t cv = (uint32_t)(buf >> (64 - l));
-                            const uint32_t d = cv - s_first[l];
-                            if (d < s_count[l]) {
-                                L = l;
-                                sym = s_sorted[s_base[l] + d];
-                                break;
-                            }
-                        }
-                    }
-                    if (L == 0) {
-                        bad = true;
-                        L = 1;
-                        sym = 0;
-                    }
-                }
-                buf <<= L;
-                nbits -= L;
-                if (nbits < 32) {
-                    buf |= (uint64_t)pre << (32 - nbits);
-                    nbits += 32;
-                    nxt += 1;
-                    pre = ring[nxt & (kRingWords - 1)];
-                }
-                o4[q >> 2] |= sym << (8 * (q & 3));
+                dst[k + q] = (uint8_t)decode_sym();
+                refill();
             }
-        }
-        if (m == R) {
-            if (R == 16)
-                *reinterpret_cast<uint4 *>(dst + k) = make_uint4(o4[0], o4[1], o4[2], o4[3]);
-            else
-                *reinterpret_cast<uint2 *>(dst + k) = make_uint2(o4[0], o4[1]);
-        } else {
-#pragma unroll
-            for (uint32_t q = 0; q < R; ++q)
-                if (q < m) dst[k + q] = (uint8_t)(o4[q >> 2] >> (8 * (q & 3)));
         }
     }
     const uint64_t pos = 32 * (nxt - pw0) - nbits;
-    if (bad || pos != p1) {
+    if ((bad & 0x8000u) || pos != p1) {
         report(err, HC_ERR_CORRUPT);
         return;
     }
@@ -895,10 +923,15 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     const uint32_t S_eff = with_index ? S : B;
     const uint32_t cpb = with_index ? (B + S - 1) / S : 1;
     const dim3 grid((uint32_t)groups);
-    if (max_len <= 16)  // a round of 16 symbols uses at most 8 words
-        k_decode_ring<16><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
-    else if (max_len <= (uint32_t)kPackedMaxLen)  // 8 symbols, at most 6 words
-        k_decode_ring<8><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+    // a round of 16 symbols of <= 16 bits fills at most one ring half (8 words)
+    if (max_len <= 8)
+        k_decode_ring<16, 4, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+    else if (max_len <= (uint32_t)kLutBits)
+        k_decode_ring<16, 2, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+    else if (max_len <= 16)
+        k_decode_ring<16, 2, true><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+    else if (max_len <= (uint32_t)kPackedMaxLen)  // 8 symbols of <= 24 bits: 6 words
+        k_decode_ring<8, 1, true><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     else
         k_decode<<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     return hipGetLastError();
