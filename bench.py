@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--traffic-summary", metavar="DIR",
+                    help="turn rocprofv3 --pmc runs in DIR/{fetch,write,copy_fetch,copy_write} into "
+                         "profiles/traffic_*.json (HBM bytes per launch of each codec kernel)")
     return ap.parse_args()
 
 
@@ -204,6 +207,54 @@ def load_traffic(kernel: str, B: int, S: int):
     return d.get("bytes_per_launch")
 
 
+def _pmc_per_kernel(root: str, counter: str):
+    """Mean counter value (KiB) per dispatch, by kernel, from rocprofv3 CSVs."""
+    import csv
+    import glob
+
+    vals = {}
+    for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            vals.setdefault(name, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in vals.items()}
+
+
+def traffic_summary(root: str, B: int, S: int):
+    """Per-launch HBM traffic of each codec kernel.  Each counter is scaled by
+    what it reads for a plain 1 GiB device copy (bytes known exactly)."""
+    copy_bytes = 1 << 30
+    fetch, write = _pmc_per_kernel(os.path.join(root, "fetch"), "FETCH_SIZE"), \
+        _pmc_per_kernel(os.path.join(root, "write"), "WRITE_SIZE")
+    cf = _pmc_per_kernel(os.path.join(root, "copy_fetch"), "FETCH_SIZE")
+    cw = _pmc_per_kernel(os.path.join(root, "copy_write"), "WRITE_SIZE")
+    copy_name = max(cf, key=cf.get)  # the 1 GiB copy dominates the probe
+    f_scale = copy_bytes / (cf[copy_name] * 1024.0)
+    w_scale = copy_bytes / (cw[copy_name] * 1024.0)
+    out = {}
+    for k in fetch:
+        short = k.split("::")[-1].split("<")[0]
+        if not short.startswith("k_"):
+            continue
+        rec = {
+            "kernel": k, "fetch_kib_per_dispatch": round(fetch[k], 1), "write_kib_per_dispatch": round(write.get(k, 0.0), 1),
+            "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+            "bytes_per_launch": int(fetch[k] * 1024 * f_scale + write.get(k, 0.0) * 1024 * w_scale),
+            "kernel_source_hash": kernel_source_hash(), "workload": WORKLOAD, "block_size": B, "sub_block": S,
+            "copy_kernel": copy_name, "copy_bytes": copy_bytes,
+        }
+        path = os.path.join(ROOT, "profiles", f"traffic_{short}_{WORKLOAD}_B{B}_S{S}.json")
+        if short in out:  # several instantiations: keep the busiest
+            if out[short]["bytes_per_launch"] >= rec["bytes_per_launch"]:
+                continue
+        out[short] = rec
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def copy_probe(torch):
     n = 1 << 30
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -238,6 +289,9 @@ def main():
     import paper_1107_1525_amd as hc
     import synth
 
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary, args.block, args.sub_block)
+        return
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(torch)

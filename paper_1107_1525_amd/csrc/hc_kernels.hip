@@ -288,7 +288,9 @@ __device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t
     }
 }
 
-template <bool kPacked>
+// kPacked: codes of <= 24 bits from the packed table, FPS codes between
+// accumulator flushes (FPS * max_len <= 32); otherwise codes up to 64 bits.
+template <bool kPacked, uint32_t FPS>
 __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B, uint32_t tpb,
                                                          uint64_t *tstate, uint64_t *bstate_all,
                                                          uint32_t *counter, uint32_t S, uint32_t cpb,
@@ -338,13 +340,18 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     __syncthreads();  // code tables and the next tile's first symbols are in LDS
     uint32_t bits = 0;
     bool absent = false;
+    uint32_t e[16];  // packed table entries (code << 8 | len) of this thread's symbols
 #pragma unroll
     for (uint32_t k = 0; k < 16; ++k) {
-        if (k < m) {
-            const uint32_t L = kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
-            absent |= (L == 0);
-            bits += L;
+        uint32_t L = 0;
+        if (kPacked) {
+            e[k] = (k < m) ? s_packed[sym_at(w, k)] : 0u;
+            L = e[k] & 255u;
+        } else if (k < m) {
+            L = s_len[sym_at(w, k)];
         }
+        absent |= (k < m) && (L == 0);
+        bits += L;
     }
     if (absent) report(err, HC_ERR_SYMBOL_ABSENT);
     uint32_t tile_total;
@@ -354,16 +361,32 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
 
     {  // pack at alignment 0
         uint32_t widx = q >> 5;
-        uint32_t nacc = q & 31u;
+        uint32_t nacc = q & 31u;  // leading zero bits keep the word aligned
         uint64_t acc = 0;
+        if (kPacked) {
+            // FPS codes of <= 32/FPS bits between flushes: the accumulator never
+            // exceeds 63 bits, and one flush retires at most one word.  Entries of
+            // missing symbols (m < 16) are 0 and add nothing.
 #pragma unroll
-        for (uint32_t k = 0; k < 16; ++k) {
-            if (k < m) {
-                const uint32_t v = sym_at(w, k);
-                if (kPacked) {
-                    const uint32_t e = s_packed[v];
-                    put_bits(acc, nacc, widx, e >> 8, e & 255u, words);
-                } else {
+            for (uint32_t k = 0; k < 16; k += FPS) {
+#pragma unroll
+                for (uint32_t j = 0; j < FPS; ++j) {
+                    const uint32_t L = e[k + j] & 255u;
+                    acc = (acc << L) | (e[k + j] >> 8);
+                    nacc += L;
+                }
+                const uint32_t need = nacc >= 32 ? 1u : 0u;
+                const uint32_t word = (uint32_t)(acc >> ((nacc - 32) & 63u));
+                atomicOr(&words[widx], need ? word : 0u);
+                nacc -= need << 5;
+                acc &= (1ull << nacc) - 1ull;
+                widx += need;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < 16; ++k) {
+                if (k < m) {
+                    const uint32_t v = sym_at(w, k);
                     const uint32_t L = s_len[v];
                     const uint64_t c = s_code[v];
                     if (L > 32) {
@@ -894,12 +917,17 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uin
     const uint32_t cpb = S ? (B + S - 1) / S : 1;
     uint32_t *counter = reinterpret_cast<uint32_t *>(state);
     uint64_t *tstate = state + 2, *bstate = state + 2 + tiles;
-    if (max_len <= (uint32_t)kPackedMaxLen)
-        k_encode<true><<<dim3((uint32_t)tiles), kTileThreads, lds_words * 4, s>>>(jl, B, tpb, tstate, bstate,
-                                                                                 counter, S, cpb, lds_words, err);
+    const dim3 grid((uint32_t)tiles);
+    const size_t lds = lds_words * 4;
+    if (max_len <= 8)
+        k_encode<true, 4><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, counter, S, cpb, lds_words, err);
+    else if (max_len <= 16)
+        k_encode<true, 2><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, counter, S, cpb, lds_words, err);
+    else if (max_len <= (uint32_t)kPackedMaxLen)
+        k_encode<true, 1><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, counter, S, cpb, lds_words, err);
     else
-        k_encode<false><<<dim3((uint32_t)tiles), kTileThreads, lds_words * 4, s>>>(jl, B, tpb, tstate, bstate,
-                                                                                  counter, S, cpb, lds_words, err);
+        k_encode<false, 1><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, counter, S, cpb, lds_words,
+                                                           err);
     return hipGetLastError();
 }
 
