@@ -15,6 +15,7 @@ constexpr int kHistTargetGroups = 512; // two 64 KiB-LDS groups per CU on 256 CU
 constexpr int kTileThreads = 256;      // encode work-group size (4 waves)
 constexpr int kSymPerThread = 16;      // one 16-byte load per thread
 constexpr uint32_t kTileSyms = kTileThreads * kSymPerThread;  // 4096 symbols per tile
+constexpr uint64_t kEncodeTargetGroups = 256 * 8 * 4;  // 256 CUs x 8 groups x 4 waves of groups
 
 constexpr int kDecThreads = 256;
 

@@ -290,10 +290,12 @@ __device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t
 
 // kPacked: codes of <= 24 bits from the packed table, FPS codes between
 // accumulator flushes (FPS * max_len <= 32); otherwise codes up to 64 bits.
+// Each work-group takes G consecutive tiles with one atomic and encodes them
+// in order (one counter update per G tiles instead of per tile).
 template <bool kPacked, uint32_t FPS>
-__global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B, uint32_t tpb,
-                                                         uint64_t *tstate, uint64_t *bstate_all,
-                                                         uint32_t *counter, uint32_t S, uint32_t cpb,
+__global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint64_t tiles, uint32_t G, uint32_t B,
+                                                         uint32_t tpb, uint64_t *tstate, uint64_t *bstate_all,
+                                                         uint64_t *counter, uint32_t S, uint32_t cpb,
                                                          uint32_t lds_words, uint32_t *err)
 {
     extern __shared__ uint32_t words[];  // the tile's code bits from bit 0, MSB first
@@ -301,25 +303,39 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     __shared__ uint64_t s_code[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_len[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_scan[kTileThreads / 64];
-    __shared__ uint32_t s_lead, s_bits;
+    __shared__ uint32_t s_lead, s_bits, s_reload;
     __shared__ uint32_t s_next[32];  // the first symbols of the next tile of the block
-    __shared__ uint64_t s_tile, s_P, s_O;
+    __shared__ uint64_t s_first, s_P, s_O, s_job_end;
     __shared__ Job s_job;
 
     const uint32_t tid = threadIdx.x;
     if (tid == 0) {
-        const uint64_t t = atomicAdd(counter, 1u);
-        s_tile = t;
-        s_job = job_at(jl, job_of_unit(jl, t));
+        s_first = atomicAdd(reinterpret_cast<unsigned long long *>(counter), (unsigned long long)G);
+        s_job_end = 0;
+    }
+    __syncthreads();
+    const uint64_t first = s_first;
+    for (uint32_t g = 0; g < G; ++g) {
+    const uint64_t t = first + g;
+    if (t >= tiles) break;  // uniform over the group
+    if (tid == 0) {
+        s_reload = 0;
+        if (t >= s_job_end || t < s_job.unit_begin) {
+            s_job = job_at(jl, job_of_unit(jl, t));
+            s_job_end = s_job.unit_begin + num_blocks_dev(s_job.n, B) * tpb;
+            s_reload = 1;
+        }
     }
     for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
-    if (kPacked) {
-        s_packed[tid] = tb->enc_packed[tid];
-    } else {
-        s_code[tid] = tb->enc_code[tid];
-        s_len[tid] = tb->enc_len[tid];
+    if (s_reload) {
+        if (kPacked) {
+            s_packed[tid] = tb->enc_packed[tid];
+        } else {
+            s_code[tid] = tb->enc_code[tid];
+            s_len[tid] = tb->enc_len[tid];
+        }
     }
 
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
@@ -327,9 +343,11 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     HC_G uint32_t *__restrict__ sub_idx = (HC_G uint32_t *)s_job.sub_idx;
     uint64_t *bstate = bstate_all + s_job.block_begin;
     const uint64_t nb = num_blocks_dev(s_job.n, B);
-    const uint64_t t = s_tile;
     const Tile tl = tile_of(s_job.n, B, tpb, t - s_job.unit_begin);
-    if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
+    if (tl.ts >= tl.te) {  // empty tile past a short last block (uniform over the group)
+        __syncthreads();   // every thread has read s_job before thread 0 moves on
+        continue;
+    }
 
     const bool last_tile = tl.te == tl.cnt;
     const uint32_t avail = last_tile ? 0u : (tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32u);
@@ -484,6 +502,8 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
         if (m > 0 && (s % S) == 0) sub_idx[tl.blk * cpb + s / S] = (uint32_t)P + q;
         if (last_tile && tid == 0)
             for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = s_bits;
+    }
+    __syncthreads();  // the next tile reuses the LDS words and broadcasts
     }
 }
 
@@ -915,19 +935,27 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uin
     const uint32_t tpb = tiles_per_block(B);
     const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * max_len + 31ull) / 32ull + 2);
     const uint32_t cpb = S ? (B + S - 1) / S : 1;
-    uint32_t *counter = reinterpret_cast<uint32_t *>(state);
+    uint64_t *counter = state;
     uint64_t *tstate = state + 2, *bstate = state + 2 + tiles;
-    const dim3 grid((uint32_t)tiles);
+    // tiles per work-group: enough groups to fill the GPU several times over
+    uint64_t G = tiles / (uint64_t)kEncodeTargetGroups;
+    if (G < 1) G = 1;
+    if (G > 16) G = 16;
+    const dim3 grid((uint32_t)((tiles + G - 1) / G));
     const size_t lds = lds_words * 4;
+    const uint32_t g32 = (uint32_t)G;
     if (max_len <= 8)
-        k_encode<true, 4><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, counter, S, cpb, lds_words, err);
+        k_encode<true, 4><<<grid, kTileThreads, lds, s>>>(jl, tiles, g32, B, tpb, tstate, bstate, counter, S, cpb,
+                                                          lds_words, err);
     else if (max_len <= 16)
-        k_encode<true, 2><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, counter, S, cpb, lds_words, err);
+        k_encode<true, 2><<<grid, kTileThreads, lds, s>>>(jl, tiles, g32, B, tpb, tstate, bstate, counter, S, cpb,
+                                                          lds_words, err);
     else if (max_len <= (uint32_t)kPackedMaxLen)
-        k_encode<true, 1><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, counter, S, cpb, lds_words, err);
+        k_encode<true, 1><<<grid, kTileThreads, lds, s>>>(jl, tiles, g32, B, tpb, tstate, bstate, counter, S, cpb,
+                                                          lds_words, err);
     else
-        k_encode<false, 1><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, counter, S, cpb, lds_words,
-                                                           err);
+        k_encode<false, 1><<<grid, kTileThreads, lds, s>>>(jl, tiles, g32, B, tpb, tstate, bstate, counter, S, cpb,
+                                                           lds_words, err);
     return hipGetLastError();
 }
 
