@@ -67,7 +67,9 @@ typedef enum {
     HC_ERR_SYMBOL_ABSENT = 4,  /* the input holds a symbol the codebook has no code for */
     HC_ERR_BLOCK_OVERFLOW = 5, /* a block's bit count does not fit the 4-byte header */
     HC_ERR_CORRUPT = 6,        /* the compressed stream is not a valid encoding */
-    HC_ERR_CODE_TOO_LONG = 7   /* a Huffman code would be longer than 64 bits */
+    HC_ERR_CODE_TOO_LONG = 7,  /* a Huffman code would be longer than 64 bits */
+    HC_ERR_TIMEOUT = 8         /* a bounded wait of a kernel expired (an earlier work-group of the
+                                  encoder never published its size); the outputs are invalid */
 } hc_status;
 
 /* Host description of a code: lengths and canonical code values.
@@ -250,7 +252,7 @@ hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, u
 /* launch: tiles of all items are packed by the same kernel; each item's   */
 /* offsets start at 0 in its own stream.                                   */
 /* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: SYMBOL_ABSENT,   */
-/* BLOCK_OVERFLOW.                                                          */
+/* BLOCK_OVERFLOW, TIMEOUT.                                                 */
 hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 

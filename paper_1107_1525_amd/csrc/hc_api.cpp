@@ -35,6 +35,7 @@ extern "C" const char *hc_status_str(int status)
     case HC_ERR_BLOCK_OVERFLOW: return "HC_ERR_BLOCK_OVERFLOW";
     case HC_ERR_CORRUPT: return "HC_ERR_CORRUPT";
     case HC_ERR_CODE_TOO_LONG: return "HC_ERR_CODE_TOO_LONG";
+    case HC_ERR_TIMEOUT: return "HC_ERR_TIMEOUT";
     default: return "HC_ERR_UNKNOWN";
     }
 }
@@ -153,6 +154,7 @@ JobList single(const Job &j)
 {
     JobList jl;
     jl.jobs = nullptr;
+    jl.starts = nullptr;
     jl.count = 1;
     jl.one = j;
     return jl;
@@ -194,13 +196,29 @@ hc_status check_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, hc_cb_h
     return HC_OK;
 }
 
-// Copies a job list into the head of the caller's workspace.
-hc_status upload_jobs(const std::vector<Job> &jobs, void *ws, hipStream_t s, JobList *jl)
+// Bytes at the head of a batch workspace: the job table, then the start unit
+// of every job and the total.
+uint64_t job_table_bytes(uint32_t count)
 {
-    if (hipMemcpyAsync(ws, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice, s) != hipSuccess)
-        return HC_ERR_HIP;
+    return align256((uint64_t)count * sizeof(Job)) + align256(8 * ((uint64_t)count + 1));
+}
+
+// Copies a job list (and the table of job start units) into the head of the
+// caller's workspace.
+hc_status upload_jobs(std::vector<Job> &jobs, uint64_t total_units, void *ws, hipStream_t s, JobList *jl)
+{
+    const uint64_t count = jobs.size();
+    // one staging buffer: jobs, pad, starts; copied in a single transfer
+    const uint64_t head = job_table_bytes((uint32_t)count);
+    std::vector<char> stage(head, 0);
+    memcpy(stage.data(), jobs.data(), count * sizeof(Job));
+    uint64_t *starts = reinterpret_cast<uint64_t *>(stage.data() + align256(count * sizeof(Job)));
+    for (uint64_t k = 0; k < count; ++k) starts[k] = jobs[k].unit_begin;
+    starts[count] = total_units;
+    if (hipMemcpyAsync(ws, stage.data(), head, hipMemcpyHostToDevice, s) != hipSuccess) return HC_ERR_HIP;
     jl->jobs = static_cast<const Job *>(ws);
-    jl->count = (uint32_t)jobs.size();
+    jl->starts = reinterpret_cast<const uint64_t *>(static_cast<char *>(ws) + align256(count * sizeof(Job)));
+    jl->count = (uint32_t)count;
     jl->one = empty_job();
     return HC_OK;
 }
@@ -286,14 +304,14 @@ extern "C" uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t coun
         blocks += nb;
         tiles += nb * tiles_per_block(block_size);
     }
-    return align256((uint64_t)count * sizeof(Job)) + 8 * encode_state_words(tiles, blocks);
+    return job_table_bytes(count) + 8 * encode_state_words(tiles, blocks);
 }
 
 extern "C" hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes,
                                         void *stream)
 {
     if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
-    if (ws_bytes < align256((uint64_t)count * sizeof(Job))) return HC_ERR_NO_SPACE;
+    if (ws_bytes < job_table_bytes(count)) return HC_ERR_NO_SPACE;
     uint64_t total = 0;
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
@@ -316,7 +334,7 @@ extern "C" hc_status hc_histogram_batch(const hc_item *items, uint32_t count, vo
     if (units > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     JobList jl;
-    hc_status st = upload_jobs(jobs, d_ws, s, &jl);
+    hc_status st = upload_jobs(jobs, units, d_ws, s, &jl);
     if (st != HC_OK) return st;
     return hip_status(launch_histogram(jl, units, chunk, s));
 }
@@ -351,11 +369,11 @@ extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint3
         jobs[k] = j;
     }
     if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
-    const uint64_t head = align256((uint64_t)count * sizeof(Job));
+    const uint64_t head = job_table_bytes(count);
     if (ws_bytes < head + 8 * encode_state_words(tiles, blocks)) return HC_ERR_NO_SPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     JobList jl;
-    hc_status st = upload_jobs(jobs, d_ws, s, &jl);
+    hc_status st = upload_jobs(jobs, tiles, d_ws, s, &jl);
     if (st != HC_OK) return st;
     for (uint32_t k = 0; k < count; ++k)
         if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
@@ -368,7 +386,7 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
 {
     if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
-    if (ws_bytes < align256((uint64_t)count * sizeof(Job))) return HC_ERR_NO_SPACE;
+    if (ws_bytes < job_table_bytes(count)) return HC_ERR_NO_SPACE;
     std::vector<Job> jobs(count);
     uint64_t groups = 0;
     uint32_t max_len = 1;
@@ -392,7 +410,7 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
     if (groups > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     JobList jl;
-    hc_status st = upload_jobs(jobs, d_ws, s, &jl);
+    hc_status st = upload_jobs(jobs, groups, d_ws, s, &jl);
     if (st != HC_OK) return st;
     return hip_status(launch_decode(jl, groups, block_size, max_len, sub_block, sub_block != 0, d_err, s));
 }

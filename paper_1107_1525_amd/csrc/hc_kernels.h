@@ -15,7 +15,10 @@ constexpr int kHistTargetGroups = 512; // two 64 KiB-LDS groups per CU on 256 CU
 constexpr int kTileThreads = 256;      // encode work-group size (4 waves)
 constexpr int kSymPerThread = 16;      // one 16-byte load per thread
 constexpr uint32_t kTileSyms = kTileThreads * kSymPerThread;  // 4096 symbols per tile
-constexpr uint64_t kEncodeTargetGroups = 256 * 8 * 4;  // 256 CUs x 8 groups x 4 waves of groups
+// Bound on the look-back waits of the encoder (iterations of a short sleep,
+// about a second): a wait that long means a predecessor never ran, which is
+// reported as HC_ERR_TIMEOUT instead of hanging the device.
+constexpr uint32_t kLookbackSpinLimit = 1u << 20;
 
 constexpr int kDecThreads = 256;
 
@@ -37,7 +40,8 @@ struct Job {
 
 // The jobs of a launch: a device array, or a single job passed by value.
 struct JobList {
-    const Job *jobs;  // device array of 'count' jobs, or null when count == 1
+    const Job *jobs;         // device array of 'count' jobs, or null when count == 1
+    const uint64_t *starts;  // device array: unit_begin of every job, then the total
     uint32_t count;
     Job one;
 };

@@ -81,15 +81,22 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t count, uint64_t value)
         p[i] = value;
 }
 
-// The job owning launch unit u (the last job whose unit_begin <= u).
-__device__ __forceinline__ uint32_t job_of_unit(const JobList &jl, uint64_t u)
+// The job owning launch unit u (the last job whose unit_begin <= u), found by
+// the 64 lanes of one wave together: each round samples 64 job starts and
+// keeps the bracket of the last one <= u, so 10^4 jobs take 3 rounds of one
+// coalesced load.  Called by every lane of the wave; all lanes return it.
+__device__ uint32_t wave_job_of_unit(const JobList &jl, uint64_t u)
 {
     if (jl.count == 1) return 0;
-    uint32_t lo = 0, hi = jl.count;
+    const uint32_t lane = threadIdx.x & 63;
+    const HC_G uint64_t *starts = (const HC_G uint64_t *)jl.starts;
+    uint32_t lo = 0, hi = jl.count;  // starts[lo] <= u always holds
     while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (jl.jobs[mid].unit_begin <= u) lo = mid;
-        else hi = mid;
+        const uint32_t stride = (hi - lo + 63) / 64;
+        const uint32_t k = lo + lane * stride;
+        const uint64_t le = __ballot(k < hi && starts[k] <= u);
+        lo += (63 - (uint32_t)__clzll((long long)le)) * stride;
+        hi = lo + stride < hi ? lo + stride : hi;
     }
     return lo;
 }
@@ -113,7 +120,10 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(JobList jl, uint64_t chun
 {
     __shared__ uint32_t sh[kNumSym * 64];
     __shared__ Job s_job;
-    if (threadIdx.x == 0) s_job = job_at(jl, job_of_unit(jl, blockIdx.x));
+    if (threadIdx.x < 64) {
+        const uint32_t k = wave_job_of_unit(jl, blockIdx.x);
+        if (threadIdx.x == 0) s_job = job_at(jl, k);
+    }
     for (int k = threadIdx.x; k < kNumSym * 64; k += kHistThreads) sh[k] = 0;
     __syncthreads();
 
@@ -231,18 +241,21 @@ __device__ __forceinline__ void put_bits(uint64_t &acc, uint32_t &nacc, uint32_t
 }
 
 // ---------------------------------------------------------------- single-pass encode
-// One launch does the length pass, the offset scan and the packing.  Each
-// work-group takes the next tile in dispatch order (an atomic counter), packs
-// its code words into LDS at bit alignment 0, publishes its bit count, and
-// learns where its bits go through two decoupled look-backs:
+// One launch does the length pass, the offset scan and the packing.  Work-group
+// t encodes tile t: it packs its code words into LDS at bit alignment 0,
+// publishes its bit count, and learns where its bits go through two decoupled
+// look-backs:
 //   tile states  (per tile)  bits of the block before the tile,
 //   block states (per block) bytes of the stream before the block.
 // A state word holds a 2-bit flag and a 62-bit value: AGGREGATE = this
 // element's own total, PREFIX = the total through this element (from the
 // start of its segment).  The first tile of every block publishes PREFIX at
 // once, so every look-back ends.  The last tile of a block publishes the
-// block's size, then its offset.  Waves only wait for tiles taken earlier from
-// the counter, which are already running, so the launch always drains.
+// block's size, then its offset.  A group waits only for tiles with smaller
+// indices; work-groups are dispatched in index order on each XCD, so the
+// smallest unfinished tile is always running and the launch drains.  The
+// waits are bounded all the same: one that outlasts kLookbackSpinLimit
+// reports HC_ERR_TIMEOUT and the group finishes without hanging the device.
 constexpr uint64_t kStAgg = 1ull << 62;
 constexpr uint64_t kStPrefix = 2ull << 62;
 constexpr uint64_t kStValue = (1ull << 62) - 1;
@@ -259,12 +272,16 @@ __device__ __forceinline__ uint64_t st_peek(const uint64_t *p)
 
 // Called by all 64 lanes of one wave.  Returns the sum of the values of
 // elements [lo, idx) of a segment whose first element lo publishes PREFIX.
-__device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t lo)
+__device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t lo, uint32_t *err)
 {
     const uint32_t lane = threadIdx.x & 63;
     uint64_t acc = 0;
     uint64_t end = idx;  // the window covers elements end-1-lane
-    for (;;) {
+    for (uint32_t spins = 0;; ++spins) {
+        if (spins == kLookbackSpinLimit) {
+            report(err, HC_ERR_TIMEOUT);
+            return acc;
+        }
         const bool inside = end >= lo + 1 + lane;
         const uint64_t st = inside ? st_peek(&states[end - 1 - lane]) : kStPrefix;
         const uint64_t flag = st >> 62;
@@ -290,12 +307,9 @@ __device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t
 
 // kPacked: codes of <= 24 bits from the packed table, FPS codes between
 // accumulator flushes (FPS * max_len <= 32); otherwise codes up to 64 bits.
-// Each work-group takes G consecutive tiles with one atomic and encodes them
-// in order (one counter update per G tiles instead of per tile).
 template <bool kPacked, uint32_t FPS>
-__global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint64_t tiles, uint32_t G, uint32_t B,
-                                                         uint32_t tpb, uint64_t *tstate, uint64_t *bstate_all,
-                                                         uint64_t *counter, uint32_t S, uint32_t cpb,
+__global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B, uint32_t tpb, uint64_t *tstate,
+                                                         uint64_t *bstate_all, uint32_t S, uint32_t cpb,
                                                          uint32_t lds_words, uint32_t *err)
 {
     extern __shared__ uint32_t words[];  // the tile's code bits from bit 0, MSB first
@@ -303,39 +317,25 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint64_t ti
     __shared__ uint64_t s_code[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_len[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_scan[kTileThreads / 64];
-    __shared__ uint32_t s_lead, s_bits, s_reload;
+    __shared__ uint32_t s_lead, s_bits;
     __shared__ uint32_t s_next[32];  // the first symbols of the next tile of the block
-    __shared__ uint64_t s_first, s_P, s_O, s_job_end;
+    __shared__ uint64_t s_P, s_O;
     __shared__ Job s_job;
 
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) {
-        s_first = atomicAdd(reinterpret_cast<unsigned long long *>(counter), (unsigned long long)G);
-        s_job_end = 0;
-    }
-    __syncthreads();
-    const uint64_t first = s_first;
-    for (uint32_t g = 0; g < G; ++g) {
-    const uint64_t t = first + g;
-    if (t >= tiles) break;  // uniform over the group
-    if (tid == 0) {
-        s_reload = 0;
-        if (t >= s_job_end || t < s_job.unit_begin) {
-            s_job = job_at(jl, job_of_unit(jl, t));
-            s_job_end = s_job.unit_begin + num_blocks_dev(s_job.n, B) * tpb;
-            s_reload = 1;
-        }
+    const uint64_t t = blockIdx.x;
+    if (tid < 64) {
+        const uint32_t k = wave_job_of_unit(jl, t);
+        if (tid == 0) s_job = job_at(jl, k);
     }
     for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
-    if (s_reload) {
-        if (kPacked) {
-            s_packed[tid] = tb->enc_packed[tid];
-        } else {
-            s_code[tid] = tb->enc_code[tid];
-            s_len[tid] = tb->enc_len[tid];
-        }
+    if (kPacked) {
+        s_packed[tid] = tb->enc_packed[tid];
+    } else {
+        s_code[tid] = tb->enc_code[tid];
+        s_len[tid] = tb->enc_len[tid];
     }
 
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
@@ -344,10 +344,7 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint64_t ti
     uint64_t *bstate = bstate_all + s_job.block_begin;
     const uint64_t nb = num_blocks_dev(s_job.n, B);
     const Tile tl = tile_of(s_job.n, B, tpb, t - s_job.unit_begin);
-    if (tl.ts >= tl.te) {  // empty tile past a short last block (uniform over the group)
-        __syncthreads();   // every thread has read s_job before thread 0 moves on
-        continue;
-    }
+    if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
 
     const bool last_tile = tl.te == tl.cnt;
     const uint32_t avail = last_tile ? 0u : (tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32u);
@@ -455,7 +452,7 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint64_t ti
     if (tid < 64) {
         uint64_t P = 0;
         if (tl.j > 0) {
-            P = wave_lookback(tstate, t, t - tl.j);
+            P = wave_lookback(tstate, t, t - tl.j, err);
             if (tid == 0) st_publish(&tstate[t], kStPrefix, P + tile_total);
         }
         const uint64_t blk_bits = P + tile_total;
@@ -466,7 +463,7 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint64_t ti
         }
         uint64_t O = 0;
         if (tl.blk > 0) {
-            O = wave_lookback(bstate, tl.blk, 0);
+            O = wave_lookback(bstate, tl.blk, 0, err);
             if (last_tile && tid == 0) st_publish(&bstate[tl.blk], kStPrefix, O + blk_bytes);
         }
         if (tid == 0) {
@@ -502,8 +499,6 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint64_t ti
         if (m > 0 && (s % S) == 0) sub_idx[tl.blk * cpb + s / S] = (uint32_t)P + q;
         if (last_tile && tid == 0)
             for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = s_bits;
-    }
-    __syncthreads();  // the next tile reuses the LDS words and broadcasts
     }
 }
 
@@ -618,7 +613,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
     __shared__ Job s_job;
 
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_job = job_at(jl, job_of_unit(jl, blockIdx.x));
+    if (tid < 64) {
+        const uint32_t k = wave_job_of_unit(jl, blockIdx.x);
+        if (tid == 0) s_job = job_at(jl, k);
+    }
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
     const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)s_job.in;
@@ -738,7 +736,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     __shared__ Job s_job;
 
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_job = job_at(jl, job_of_unit(jl, blockIdx.x));
+    if (tid < 64) {
+        const uint32_t k = wave_job_of_unit(jl, blockIdx.x);
+        if (tid == 0) s_job = job_at(jl, k);
+    }
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
     const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)s_job.in;
@@ -935,27 +936,17 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uin
     const uint32_t tpb = tiles_per_block(B);
     const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * max_len + 31ull) / 32ull + 2);
     const uint32_t cpb = S ? (B + S - 1) / S : 1;
-    uint64_t *counter = state;
     uint64_t *tstate = state + 2, *bstate = state + 2 + tiles;
-    // tiles per work-group: enough groups to fill the GPU several times over
-    uint64_t G = tiles / (uint64_t)kEncodeTargetGroups;
-    if (G < 1) G = 1;
-    if (G > 16) G = 16;
-    const dim3 grid((uint32_t)((tiles + G - 1) / G));
+    const dim3 grid((uint32_t)tiles);
     const size_t lds = lds_words * 4;
-    const uint32_t g32 = (uint32_t)G;
     if (max_len <= 8)
-        k_encode<true, 4><<<grid, kTileThreads, lds, s>>>(jl, tiles, g32, B, tpb, tstate, bstate, counter, S, cpb,
-                                                          lds_words, err);
+        k_encode<true, 4><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err);
     else if (max_len <= 16)
-        k_encode<true, 2><<<grid, kTileThreads, lds, s>>>(jl, tiles, g32, B, tpb, tstate, bstate, counter, S, cpb,
-                                                          lds_words, err);
+        k_encode<true, 2><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err);
     else if (max_len <= (uint32_t)kPackedMaxLen)
-        k_encode<true, 1><<<grid, kTileThreads, lds, s>>>(jl, tiles, g32, B, tpb, tstate, bstate, counter, S, cpb,
-                                                          lds_words, err);
+        k_encode<true, 1><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err);
     else
-        k_encode<false, 1><<<grid, kTileThreads, lds, s>>>(jl, tiles, g32, B, tpb, tstate, bstate, counter, S, cpb,
-                                                           lds_words, err);
+        k_encode<false, 1><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err);
     return hipGetLastError();
 }
 
