@@ -51,6 +51,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--batched", type=int, default=0, metavar="N",
+                    help="also measure N independent buffers (log-uniform 1 KiB-64 MiB, Zipf s in [0.8,1.6]): "
+                         "one launch per phase vs one buffer per launch")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="also run the serving loop on N Poisson-arriving requests (50/50 compress/decompress, "
+                         "log-uniform 4 KiB-64 MiB, mixed data): aggregate GB/s and p50/p99 latency vs one "
+                         "request per launch")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="turn rocprofv3 --pmc runs in DIR/{fetch,write,copy_fetch,copy_write} into "
                          "profiles/traffic_*.json (HBM bytes per launch of each codec kernel)")
@@ -205,6 +212,141 @@ def load_traffic(kernel: str, B: int, S: int):
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def _loguniform_sizes(rng, count, lo, hi):
+    import numpy as np
+
+    return [int(v) for v in np.exp(rng.uniform(np.log(lo), np.log(hi), size=count))]
+
+
+def batched_bench(hc, synth, torch, np, count: int, B: int, S: int):
+    """Independent buffers with their own codebooks: one batched launch per
+    phase against one buffer per launch, same buffers, same results."""
+    rng = np.random.default_rng(synth.derive_seed(4, 0))
+    sizes = _loguniform_sizes(rng, count, 1 << 10, 64 << 20)
+    total = sum(sizes)
+    xs = []
+    for k, n in enumerate(sizes):
+        s_k = float(rng.uniform(0.8, 1.6))
+        xs.append(synth.zipf_bytes_torch(n, s_k, synth.derive_seed(4, k + 1)))
+    hist = torch.empty((count, 256), dtype=torch.int64, device="cuda")
+    items = hc.make_items(count)
+    for k, x in enumerate(xs):
+        hc.set_item(items, k, x=x, hist=hist[k])
+    hws = torch.empty(max(hc.hc_batch_workspace_bytes(items, B), 256), dtype=torch.uint8, device="cuda")
+    hc.hc_histogram_batch(items, hws)
+    h = hist.cpu().numpy().view(np.uint64)
+    dcbs = [hc.DeviceCodebook(hc.hc_build_codebook(h[k])) for k in range(count)]
+    outs = [torch.empty(hc.hc_encode_bound(n, B, d.max_len) + 256, dtype=torch.uint8, device="cuda")
+            for n, d in zip(sizes, dcbs)]
+    offs = [torch.empty(hc.num_blocks(n, B) + 1, dtype=torch.int64, device="cuda") for n in sizes]
+    subs = [torch.empty(max(hc.hc_sub_index_entries(n, B, S), 1), dtype=torch.int32, device="cuda") if S else None
+            for n in sizes]
+    ys = [torch.empty(n + 16, dtype=torch.uint8, device="cuda") for n in sizes]
+    enc_items = hc.make_items(count)
+    for k in range(count):
+        hc.set_item(enc_items, k, x=xs[k], dcb=dcbs[k], out=outs[k], block_off=offs[k], sub_idx=subs[k])
+    ws = torch.empty(hc.hc_batch_workspace_bytes(enc_items, B), dtype=torch.uint8, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    hc.hc_encode_batch(enc_items, B, S, ws, err)
+    C = [int(o[-1].item()) for o in offs]
+    dec_items = hc.make_items(count)
+    for k in range(count):
+        hc.set_item(dec_items, k, x=outs[k], n=sizes[k], in_bytes=C[k], dcb=dcbs[k], out=ys[k], block_off=offs[k],
+                    sub_idx=subs[k])
+    single_ws = torch.empty(max(hc.hc_encode_workspace_bytes(max(sizes), B), 16), dtype=torch.uint8, device="cuda")
+
+    def batched():
+        hc.hc_histogram_batch(items, hws)
+        hc.hc_encode_batch(enc_items, B, S, ws, err)
+        hc.hc_decode_batch(dec_items, B, S, ws, err)
+
+    def plain():
+        for k in range(count):
+            hc.hc_histogram(xs[k], out=hist[k])
+            hc.hc_encode_blocks(xs[k], B, dcbs[k], outs[k], offs[k], subs[k], S, single_ws, err)
+            hc.hc_decode_blocks(outs[k], C[k], sizes[k], B, dcbs[k], offs[k], subs[k], S, ys[k], err)
+
+    res = {}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        fn()
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / reps
+    if hc.read_error(err):
+        raise hc.HcError(hc.read_error(err), "batched bench")
+    for k in range(count):
+        assert torch.equal(ys[k][: sizes[k]], xs[k]), f"buffer {k}"
+    return {
+        "buffers": count, "bytes": total, "sizes": "log-uniform 1 KiB-64 MiB", "data": "Zipf s~U[0.8,1.6]",
+        "batched_GBps": round(total / res["batched"] / 1e9, 2), "plain_GBps": round(total / res["plain"] / 1e9, 2),
+        "batched_ms": round(res["batched"] * 1e3, 3), "plain_ms": round(res["plain"] * 1e3, 3),
+        "phases": "counts + encode + decode (codebooks fixed)",
+    }
+
+
+def serve_bench(hc, synth, torch, np, count: int, B: int, S: int):
+    """Poisson arrivals at a fixed offered load, 50/50 compress/decompress."""
+    from paper_1107_1525_amd.serve import Request, Server, percentile
+
+    rng = np.random.default_rng(synth.derive_seed(5, 0))
+    sizes = _loguniform_sizes(rng, count, 4 << 10, 64 << 20)
+    kinds = rng.random(count) < 0.5
+    data, encs = [], []
+    for k, n in enumerate(sizes):
+        n4 = (n + 3) // 4 * 4
+        x = synth.segment_bytes_torch(synth.mixed_kind(k), n4, synth.derive_seed(5, k + 1))[:n]
+        data.append(x)
+        encs.append(None if kinds[k] else hc.compress(x, B, sub_block=S))
+    torch.cuda.synchronize()
+    # plain replay: one request at a time, one launch per call
+    t0 = time.perf_counter()
+    lat_plain = []
+    for k in range(count):
+        a = time.perf_counter()
+        if kinds[k]:
+            hc.compress(data[k], B, sub_block=S)
+        else:
+            hc.decompress(encs[k])
+        torch.cuda.synchronize()
+        lat_plain.append(time.perf_counter() - a)
+    plain_s = time.perf_counter() - t0
+    total = sum(sizes)
+    plain_rate = total / plain_s
+    # served: arrivals at 80% of the plain form's throughput
+    rho = 0.8
+    gaps = rng.exponential(np.mean(sizes) / (rho * plain_rate), size=count)
+    srv = Server(block_size=B, sub_block=S, hbm_budget=32 << 30)
+    start = srv.clock() + 0.01
+    arr = start + np.cumsum(gaps)
+    reqs = []
+    for k in range(count):
+        if kinds[k]:
+            reqs.append(srv.submit(Request("compress", data=data[k], arrival=float(arr[k]))))
+        else:
+            reqs.append(srv.submit(Request("decompress", encoded=encs[k], arrival=float(arr[k]))))
+    srv.run_until_idle()
+    end = max(r.completed for r in reqs)
+    for k, r in enumerate(reqs):
+        if kinds[k]:
+            assert torch.equal(hc.decompress(r.result), data[k]), k
+        else:
+            assert torch.equal(r.result, data[k]), k
+    lat = [r.latency for r in reqs]
+    return {
+        "requests": count, "bytes": total, "offered_load": rho, "sizes": "log-uniform 4 KiB-64 MiB",
+        "served_GBps": round(total / (end - start) / 1e9, 2),
+        "p50_ms": round(percentile(lat, 50) * 1e3, 3), "p99_ms": round(percentile(lat, 99) * 1e3, 3),
+        "plain_GBps": round(plain_rate / 1e9, 2),
+        "plain_p50_ms": round(percentile(lat_plain, 50) * 1e3, 3),
+        "plain_p99_ms": round(percentile(lat_plain, 99) * 1e3, 3),
+        "iterations": srv.iterations, "max_inflight_requests": srv.max_inflight_requests,
+    }
 
 
 def _pmc_per_kernel(root: str, counter: str):
@@ -365,9 +507,17 @@ def main():
         if not args.no_cpu_baseline and not args.sweep:
             print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
             line["cpu_baseline"] = cpu_baseline(w, __import__("oracle"), np)
-        print(json.dumps(line), flush=True)
         del w
         torch.cuda.empty_cache()
+        if args.batched:
+            print(f"[bench] batched: {args.batched} buffers", file=sys.stderr, flush=True)
+            line["batched"] = batched_bench(hc, synth, torch, np, args.batched, B, S)
+            torch.cuda.empty_cache()
+        if args.serve:
+            print(f"[bench] serving: {args.serve} requests", file=sys.stderr, flush=True)
+            line["serving"] = serve_bench(hc, synth, torch, np, args.serve, B, S)
+            torch.cuda.empty_cache()
+        print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
