@@ -53,6 +53,9 @@ void build_dev_tables(const hc_codebook &cb, DevTables *t)
     t->nsym = cb.nsym;
     t->lut_bits = cb.max_len == 0 ? 1 : std::min<uint32_t>(cb.max_len, kLutBits);
     const uint32_t K = t->lut_bits;
+    t->fixed_len = cb.max_len;
+    for (int v = 0; v < kNumSym; ++v)
+        if (cb.len[v] && cb.len[v] != cb.max_len) t->fixed_len = 0;
 
     for (int v = 0; v < kNumSym; ++v) {
         t->enc_len[v] = cb.len[v];

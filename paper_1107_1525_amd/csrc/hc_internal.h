@@ -30,7 +30,7 @@ struct DevTables {
     uint32_t max_len;
     uint32_t nsym;
     uint32_t lut_bits;             // min(max_len, kLutBits), at least 1
-    uint32_t pad_;
+    uint32_t fixed_len;            // L if every code has length L, else 0
 };
 
 // Fills the device tables for a (validated) host codebook.

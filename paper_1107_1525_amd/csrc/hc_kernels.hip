@@ -750,7 +750,9 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)s_job.out;
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
-    for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
+    const bool fixed8 = tb->fixed_len == 8;  // uniform over the group: one job per group
+    if (!fixed8)
+        for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
     if (tid <= (uint32_t)kPackedMaxLen) {
         s_first[tid] = (uint32_t)tb->first[tid];
         s_count[tid] = tb->count[tid];
@@ -789,6 +791,46 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     }
     if (p0 > p1 || p1 > hdr) {
         report(err, HC_ERR_CORRUPT);
+        return;
+    }
+
+    if (fixed8) {
+        // Every code is 8 bits: symbol k of the block is byte 3 - (k & 3) of
+        // payload word k >> 2, so the chunk decodes word by word with
+        // independent table lookups.  The index, the header and the pad must
+        // agree with that layout.
+        if (p0 != 8ull * s0 || p1 != 8ull * s1 || hdr != 8ull * cnt) {
+            report(err, HC_ERR_CORRUPT);
+            return;
+        }
+        const HC_G uint32_t *src = in32 + (o >> 2) + 1 + (s0 >> 2);
+        HC_G uint8_t *dst8 = out + blk_start + s0;
+        const uint32_t nsym = s1 - s0;
+        const uint32_t ncode = s_count[8];
+        uint32_t bad8 = 0;
+        uint32_t k = 0;
+        for (; k + 16 <= nsym; k += 16) {
+            uint32_t o4[4];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) {
+                const uint32_t wd = src[(k >> 2) + q];
+                const uint32_t c0 = wd >> 24, c1 = (wd >> 16) & 255u, c2 = (wd >> 8) & 255u, c3 = wd & 255u;
+                bad8 |= (uint32_t)(c0 >= ncode) | (uint32_t)(c1 >= ncode) | (uint32_t)(c2 >= ncode) |
+                        (uint32_t)(c3 >= ncode);
+                o4[q] = s_sorted[c0 & 255u] | (s_sorted[c1] << 8) | (s_sorted[c2] << 16) | (s_sorted[c3] << 24);
+            }
+            *(HC_G v4u *)(dst8 + k) = v4u{o4[0], o4[1], o4[2], o4[3]};
+        }
+        for (; k < nsym; ++k) {
+            const uint32_t c = (src[k >> 2] >> (24 - 8 * (k & 3))) & 255u;
+            bad8 |= (uint32_t)(c >= ncode);
+            dst8[k] = (uint8_t)s_sorted[c];
+        }
+        if (s1 == cnt && (hdr & 31u)) {
+            const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
+            bad8 |= (in32[(o >> 2) + 1 + nwords - 1] & mask) ? 1u : 0u;
+        }
+        if (bad8) report(err, HC_ERR_CORRUPT);
         return;
     }
 

@@ -399,3 +399,26 @@ def test_batch_matches_single_and_oracle(hc, oracle, B, S):
     assert hc.read_error(err) == 0
     for k in range(cnt):
         assert torch.equal(ys[k][: xs[k].size], xd[k]), k
+
+
+def test_fixed_length_codes(hc, oracle):
+    """All codes 8 bits long (uniform bytes): the decoder's fixed-length path,
+    with and without the sub-block index, and its strict checks."""
+    x = synth.uniform_bytes(1_000_001, 31)
+    for B, S in ((4096, 0), (65536, 1024), (16384, 0)):
+        enc = check_full(hc, oracle, x, B, S, "fixed 8-bit codes")
+        assert enc.codebook.max_len == 8
+    # an incomplete 8-bit code: 200 symbols, bytes >= 200 have no code
+    L = np.zeros(256, np.uint8)
+    L[:200] = 8
+    cb = hc.DeviceCodebook(hc.hc_codebook_from_lengths(L))
+    y = (np.arange(50_000) % 200).astype(np.uint8)
+    enc = hc.compress(dev(y), 4096, codebook=cb)
+    assert torch.equal(hc.decompress(enc), dev(y))
+    s = enc.stream.cpu().numpy().copy()
+    s[4 + 3] = 0xFF  # first code of block 0 becomes 255
+    assert oracle.decode_status(s, y.size, 4096, L)[0] == oracle.ERR_CORRUPT
+    assert _decode_status(hc, s, enc, sub=False) == hc.HC_ERR_CORRUPT
+    s = enc.stream.cpu().numpy().copy()
+    s[0] ^= 8  # header no longer 8 bits per symbol
+    assert _decode_status(hc, s, enc, sub=False) == hc.HC_ERR_CORRUPT
