@@ -5,8 +5,8 @@ One step = the whole coding path over the 4 GiB mixed workload (64 segments of
 
   1. symbol counts of every segment            (hc_histogram_batch, one launch)
   2. read-back of the 64 histograms (16 KiB)
-  3. Huffman code + canonical codes per segment (hc_build_codebook, host)
-     and refresh of the device tables           (hc_codebook_update, async)
+  3. Huffman code + canonical codes of every segment and one refresh of the
+     resident device tables                     (hc_cbset_build, host + async copy)
   4. block encode of every segment: length pass, offset scan by look-back,
      bit packing                                (hc_encode_batch, one launch)
   5. block decode of every segment from the encoder's offsets and sub-block
@@ -100,10 +100,10 @@ class Workload:
         # codebooks of the data (fixed across steps) size the output buffers
         hc.hc_histogram_batch(self.hist_items, self.hist_ws)
         h = self.hist.cpu().numpy().view("uint64")
-        cbs = [hc.hc_build_codebook(h[t]) for t in range(nseg)]
-        self.dcb = [hc.DeviceCodebook(cb) for cb in cbs]
+        self.cbset = hc.CodebookSet(nseg)  # resident tables, rebuilt every step
+        self.dcb = self.cbset.build(h)
         self.nb = hc.num_blocks(self.seg, B)
-        self.cap = [(hc.hc_encode_bound(self.seg, B, cb.max_len) + 255) // 256 * 256 for cb in cbs]
+        self.cap = [(hc.hc_encode_bound(self.seg, B, d.max_len) + 255) // 256 * 256 for d in self.dcb]
         self.out_base = [0]
         for c in self.cap:
             self.out_base.append(self.out_base[-1] + c)
@@ -150,9 +150,7 @@ class Workload:
         mark("hist", 1)
         self.hist_host.copy_(self.hist, non_blocking=True)
         torch.cuda.current_stream().synchronize()
-        h = self.hist_host.numpy().view("uint64")
-        for t in range(self.nseg):
-            self.dcb[t].update(hc.hc_build_codebook(h[t]))
+        self.cbset.build(self.hist_host.numpy().view("uint64"))  # all codes, one table copy
         mark("enc", 0)
         hc.hc_encode_batch(self.enc_items, self.B, self.S, self.ws, self.err)
         mark("enc", 1)

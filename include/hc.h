@@ -138,6 +138,34 @@ hc_status hc_codebook_upload(const hc_codebook *cb, hc_cb_handle *out);
 /* Errors: INVALID_ARG (null pointer, inconsistent codebook), HIP.        */
 hc_status hc_codebook_update(hc_cb_handle h, const hc_codebook *cb, void *stream);
 
+/* A codebook set: 'count' device-resident code tables in one allocation, */
+/* rebuilt together from 'count' histograms with one asynchronous copy.   */
+/* For streams that get a new code every step (one per segment or        */
+/* buffer).  Owned by the library; the handles from hc_cbset_handle are   */
+/* valid until hc_cbset_destroy and must not be passed to                 */
+/* hc_codebook_update or hc_codebook_destroy (which ignores them).         */
+typedef struct hc_cbset_s *hc_cbset;
+
+/* Allocates a set of 'count' tables (device memory, pinned staging, an   */
+/* event); every table starts as the empty code.  Synchronous.            */
+/* Errors: INVALID_ARG (count 0, null pointer), HIP.                       */
+hc_status hc_cbset_create(uint32_t count, hc_cbset *out);
+
+/* Handle of table k of the set (NULL if k is out of range).              */
+hc_cb_handle hc_cbset_handle(hc_cbset set, uint32_t k);
+
+/* Builds code k from histogram k (h_hists: count x 256 u64, host) for     */
+/* every k, exactly as hc_build_codebook (an all-zero histogram gets the  */
+/* one-symbol code {0: 1 bit}), writes the codebooks to h_out (count, may */
+/* be NULL), and refreshes the device tables with one asynchronous copy   */
+/* on 'stream': work enqueued later on that stream sees the new tables.   */
+/* Waits (host side) for the set's previous copy before reusing the       */
+/* staging area.  Errors: INVALID_ARG, CODE_TOO_LONG, HIP.                 */
+hc_status hc_cbset_build(hc_cbset set, const uint64_t *h_hists, hc_codebook *h_out, void *stream);
+
+/* Frees a set (NULL is accepted).  Waits for the device to finish.       */
+hc_status hc_cbset_destroy(hc_cbset set);
+
 /* Frees a handle from hc_codebook_upload (NULL is accepted).  Waits for  */
 /* the device to finish work that may still read it.                      */
 hc_status hc_codebook_destroy(hc_cb_handle cb);

@@ -9,7 +9,8 @@ names of the C ABI in ``include/hc.h``:
     hc_codebook_upload, hc_codebook_update, hc_codebook_destroy, hc_encode_bound,
     hc_encode_workspace_bytes, hc_sub_index_entries, hc_encode_blocks,
     hc_walk_blocks, hc_decode_blocks, hc_status_str, hc_batch_workspace_bytes,
-    hc_histogram_batch, hc_encode_batch, hc_decode_batch
+    hc_histogram_batch, hc_encode_batch, hc_decode_batch, hc_cbset_create,
+    hc_cbset_handle, hc_cbset_build, hc_cbset_destroy (as CodebookSet)
 
 and add two conveniences, ``compress`` and ``decompress``, that chain them.
 u64 device buffers are held in int64 tensors and u32 ones in int32 tensors
@@ -97,6 +98,10 @@ _sigs = {
     "hc_codebook_upload": ([ctypes.POINTER(hc_codebook), ctypes.POINTER(_vp)], _st),
     "hc_codebook_update": ([_vp, ctypes.POINTER(hc_codebook), _vp], _st),
     "hc_codebook_destroy": ([_vp], _st),
+    "hc_cbset_create": ([_u32, ctypes.POINTER(_vp)], _st),
+    "hc_cbset_handle": ([_vp, _u32], _vp),
+    "hc_cbset_build": ([_vp, _vp, ctypes.POINTER(hc_codebook), _vp], _st),
+    "hc_cbset_destroy": ([_vp], _st),
     "hc_encode_bound": ([_u64, _u32, _u32], _u64),
     "hc_encode_workspace_bytes": ([_u64, _u32], _u64),
     "hc_sub_index_entries": ([_u64, _u32, _u32], _u64),
@@ -183,6 +188,52 @@ class DeviceCodebook:
         if self.handle:
             _check(_lib.hc_codebook_destroy(self.handle), "hc_codebook_destroy")
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _SetCodebook:
+    """Handle of one table of a CodebookSet; usable wherever a DeviceCodebook is."""
+
+    def __init__(self, owner, handle_value: int):
+        self._owner = owner  # keeps the set alive
+        self.handle = ctypes.c_void_p(handle_value)
+        self.host = hc_codebook()
+        self.max_len = 0
+
+
+class CodebookSet:
+    """Device-resident code tables for many buffers, rebuilt together from
+    their histograms with one copy (hc_cbset_*)."""
+
+    def __init__(self, count: int):
+        h = ctypes.c_void_p()
+        _check(_lib.hc_cbset_create(count, ctypes.byref(h)), "hc_cbset_create")
+        self._h = h
+        self.count = count
+        self.books = [_SetCodebook(self, _lib.hc_cbset_handle(h, k)) for k in range(count)]
+        self._out = (hc_codebook * count)()
+
+    def build(self, hists: np.ndarray, stream=None):
+        """hists: (count, 256) uint64 on the host."""
+        hh = np.ascontiguousarray(np.asarray(hists, dtype=np.uint64).reshape(self.count, 256))
+        _check(_lib.hc_cbset_build(self._h, hh.ctypes.data_as(_vp), self._out, _stream(stream)), "hc_cbset_build")
+        for k, b in enumerate(self.books):
+            b.host = self._out[k]
+            b.max_len = int(self._out[k].max_len)
+        return self.books
+
+    def __getitem__(self, k):
+        return self.books[k]
+
+    def close(self):
+        if self._h:
+            _check(_lib.hc_cbset_destroy(self._h), "hc_cbset_destroy")
+            self._h = None
 
     def __del__(self):
         try:

@@ -96,7 +96,7 @@ extern "C" hc_status hc_codebook_upload(const hc_codebook *cb, hc_cb_handle *out
 
 extern "C" hc_status hc_codebook_update(hc_cb_handle h, const hc_codebook *cb, void *stream)
 {
-    if (!h || !cb) return HC_ERR_INVALID_ARG;
+    if (!h || !cb || h->in_set) return HC_ERR_INVALID_ARG;
     hc_status st = validate_codebook(cb);
     if (st != HC_OK) return st;
     hipEvent_t ev = static_cast<hipEvent_t>(h->copy_done);
@@ -110,9 +110,96 @@ extern "C" hc_status hc_codebook_update(hc_cb_handle h, const hc_codebook *cb, v
     return HC_OK;
 }
 
+extern "C" hc_status hc_cbset_create(uint32_t count, hc_cbset *out)
+{
+    if (!out || count == 0) return HC_ERR_INVALID_ARG;
+    *out = nullptr;
+    hc_cbset_s *set = static_cast<hc_cbset_s *>(calloc(1, sizeof(hc_cbset_s)));
+    if (!set) return HC_ERR_INVALID_ARG;
+    set->count = count;
+    set->handles = static_cast<hc_cb_dev_s *>(calloc(count, sizeof(hc_cb_dev_s)));
+    hipEvent_t ev = nullptr;
+    int dev = 0;
+    const size_t bytes = (size_t)count * sizeof(DevTables);
+    if (!set->handles || hipGetDevice(&dev) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&set->staging), bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&set->d_tables), bytes) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        if (set->d_tables) (void)hipFree(set->d_tables);
+        if (set->staging) (void)hipHostFree(set->staging);
+        free(set->handles);
+        free(set);
+        return HC_ERR_HIP;
+    }
+    set->copy_done = ev;
+    // Until the first build every table is the empty code (no symbol has a code).
+    memset(set->staging, 0, bytes);
+    for (uint32_t k = 0; k < count; ++k) {
+        hc_cb_dev_s &h = set->handles[k];
+        build_dev_tables(h.host, &set->staging[k]);
+        h.d_tables = &set->d_tables[k];
+        h.device = dev;
+        h.in_set = 1;
+    }
+    if (hipMemcpy(set->d_tables, set->staging, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(set->d_tables);
+        (void)hipHostFree(set->staging);
+        (void)hipEventDestroy(ev);
+        free(set->handles);
+        free(set);
+        return HC_ERR_HIP;
+    }
+    *out = set;
+    return HC_OK;
+}
+
+extern "C" hc_cb_handle hc_cbset_handle(hc_cbset set, uint32_t k)
+{
+    if (!set || k >= set->count) return nullptr;
+    return &set->handles[k];
+}
+
+extern "C" hc_status hc_cbset_build(hc_cbset set, const uint64_t *h_hists, hc_codebook *h_out, void *stream)
+{
+    if (!set || !h_hists) return HC_ERR_INVALID_ARG;
+    hipEvent_t ev = static_cast<hipEvent_t>(set->copy_done);
+    if (hipEventSynchronize(ev) != hipSuccess) return HC_ERR_HIP;  // staging no longer being read
+    for (uint32_t k = 0; k < set->count; ++k) {
+        hc_codebook cb;
+        hc_status st = hc_build_codebook(h_hists + (size_t)256 * k, &cb);
+        if (st != HC_OK) return st;
+        if (cb.max_len == 0) {  // an empty buffer: a one-symbol code keeps the tables usable
+            uint8_t len[kNumSym] = {0};
+            len[0] = 1;
+            canonical_from_lengths(len, &cb);
+        }
+        set->handles[k].host = cb;
+        build_dev_tables(cb, &set->staging[k]);
+        if (h_out) h_out[k] = cb;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(set->d_tables, set->staging, (size_t)set->count * sizeof(DevTables), hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
+        hipEventRecord(ev, s) != hipSuccess)
+        return HC_ERR_HIP;
+    return HC_OK;
+}
+
+extern "C" hc_status hc_cbset_destroy(hc_cbset set)
+{
+    if (!set) return HC_OK;
+    hipError_t e = hipDeviceSynchronize();
+    (void)hipFree(set->d_tables);
+    (void)hipHostFree(set->staging);
+    (void)hipEventDestroy(static_cast<hipEvent_t>(set->copy_done));
+    free(set->handles);
+    free(set);
+    return hip_status(e);
+}
+
 extern "C" hc_status hc_codebook_destroy(hc_cb_handle cb)
 {
-    if (!cb) return HC_OK;
+    if (!cb || cb->in_set) return HC_OK;
     hipError_t e = hipDeviceSynchronize();
     release(cb);
     return hip_status(e);

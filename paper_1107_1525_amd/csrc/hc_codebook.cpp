@@ -65,18 +65,19 @@ void build_dev_tables(const hc_codebook &cb, DevTables *t)
                                : 0u;
         if (cb.len[v]) t->count[cb.len[v]] += 1;
     }
+    // symbols in canonical order (length, value): counting sort by length
     uint32_t pos = 0;
     for (int L = 1; L <= kMaxLen; ++L) {
         t->base[L] = pos;
-        bool first_seen = false;
-        for (int v = 0; v < kNumSym; ++v) {
-            if (cb.len[v] != L) continue;
-            if (!first_seen) {
-                t->first[L] = cb.code[v];  // codes of one length rise with the symbol value
-                first_seen = true;
-            }
-            t->sorted[pos++] = (uint32_t)v;
-        }
+        pos += t->count[L];
+    }
+    uint32_t fill[kMaxLen + 1];
+    for (int L = 0; L <= kMaxLen; ++L) fill[L] = t->base[L];
+    for (int v = 0; v < kNumSym; ++v) {
+        const uint32_t L = cb.len[v];
+        if (!L) continue;
+        if (fill[L] == t->base[L]) t->first[L] = cb.code[v];  // codes of one length rise with the value
+        t->sorted[fill[L]++] = (uint32_t)v;
     }
     for (uint32_t e = 0; e < (1u << K); ++e) t->lut[e] = kLutInvalid;
     for (int v = 0; v < kNumSym; ++v) {

@@ -47,4 +47,13 @@ struct hc_cb_dev_s {
     hc::DevTables *staging;   // pinned host staging area for updates
     void *copy_done;          // hipEvent_t recorded after the last update copy
     int device;
+    int in_set;               // owned by a codebook set (its tables live in the set's arrays)
+};
+
+struct hc_cbset_s {
+    uint32_t count;
+    hc_cb_dev_s *handles;     // count handles pointing into the arrays below
+    hc::DevTables *d_tables;  // count tables, contiguous on the device
+    hc::DevTables *staging;   // count tables, contiguous in pinned host memory
+    void *copy_done;          // hipEvent_t recorded after the last build copy
 };

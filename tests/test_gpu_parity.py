@@ -422,3 +422,25 @@ def test_fixed_length_codes(hc, oracle):
     s = enc.stream.cpu().numpy().copy()
     s[0] ^= 8  # header no longer 8 bits per symbol
     assert _decode_status(hc, s, enc, sub=False) == hc.HC_ERR_CORRUPT
+
+
+def test_codebook_set(hc, oracle):
+    """A set of resident tables rebuilt from histograms in one call gives the
+    same codes and streams as separate codebooks, rebuild after rebuild."""
+    xs = [synth.zipf_bytes(200_000 + 17 * k, 1.0 + 0.2 * k, 40 + k) for k in range(5)]
+    xs.append(np.zeros(0, np.uint8))
+    cset = hc.CodebookSet(len(xs))
+    for rebuild in range(3):
+        order = xs if rebuild % 2 == 0 else xs[::-1]
+        hists = np.stack([oracle.histogram(x) for x in order])
+        books = cset.build(hists)
+        for k, x in enumerate(order):
+            if x.size == 0:
+                assert books[k].max_len == 1
+                continue
+            L, C = oracle.codebook(hists[k])
+            assert np.array_equal(books[k].host.lengths, L) and np.array_equal(books[k].host.codes, C)
+            enc = hc.compress(dev(x), 4096, sub_block=1024, codebook=books[k])
+            assert np.array_equal(enc.stream.cpu().numpy(), oracle.encode(x, 4096, L, C)[0])
+            assert torch.equal(hc.decompress(enc), dev(x))
+    cset.close()
