@@ -751,6 +751,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
     const bool fixed8 = tb->fixed_len == 8;  // uniform over the group: one job per group
+    const bool has_zero_code = tb->count[1] != 0;
     if (!fixed8)
         for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
     if (tid <= (uint32_t)kPackedMaxLen) {
@@ -921,6 +922,53 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     };
 
     uint32_t k = 0;
+    if (has_zero_code) {
+        // The code '0' (one bit) exists: it is the shortest canonical code, of
+        // symbol sorted[0].  A run of that symbol is a run of leading zero bits,
+        // so each step emits min(leading zeros, symbols left) copies at once and
+        // then, if a '1' follows, decodes one other symbol through the table.
+        // A step consumes at most 32 + max_len bits (two words), which the ring
+        // always holds after advance_ring.
+        const uint32_t zsym = s_sorted[0];
+        const uint64_t rep = 0x0101010101010101ull * zsym;
+        uint64_t ob = 0;  // output bytes waiting for a full 8-byte store
+        uint32_t oc = 0;
+        HC_G uint8_t *o8 = dst;
+        auto emit = [&](uint64_t bytes, uint32_t cnt) {  // append cnt (<= 8) bytes
+            const uint32_t take = cnt < 8 - oc ? cnt : 8 - oc;
+            ob |= (take == 8 ? bytes : (bytes & ((1ull << (8 * take)) - 1))) << (8 * oc);
+            oc += take;
+            if (oc == 8) {
+                *(HC_G uint64_t *)o8 = ob;
+                o8 += 8;
+                oc = 0;
+                ob = (take < cnt) ? (bytes >> (8 * take)) & ((1ull << (8 * (cnt - take))) - 1) : 0ull;
+                oc = cnt - take;
+            }
+        };
+        while (k < nsym) {
+            advance_ring();
+            const uint32_t hi = (uint32_t)(buf >> 32);
+            const uint32_t z = hi ? (uint32_t)__clz((int)hi) : 32u;
+            uint32_t r = nsym - k < z ? nsym - k : z;
+            buf <<= r;
+            nbits -= r;
+            refill();
+            k += r;
+            while (r) {
+                const uint32_t c = r < 8 ? r : 8;
+                emit(rep, c);
+                r -= c;
+            }
+            if (z < 32 && k < nsym) {  // a '1' follows the run: one other symbol
+                emit(decode_sym(), 1);
+                refill();
+                k += 1;
+            }
+        }
+        for (uint32_t q = 0; q < oc; ++q) o8[q] = (uint8_t)(ob >> (8 * q));
+        k = nsym;
+    }
     for (; k + R <= nsym; k += R) {  // full rounds: SPR symbols between refills
         advance_ring();
         uint32_t o4[R / 4];

@@ -187,8 +187,9 @@ def _decode_status(hc, stream_np, enc, n=None, sub=True):
     return hc.read_error(err)
 
 
-def test_corruption_matches_oracle(hc, oracle):
-    x = synth.zipf_bytes(200_000, 1.2, 1)
+@pytest.mark.parametrize("kind", ["zipf", "skewed"])
+def test_corruption_matches_oracle(hc, oracle, kind):
+    x = synth.zipf_bytes(200_000, 1.2, 1) if kind == "zipf" else synth.skewed_bytes(200_000, 1)
     B = 4096
     enc = hc.compress(dev(x), B, sub_block=1024)
     L = enc.codebook.host.lengths
