@@ -43,8 +43,8 @@ WORKLOAD = "mixed-4GiB-64x64MiB"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--block", type=int, default=64 * 1024)
     ap.add_argument("--sub-block", type=int, default=1024)
     ap.add_argument("--segments", type=int, default=64, help="number of 64 MiB segments (64 = 4 GiB)")
@@ -157,20 +157,6 @@ class Workload:
         mark("dec", 0)
         hc.hc_decode_batch(self.dec_items, self.B, self.S, self.ws, self.err)
         mark("dec", 1)
-
-
-def time_phases(w, torch, reps=5):
-    """GPU time (ms) of each phase's launch, from HIP events recorded on the
-    stream the library launches on (torch's current stream)."""
-    E = torch.cuda.Event
-    res = {"hist": [], "enc": [], "dec": []}
-    for _ in range(reps):
-        ev = {k: (E(enable_timing=True), E(enable_timing=True)) for k in res}
-        w.step(ev)
-        torch.cuda.synchronize()
-        for k in res:
-            res[k].append(ev[k][0].elapsed_time(ev[k][1]))
-    return res
 
 
 def cpu_baseline(w, oracle, np):
@@ -452,18 +438,22 @@ def main():
         # correctness of the timed configuration: decode must reproduce the input
         assert torch.equal(w.y, w.x), "round trip failed"
         print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+        # HIP events around every launch of the timed steps, on the stream the
+        # library launches on (torch's current stream)
+        E = torch.cuda.Event
+        evs = [{k: (E(enable_timing=True), E(enable_timing=True)) for k in ("hist", "enc", "dec")}
+               for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            w.step()
+        for k in range(args.steps):
+            w.step(evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         if hc.read_error(w.err):
             raise hc.HcError(hc.read_error(w.err), "timed steps")
         ms_step = wall * 1e3 / args.steps
-        ph = time_phases(w, torch)
-        med = lambda v: float(np.median(v))
-        hist_ms, enc_ms, dec_ms = med(ph["hist"]), med(ph["enc"]), med(ph["dec"])
+        avg = lambda k: float(np.mean([e[k][0].elapsed_time(e[k][1]) for e in evs]))
+        hist_ms, enc_ms, dec_ms = avg("hist"), avg("enc"), avg("dec")
         n = w.n
         C = sum(w.C)
         off_bytes = 8 * (w.nb + 1) * w.nseg
