@@ -219,7 +219,7 @@ extern "C" uint64_t hc_encode_workspace_bytes(uint64_t n, uint32_t block_size)
 {
     if (block_size == 0) return 0;
     const uint64_t nb = num_blocks(n, block_size);
-    return 8 * encode_state_words(nb * tiles_per_block(block_size), nb);
+    return 8 * encode_state_words(nb * tiles_per_block(block_size, 1), nb);  // the smallest tile: an upper bound
 }
 
 extern "C" uint64_t hc_sub_index_entries(uint64_t n, uint32_t block_size, uint32_t sub_block)
@@ -337,7 +337,8 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (n == 0) return hip_status(launch_encode_empty(d_block_off, s));
     const uint64_t nb = num_blocks(n, block_size);
-    const uint64_t tiles = nb * tiles_per_block(block_size);
+    const uint32_t qpt = encode_qpt(block_size, cb->host.max_len);
+    const uint64_t tiles = nb * tiles_per_block(block_size, qpt);
     if (!d_ws || !aligned(d_ws, 8)) return HC_ERR_INVALID_ARG;
     if (ws_bytes < 8 * encode_state_words(tiles, nb)) return HC_ERR_NO_SPACE;
     if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;  // grid limit
@@ -348,7 +349,7 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
     j.out = d_out;
     j.block_off = d_block_off;
     j.sub_idx = d_sub_idx;
-    return hip_status(launch_encode(single(j), tiles, nb, block_size, cb->host.max_len, sub_block,
+    return hip_status(launch_encode(single(j), tiles, nb, block_size, qpt, cb->host.max_len, sub_block,
                                     static_cast<uint64_t *>(d_ws), d_err, s));
 }
 
@@ -389,7 +390,7 @@ extern "C" uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t coun
     for (uint32_t k = 0; k < count; ++k) {
         const uint64_t nb = num_blocks(items[k].n, block_size);
         blocks += nb;
-        tiles += nb * tiles_per_block(block_size);
+        tiles += nb * tiles_per_block(block_size, 1);
     }
     return job_table_bytes(count) + 8 * encode_state_words(tiles, blocks);
 }
@@ -434,12 +435,18 @@ extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint3
     std::vector<Job> jobs(count);
     uint64_t tiles = 0, blocks = 0;
     uint32_t max_len = 1;
-    const uint32_t tpb = tiles_per_block(block_size);
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
         hc_status st = check_encode(it.in, it.n, block_size, it.cb, it.out, it.out_cap, it.block_off, it.sub_idx,
                                     sub_block);
         if (st != HC_OK) return st;
+        if (it.n > 0 && it.cb->host.max_len > max_len) max_len = it.cb->host.max_len;
+    }
+    // one tile shape for the launch, from the longest code of any job
+    const uint32_t qpt = encode_qpt(block_size, max_len);
+    const uint32_t tpb = tiles_per_block(block_size, qpt);
+    for (uint32_t k = 0; k < count; ++k) {
+        const hc_item &it = items[k];
         Job j = empty_job();
         j.in = it.in;
         j.n = it.n;
@@ -452,7 +459,6 @@ extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint3
         const uint64_t nb = num_blocks(it.n, block_size);
         tiles += nb * tpb;
         blocks += nb;
-        if (it.n > 0 && it.cb->host.max_len > max_len) max_len = it.cb->host.max_len;
         jobs[k] = j;
     }
     if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
@@ -465,7 +471,7 @@ extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint3
     for (uint32_t k = 0; k < count; ++k)
         if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
     uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(d_ws) + head);
-    return hip_status(launch_encode(jl, tiles, blocks, block_size, max_len, sub_block, state, d_err, s));
+    return hip_status(launch_encode(jl, tiles, blocks, block_size, qpt, max_len, sub_block, state, d_err, s));
 }
 
 extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,

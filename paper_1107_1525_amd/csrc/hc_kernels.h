@@ -13,8 +13,8 @@ constexpr uint64_t kHistMinChunk = 128 * 1024;
 constexpr int kHistTargetGroups = 512; // two 64 KiB-LDS groups per CU on 256 CUs
 
 constexpr int kTileThreads = 256;      // encode work-group size (4 waves)
-constexpr int kSymPerThread = 16;      // one 16-byte load per thread
-constexpr uint32_t kTileSyms = kTileThreads * kSymPerThread;  // 4096 symbols per tile
+constexpr uint32_t kQuadSyms = 16;     // symbols of one 16-byte load
+constexpr uint32_t kTileSyms = kTileThreads * kQuadSyms;  // tile of one load per thread
 // Bound on the look-back waits of the encoder (iterations of a short sleep,
 // about a second): a wait that long means a predecessor never ran, which is
 // reported as HC_ERR_TIMEOUT instead of hanging the device.
@@ -47,7 +47,21 @@ struct JobList {
 };
 
 inline uint64_t num_blocks(uint64_t n, uint32_t B) { return (n + B - 1) / B; }
-inline uint32_t tiles_per_block(uint32_t B) { return (B + kTileSyms - 1) / kTileSyms; }
+// Loads (16 symbols each) per encode thread: a tile is qpt * 4096 symbols.
+// Large tiles give each work-group more bytes per look-back; they need
+// qpt * 4096 * max_len bits of LDS, so long codes keep the small tile.
+inline uint32_t encode_qpt(uint32_t B, uint32_t max_len)
+{
+    if (max_len > (uint32_t)kPackedMaxLen) return 1;
+    if (B >= 4 * kTileSyms && max_len <= 16) return 4;
+    if (B >= 2 * kTileSyms) return 2;
+    return 1;
+}
+inline uint32_t tiles_per_block(uint32_t B, uint32_t qpt)
+{
+    const uint32_t t = qpt * kTileSyms;
+    return (B + t - 1) / t;
+}
 inline uint64_t hist_chunk(uint64_t total)
 {
     uint64_t chunk = (total + kHistTargetGroups - 1) / kHistTargetGroups;
@@ -61,8 +75,8 @@ inline uint64_t hist_chunk(uint64_t total)
 inline uint64_t encode_state_words(uint64_t tiles, uint64_t blocks) { return 2 + tiles + blocks; }
 
 hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, hipStream_t s);
-hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uint32_t B, uint32_t max_len,
-                         uint32_t S, uint64_t *state, uint32_t *err, hipStream_t s);
+hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uint32_t B, uint32_t qpt,
+                         uint32_t max_len, uint32_t S, uint64_t *state, uint32_t *err, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s);
 hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64_t *block_off,
                        uint32_t *err, hipStream_t s);

@@ -184,8 +184,9 @@ struct Tile {
     uint32_t ts, te;    // symbol range of the tile, relative to the block
 };
 
-// Tile t (counted from the job's first tile) of a job of n symbols.
-__device__ __forceinline__ Tile tile_of(uint64_t n, uint32_t B, uint32_t tpb, uint64_t t)
+// Tile t (counted from the job's first tile) of a job of n symbols: tiles of
+// tile_syms symbols, tpb of them per block.
+__device__ __forceinline__ Tile tile_of(uint64_t n, uint32_t B, uint32_t tpb, uint32_t tile_syms, uint64_t t)
 {
     Tile r;
     r.blk = t / tpb;
@@ -193,30 +194,38 @@ __device__ __forceinline__ Tile tile_of(uint64_t n, uint32_t B, uint32_t tpb, ui
     r.blk_start = r.blk * (uint64_t)B;
     const uint64_t left = n - r.blk_start;
     r.cnt = (uint32_t)(left < B ? left : B);
-    r.ts = r.j * kTileSyms;
-    const uint32_t e = r.ts + kTileSyms;
+    r.ts = r.j * tile_syms;
+    const uint32_t e = r.ts + tile_syms;
     r.te = e < r.cnt ? e : r.cnt;
     if (r.ts > r.te) r.ts = r.te;  // empty tile past the end of a short last block
     return r;
 }
 
-// Loads the (up to) 16 symbols of this thread; returns how many there are.
-__device__ __forceinline__ uint32_t load16(const HC_G uint8_t *__restrict__ in, const Tile &tl, uint32_t s,
-                                           uint32_t w[4])
+// Loads the (up to) 16*QPT consecutive symbols of this thread from symbol s
+// of the tile's block; returns how many there are.
+template <uint32_t QPT>
+__device__ __forceinline__ uint32_t load_syms(const HC_G uint8_t *__restrict__ in, const Tile &tl, uint32_t s,
+                                              uint32_t w[4 * QPT])
 {
-    w[0] = w[1] = w[2] = w[3] = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * QPT; ++i) w[i] = 0;
     if (s >= tl.te) return 0;
     const HC_G uint8_t *src = in + tl.blk_start + s;
-    if (s + 16 <= tl.te) {
-        v4u q = *(const HC_G v4u *)src;
-        w[0] = q.x;
-        w[1] = q.y;
-        w[2] = q.z;
-        w[3] = q.w;
-        return 16;
+    if (s + kQuadSyms * QPT <= tl.te) {
+#pragma unroll
+        for (uint32_t q = 0; q < QPT; ++q) {
+            const v4u v = ((const HC_G v4u *)src)[q];
+            w[4 * q + 0] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+        return kQuadSyms * QPT;
     }
-    const uint32_t m = tl.te - s;
-    for (uint32_t k = 0; k < m; ++k) w[k >> 2] |= (uint32_t)src[k] << (8 * (k & 3));
+    const uint32_t m = tl.te - s;  // the ragged end of a block: byte loads
+#pragma unroll
+    for (uint32_t k = 0; k < kQuadSyms * QPT; ++k)
+        if (k < m) w[k >> 2] |= (uint32_t)src[k] << (8 * (k & 3));
     return m;
 }
 
@@ -307,11 +316,14 @@ __device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t
 
 // kPacked: codes of <= 24 bits from the packed table, FPS codes between
 // accumulator flushes (FPS * max_len <= 32); otherwise codes up to 64 bits.
-template <bool kPacked, uint32_t FPS>
+// QPT: 16-symbol loads per thread; a tile is 4096 * QPT symbols and thread i
+// codes its symbols [16 * QPT * i, 16 * QPT * (i + 1)).
+template <bool kPacked, uint32_t FPS, uint32_t QPT>
 __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B, uint32_t tpb, uint64_t *tstate,
                                                          uint64_t *bstate_all, uint32_t S, uint32_t cpb,
                                                          uint32_t lds_words, uint32_t *err)
 {
+    constexpr uint32_t kSyms = kQuadSyms * QPT;  // symbols per thread
     extern __shared__ uint32_t words[];  // the tile's code bits from bit 0, MSB first
     __shared__ uint32_t s_packed[kNumSym];
     __shared__ uint64_t s_code[kPacked ? 1 : kNumSym];
@@ -343,28 +355,26 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     HC_G uint32_t *__restrict__ sub_idx = (HC_G uint32_t *)s_job.sub_idx;
     uint64_t *bstate = bstate_all + s_job.block_begin;
     const uint64_t nb = num_blocks_dev(s_job.n, B);
-    const Tile tl = tile_of(s_job.n, B, tpb, t - s_job.unit_begin);
+    const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
     if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
 
     const bool last_tile = tl.te == tl.cnt;
     const uint32_t avail = last_tile ? 0u : (tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32u);
     if (tid < 32) s_next[tid] = tid < avail ? in[tl.blk_start + tl.te + tid] : 0u;
-    const uint32_t s = tl.ts + kSymPerThread * tid;
-    uint32_t w[4];
-    const uint32_t m = load16(in, tl, s, w);
+    const uint32_t s = tl.ts + kSyms * tid;
+    uint32_t w[4 * QPT];
+    const uint32_t m = load_syms<QPT>(in, tl, s, w);
     __syncthreads();  // code tables and the next tile's first symbols are in LDS
+
+    // lengths: the thread's bit count, and the bits before each of its loads
     uint32_t bits = 0;
+    uint32_t qbits[QPT];
     bool absent = false;
-    uint32_t e[16];  // packed table entries (code << 8 | len) of this thread's symbols
 #pragma unroll
-    for (uint32_t k = 0; k < 16; ++k) {
+    for (uint32_t k = 0; k < kSyms; ++k) {
+        if ((k & (kQuadSyms - 1)) == 0) qbits[k / kQuadSyms] = bits;
         uint32_t L = 0;
-        if (kPacked) {
-            e[k] = (k < m) ? s_packed[sym_at(w, k)] : 0u;
-            L = e[k] & 255u;
-        } else if (k < m) {
-            L = s_len[sym_at(w, k)];
-        }
+        if (k < m) L = kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
         absent |= (k < m) && (L == 0);
         bits += L;
     }
@@ -380,14 +390,15 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
         uint64_t acc = 0;
         if (kPacked) {
             // FPS codes of <= 32/FPS bits between flushes: the accumulator never
-            // exceeds 63 bits, and one flush retires at most one word.  Entries of
-            // missing symbols (m < 16) are 0 and add nothing.
+            // exceeds 63 bits, and one flush retires at most one word.  Symbols
+            // past m add nothing.
 #pragma unroll
-            for (uint32_t k = 0; k < 16; k += FPS) {
+            for (uint32_t k = 0; k < kSyms; k += FPS) {
 #pragma unroll
                 for (uint32_t j = 0; j < FPS; ++j) {
-                    const uint32_t L = e[k + j] & 255u;
-                    acc = (acc << L) | (e[k + j] >> 8);
+                    const uint32_t e = (k + j < m) ? s_packed[sym_at(w, k + j)] : 0u;
+                    const uint32_t L = e & 255u;
+                    acc = (acc << L) | (e >> 8);
                     nacc += L;
                 }
                 const uint32_t need = nacc >= 32 ? 1u : 0u;
@@ -399,7 +410,7 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
             }
         } else {
 #pragma unroll
-            for (uint32_t k = 0; k < 16; ++k) {
+            for (uint32_t k = 0; k < kSyms; ++k) {
                 if (k < m) {
                     const uint32_t v = sym_at(w, k);
                     const uint32_t L = s_len[v];
@@ -496,7 +507,12 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     }
     if (last_tile && tid == 0) out32[O >> 2] = s_bits;
     if (sub_idx) {
-        if (m > 0 && (s % S) == 0) sub_idx[tl.blk * cpb + s / S] = (uint32_t)P + q;
+        // S is a multiple of 16: entries fall on the first symbol of a load
+#pragma unroll
+        for (uint32_t j = 0; j < QPT; ++j) {
+            const uint32_t sj = s + kQuadSyms * j;
+            if (m > kQuadSyms * j && (sj % S) == 0) sub_idx[tl.blk * cpb + sj / S] = (uint32_t)P + q + qbits[j];
+        }
         if (last_tile && tid == 0)
             for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = s_bits;
     }
@@ -699,16 +715,20 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 }
 
 // ---------------------------------------------------------------- decode, codes of <= 24 bits
-// Same lane mapping and checks as k_decode, but the lane's payload words reach
-// its bit buffer through a private ring of 16 words in LDS (two halves of 8).
-// The ring is filled with 16-byte loads; the half after the ring is loaded into
-// registers one round ahead and written into the ring when the lane has moved
-// past a half, so no symbol waits on a global load.  A round decodes R symbols
-// with R * max_len <= 8 words (one half), so the ring always holds what a round
-// can consume.
-constexpr uint32_t kRingHalf = 8;
-constexpr uint32_t kRingWords = 2 * kRingHalf;
-constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
+// Same lane mapping and checks as k_decode; what differs is how a lane meets
+// HBM.  Thousands of lanes each stream their own chunk, so a lane that read or
+// wrote 16 bytes at a time would leave partly used 128-byte lines in L2 long
+// enough to be evicted and fetched (or written) again.  Here every HBM access
+// of a lane is a whole line:
+//  * input: a private LDS ring of two 16-word halves; the lane loads a whole
+//    line (8 consecutive 16-byte loads) into registers one half ahead of use
+//    and moves it into the ring half by half as it leaves a half;
+//  * output: a private 128-byte LDS line; decoded bytes are appended to it and
+//    it is stored as 8 consecutive 16-byte stores when full.
+// A round decodes R symbols with R * max_len <= 16 words, so the two ring
+// halves always hold what a round can consume.
+constexpr uint32_t kRingHalf = 16;
+constexpr uint32_t kRingWords = 2 * kRingHalf;  // one 128-byte line per lane
 
 __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32, uint64_t q, uint64_t in_words)
 {
@@ -721,14 +741,13 @@ __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32,
     return r;
 }
 
-// R symbols per round (8 or 16), SPR symbols between buffer refills
-// (SPR * max_len <= 32), kLong: codes may be longer than the table.
 template <uint32_t R, uint32_t SPR, bool kLong>
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
                                                              uint32_t *err)
 {
     __shared__ uint16_t s_lut[1 << kLutBits];
-    __shared__ uint32_t s_ring[kDecThreads * kRingStride];
+    __shared__ uint32_t s_ring[kDecThreads * kRingWords];
+    __shared__ v4u s_stage[kDecThreads * 8];  // one output line per lane
     __shared__ uint32_t s_first[kPackedMaxLen + 1];
     __shared__ uint32_t s_count[kPackedMaxLen + 1];
     __shared__ uint32_t s_base[kPackedMaxLen + 1];
@@ -795,6 +814,101 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         return;
     }
 
+    // ---- output line: bytes are appended at virtual position ov = ph + bytes
+    // written, ph = the chunk start's offset in its 128-byte line (a multiple
+    // of 16); quad j of the lane's line sits at LDS quad j ^ (lane & 7) so 8
+    // consecutive lanes touch distinct banks.
+    HC_G uint8_t *const dst = out + blk_start + s0;
+    const uint32_t ph = (uint32_t)((uint64_t)dst & 127u);
+    uint32_t ov = ph;
+    v4u *stage = s_stage + tid * 8;
+    const uint32_t osw = tid & 7u;
+    auto flush_line = [&](uint32_t lv, uint32_t jto) {  // quads [.., jto) of the line at virtual lv
+        const uint32_t jfrom = lv < ph ? (ph - lv) >> 4 : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j)
+            if (j >= jfrom && j < jto) *(HC_G v4u *)(dst + ((int64_t)(lv + 16 * j) - (int64_t)ph)) = stage[j ^ osw];
+    };
+    auto put16 = [&](v4u v) {  // ov is a multiple of 16
+        stage[((ov >> 4) & 7u) ^ osw] = v;
+        ov += 16;
+        if ((ov & 127u) == 0) flush_line(ov - 128, 8);
+    };
+    auto put8 = [&](uint64_t v) {  // ov is a multiple of 8
+        reinterpret_cast<uint64_t *>(&stage[((ov >> 4) & 7u) ^ osw])[(ov >> 3) & 1u] = v;
+        ov += 8;
+        if ((ov & 127u) == 0) flush_line(ov - 128, 8);
+    };
+    auto put1 = [&](uint32_t v) {
+        reinterpret_cast<uint8_t *>(&stage[((ov >> 4) & 7u) ^ osw])[ov & 15u] = (uint8_t)v;
+        ov += 1;
+        if ((ov & 127u) == 0) flush_line(ov - 128, 8);
+    };
+    auto finish_output = [&]() {  // the last line, in part
+        if (ov & 127u) {
+            const uint32_t lv = ov & ~127u, jl = (ov & 127u) >> 4, tail = ov & 15u;
+            flush_line(lv, jl);
+            const uint8_t *sb = reinterpret_cast<const uint8_t *>(&stage[jl ^ osw]);
+            for (uint32_t q = 0; q < tail; ++q) dst[(int64_t)(lv + 16 * jl + q) - (int64_t)ph] = sb[q];
+        }
+    };
+
+    // ---- input ring: stream words are counted from the 128-byte line holding
+    // the stream's first word (virtual word u = stream word + mis), so line L
+    // is virtual words [32L, 32L + 32).  The ring holds halves h and h + 1
+    // (16 words each, word u at slot (u mod 32) ^ swizzle); registers f hold the
+    // line of half h + 2.
+    const uint64_t in_words = in_bytes >> 2;
+    const uint32_t mis = (uint32_t)(((uint64_t)in32 >> 2) & 31u);  // a multiple of 4
+    const uint64_t pw0 = (o >> 2) + 1;                             // stream word of payload bit 0
+    uint32_t *ring = s_ring + tid * kRingWords;
+    const uint32_t rsw = (tid >> 1) & 31u;
+    auto rslot = [&](uint64_t u) -> uint32_t { return ((uint32_t)u & 31u) ^ rsw; };
+    auto load_line = [&](uint64_t L, v4u f[8]) {
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            const uint64_t qa = 8 * L + j;
+            f[j] = qa >= mis / 4 ? load_quad(in32, qa - mis / 4, in_words) : v4u{0u, 0u, 0u, 0u};
+        }
+    };
+    auto put_quad = [&](uint64_t u, v4u v) {
+        ring[rslot(u + 0)] = v.x;
+        ring[rslot(u + 1)] = v.y;
+        ring[rslot(u + 2)] = v.z;
+        ring[rslot(u + 3)] = v.w;
+    };
+    const uint64_t u0 = pw0 + (p0 >> 5) + mis;  // virtual word of the chunk's first bit
+    uint64_t h = u0 >> 4;
+    v4u f[8];
+    {
+        v4u a[8];
+        load_line(h >> 1, a);
+        load_line((h >> 1) + 1, f);
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) put_quad(32 * (h >> 1) + 4 * j, a[j]);
+        if (h & 1) {  // half h + 1 is the first half of the next line; h + 2 stays in f
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) put_quad(32 * ((h >> 1) + 1) + 4 * j, f[j]);
+        }
+    }
+    uint64_t nxt = u0;  // next virtual word to enter the bit buffer
+    // Once nxt has left half h, its slots take half h + 2 from f; after the
+    // second half of f's line is placed, f is refilled with the next line.
+    auto advance_ring = [&]() {
+        if (nxt >= 16 * h + 16) {
+            if ((h & 1) == 0) {
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) put_quad(16 * (h + 2) + 4 * j, f[j]);
+            } else {
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) put_quad(16 * (h + 2) + 4 * j, f[4 + j]);
+                load_line((h + 3) >> 1, f);
+            }
+            h += 1;
+        }
+    };
+    const uint32_t nsym = s1 - s0;
+
     if (fixed8) {
         // Every code is 8 bits: symbol k of the block is byte 3 - (k & 3) of
         // payload word k >> 2, so the chunk decodes word by word with
@@ -804,66 +918,45 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             report(err, HC_ERR_CORRUPT);
             return;
         }
-        const HC_G uint32_t *src = in32 + (o >> 2) + 1 + (s0 >> 2);
-        HC_G uint8_t *dst8 = out + blk_start + s0;
-        const uint32_t nsym = s1 - s0;
         const uint32_t ncode = s_count[8];
         uint32_t bad8 = 0;
+        auto code_at = [&](uint32_t q) -> uint32_t {  // code of symbol q of the round at nxt
+            const uint32_t c = (ring[rslot(nxt + (q >> 2))] >> (24 - 8 * (q & 3))) & 255u;
+            bad8 |= (uint32_t)(c >= ncode);
+            return c;
+        };
         uint32_t k = 0;
         for (; k + 16 <= nsym; k += 16) {
+            advance_ring();
             uint32_t o4[4];
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) {
-                const uint32_t wd = src[(k >> 2) + q];
-                const uint32_t c0 = wd >> 24, c1 = (wd >> 16) & 255u, c2 = (wd >> 8) & 255u, c3 = wd & 255u;
-                bad8 |= (uint32_t)(c0 >= ncode) | (uint32_t)(c1 >= ncode) | (uint32_t)(c2 >= ncode) |
-                        (uint32_t)(c3 >= ncode);
-                o4[q] = s_sorted[c0 & 255u] | (s_sorted[c1] << 8) | (s_sorted[c2] << 16) | (s_sorted[c3] << 24);
-            }
-            *(HC_G v4u *)(dst8 + k) = v4u{o4[0], o4[1], o4[2], o4[3]};
+            for (uint32_t q = 0; q < 4; ++q)
+                o4[q] = s_sorted[code_at(4 * q)] | (s_sorted[code_at(4 * q + 1)] << 8) |
+                        (s_sorted[code_at(4 * q + 2)] << 16) | (s_sorted[code_at(4 * q + 3)] << 24);
+            nxt += 4;
+            put16(v4u{o4[0], o4[1], o4[2], o4[3]});
         }
-        for (; k < nsym; ++k) {
-            const uint32_t c = (src[k >> 2] >> (24 - 8 * (k & 3))) & 255u;
-            bad8 |= (uint32_t)(c >= ncode);
-            dst8[k] = (uint8_t)s_sorted[c];
+        if (k < nsym) {  // fewer than 16 symbols: at most 4 words from nxt
+            advance_ring();
+#pragma unroll
+            for (uint32_t q = 0; q < 16; ++q)
+                if (k + q < nsym) put1(s_sorted[code_at(q)]);
         }
+        finish_output();
         if (s1 == cnt && (hdr & 31u)) {
             const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
-            bad8 |= (in32[(o >> 2) + 1 + nwords - 1] & mask) ? 1u : 0u;
+            bad8 |= (in32[pw0 + nwords - 1] & mask) ? 1u : 0u;
         }
         if (bad8) report(err, HC_ERR_CORRUPT);
         return;
     }
 
-    // ring: stream words [kRingHalf*h, kRingHalf*h + kRingWords) at slot (word mod kRingWords)
-    const uint64_t in_words = in_bytes >> 2;
-    const uint64_t pw0 = (o >> 2) + 1;  // stream word of payload bit 0
-    uint32_t *ring = s_ring + tid * kRingStride;
-    const uint64_t sw = pw0 + (p0 >> 5);
-    uint64_t h = sw / kRingHalf;
-    constexpr uint32_t kQuadsPerHalf = kRingHalf / 4;
-#pragma unroll
-    for (uint32_t j = 0; j < 2 * kQuadsPerHalf; ++j) {
-        const v4u v = load_quad(in32, h * kQuadsPerHalf + j, in_words);
-        const uint32_t base = (uint32_t)((h * kRingHalf + 4 * j) & (kRingWords - 1));
-        ring[base + 0] = v.x;
-        ring[base + 1] = v.y;
-        ring[base + 2] = v.z;
-        ring[base + 3] = v.w;
-    }
-    v4u f[kQuadsPerHalf];  // in flight: stream words of half h + 2
-#pragma unroll
-    for (uint32_t j = 0; j < kQuadsPerHalf; ++j) f[j] = load_quad(in32, (h + 2) * kQuadsPerHalf + j, in_words);
-
-    const uint32_t r = (uint32_t)(p0 & 31);
-    uint64_t buf = (((uint64_t)ring[sw & (kRingWords - 1)] << 32) | ring[(sw + 1) & (kRingWords - 1)]) << r;
-    uint32_t nbits = 64 - r;
-    uint64_t nxt = sw + 2;  // next stream word to enter the bit buffer
-    uint32_t pre = ring[nxt & (kRingWords - 1)];
-
+    const uint32_t r0 = (uint32_t)(p0 & 31);
+    uint64_t buf = (((uint64_t)ring[rslot(u0)] << 32) | ring[rslot(u0 + 1)]) << r0;
+    uint32_t nbits = 64 - r0;
+    nxt = u0 + 2;
+    uint32_t pre = ring[rslot(nxt)];
     uint32_t bad = 0;  // bit 15: an invalid prefix was met
-    HC_G uint8_t *dst = out + blk_start + s0;
-    const uint32_t nsym = s1 - s0;
 
     // One symbol from the buffer (which holds >= max_len bits here).  Table
     // entries of invalid prefixes carry bit 15 and length 1, so codes of at
@@ -901,24 +994,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         buf |= need ? add : 0ull;
         nbits += need << 5;
         nxt += need;
-        pre = ring[(uint32_t)nxt & (kRingWords - 1)];
-    };
-    auto advance_ring = [&]() {
-        if (nxt >= kRingHalf * h + kRingHalf) {
-            // the lane has left half h: its slots receive half h + 2
-#pragma unroll
-            for (uint32_t j = 0; j < kQuadsPerHalf; ++j) {
-                const uint32_t base = (uint32_t)(((h + 2) * kRingHalf + 4 * j) & (kRingWords - 1));
-                ring[base + 0] = f[j].x;
-                ring[base + 1] = f[j].y;
-                ring[base + 2] = f[j].z;
-                ring[base + 3] = f[j].w;
-            }
-            h += 1;
-#pragma unroll
-            for (uint32_t j = 0; j < kQuadsPerHalf; ++j)
-                f[j] = load_quad(in32, (h + 2) * kQuadsPerHalf + j, in_words);
-        }
+        pre = ring[rslot(nxt)];
     };
 
     uint32_t k = 0;
@@ -931,19 +1007,16 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         // always holds after advance_ring.
         const uint32_t zsym = s_sorted[0];
         const uint64_t rep = 0x0101010101010101ull * zsym;
-        uint64_t ob = 0;  // output bytes waiting for a full 8-byte store
+        uint64_t ob = 0;  // output bytes waiting for a full 8-byte append
         uint32_t oc = 0;
-        HC_G uint8_t *o8 = dst;
-        auto emit = [&](uint64_t bytes, uint32_t cnt) {  // append cnt (<= 8) bytes
-            const uint32_t take = cnt < 8 - oc ? cnt : 8 - oc;
+        auto emit = [&](uint64_t bytes, uint32_t cnt8) {  // append cnt8 (<= 8) bytes
+            const uint32_t take = cnt8 < 8 - oc ? cnt8 : 8 - oc;
             ob |= (take == 8 ? bytes : (bytes & ((1ull << (8 * take)) - 1))) << (8 * oc);
             oc += take;
             if (oc == 8) {
-                *(HC_G uint64_t *)o8 = ob;
-                o8 += 8;
-                oc = 0;
-                ob = (take < cnt) ? (bytes >> (8 * take)) & ((1ull << (8 * (cnt - take))) - 1) : 0ull;
-                oc = cnt - take;
+                put8(ob);
+                ob = (take < cnt8) ? (bytes >> (8 * take)) & ((1ull << (8 * (cnt8 - take))) - 1) : 0ull;
+                oc = cnt8 - take;
             }
         };
         while (k < nsym) {
@@ -966,7 +1039,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
                 k += 1;
             }
         }
-        for (uint32_t q = 0; q < oc; ++q) o8[q] = (uint8_t)(ob >> (8 * q));
+        for (uint32_t q = 0; q < oc; ++q) put1((uint32_t)(ob >> (8 * q)) & 255u);
         k = nsym;
     }
     for (; k + R <= nsym; k += R) {  // full rounds: SPR symbols between refills
@@ -981,9 +1054,9 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             refill();
         }
         if (R == 16)
-            *(HC_G v4u *)(dst + k) = v4u{o4[0], o4[1], o4[2], o4[3]};
+            put16(v4u{o4[0], o4[1], o4[2], o4[3]});
         else
-            *(HC_G v2u *)(dst + k) = v2u{o4[0], o4[1]};
+            put8(((uint64_t)o4[1] << 32) | o4[0]);
     }
     if (k < nsym) {  // the ragged last round: one symbol between refills
         advance_ring();
@@ -991,12 +1064,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
 #pragma unroll
         for (uint32_t q = 0; q < R; ++q) {
             if (q < m) {
-                dst[k + q] = (uint8_t)decode_sym();
+                put1(decode_sym());
                 refill();
             }
         }
     }
-    const uint64_t pos = 32 * (nxt - pw0) - nbits;
+    finish_output();
+    const uint64_t pos = 32 * (nxt - mis - pw0) - nbits;
     if ((bad & 0x8000u) || pos != p1) {
         report(err, HC_ERR_CORRUPT);
         return;
@@ -1015,28 +1089,39 @@ hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, h
     return hipGetLastError();
 }
 
-hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uint32_t B, uint32_t max_len,
-                         uint32_t S, uint64_t *state, uint32_t *err, hipStream_t s)
+hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uint32_t B, uint32_t qpt,
+                         uint32_t max_len, uint32_t S, uint64_t *state, uint32_t *err, hipStream_t s)
 {
     const uint64_t words = encode_state_words(tiles, blocks);
     uint64_t fill_groups = (words + 255) / 256;
     if (fill_groups > 4096) fill_groups = 4096;
     k_fill_u64<<<dim3((uint32_t)fill_groups), 256, 0, s>>>(state, words, 0);
     if (tiles == 0) return hipGetLastError();
-    const uint32_t tpb = tiles_per_block(B);
-    const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * max_len + 31ull) / 32ull + 2);
+    const uint32_t tpb = tiles_per_block(B, qpt);
+    const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * qpt * max_len + 31ull) / 32ull + 2);
     const uint32_t cpb = S ? (B + S - 1) / S : 1;
     uint64_t *tstate = state + 2, *bstate = state + 2 + tiles;
     const dim3 grid((uint32_t)tiles);
     const size_t lds = lds_words * 4;
-    if (max_len <= 8)
-        k_encode<true, 4><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err);
-    else if (max_len <= 16)
-        k_encode<true, 2><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err);
-    else if (max_len <= (uint32_t)kPackedMaxLen)
-        k_encode<true, 1><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err);
-    else
-        k_encode<false, 1><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err);
+#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err)
+    if (max_len > (uint32_t)kPackedMaxLen) {
+        HC_ENC(false, 1, 1);
+    } else {
+        // FPS codes between accumulator flushes: FPS * max_len <= 32
+        const uint32_t fps = max_len <= 8 ? 4 : max_len <= 16 ? 2 : 1;
+        switch (fps * 8 + qpt) {
+        case 4 * 8 + 4: HC_ENC(true, 4, 4); break;
+        case 4 * 8 + 2: HC_ENC(true, 4, 2); break;
+        case 4 * 8 + 1: HC_ENC(true, 4, 1); break;
+        case 2 * 8 + 4: HC_ENC(true, 2, 4); break;
+        case 2 * 8 + 2: HC_ENC(true, 2, 2); break;
+        case 2 * 8 + 1: HC_ENC(true, 2, 1); break;
+        case 1 * 8 + 2: HC_ENC(true, 1, 2); break;
+        case 1 * 8 + 1: HC_ENC(true, 1, 1); break;
+        default: return hipErrorInvalidValue;  // encode_qpt never pairs these
+        }
+    }
+#undef HC_ENC
     return hipGetLastError();
 }
 
@@ -1060,7 +1145,7 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     const uint32_t S_eff = with_index ? S : B;
     const uint32_t cpb = with_index ? (B + S - 1) / S : 1;
     const dim3 grid((uint32_t)groups);
-    // a round of 16 symbols of <= 16 bits fills at most one ring half (8 words)
+    // a round of R symbols of <= 32 * 16 / R bits stays within one ring half (16 words)
     if (max_len <= 8)
         k_decode_ring<16, 4, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     else if (max_len <= (uint32_t)kLutBits)

@@ -89,10 +89,33 @@ def test_small_workload_1mib(hc, oracle):
 
 
 @pytest.mark.parametrize("B,S", [(16, 0), (48, 16), (4096, 256), (4112, 0), (6016, 512), (16384, 1024),
-                                 (65536, 4096), (262144, 0), (1 << 20, 65536)])
+                                 (65536, 4096), (262144, 0), (1 << 20, 65536),
+                                 # encode tiles of 2 and 4 loads per thread, index entries on every load
+                                 (8192, 16), (8208, 16), (16384, 16), (65536, 48), (32768 + 4096, 32)])
 def test_block_sizes(hc, oracle, B, S):
     x = synth.zipf_bytes(2 * MIB + 333, 1.1, B)
     check_full(hc, oracle, x, B, S, "zipf1.1 ragged")
+
+
+@pytest.mark.parametrize("kind", ["zipf", "uniform", "skewed"])
+@pytest.mark.parametrize("shift_in,shift_out", [(16, 0), (48, 32), (112, 80), (64, 112)])
+def test_decode_unaligned_lines(hc, oracle, kind, shift_in, shift_out):
+    """Stream and output 16-byte aligned but not at the start of a 128-byte
+    line: the decoder's line-wide loads and stores must touch only the chunk's
+    own bytes (neighbouring bytes keep a sentinel)."""
+    x = (synth.zipf_bytes(300_000 + 13, 1.2, 5) if kind == "zipf" else synth.segment_bytes(kind, 300_000 + 13, 5))
+    B, S = 16384, 1024
+    enc = check_full(hc, oracle, x, B, S, f"{kind} unaligned {shift_in}/{shift_out}")
+    sbuf = torch.full((enc.nbytes + 256,), 0xA5, dtype=torch.uint8, device="cuda")
+    sbuf[shift_in:shift_in + enc.nbytes].copy_(enc.stream[: enc.nbytes])
+    obuf = torch.full((x.size + 256,), 0x5A, dtype=torch.uint8, device="cuda")
+    err = hc.new_error_word("cuda")
+    hc.hc_decode_blocks(sbuf[shift_in:], enc.nbytes, x.size, B, enc.codebook, enc.block_off, enc.sub_idx, S,
+                        obuf[shift_out:], err)
+    assert hc.read_error(err) == 0
+    o = obuf.cpu().numpy()
+    assert np.array_equal(o[shift_out:shift_out + x.size], x)
+    assert (o[:shift_out] == 0x5A).all() and (o[shift_out + x.size:] == 0x5A).all()
 
 
 @pytest.mark.parametrize("n", [1, 15, 16, 17, 4095, 4096, 4097, 8191, 8193, 65535, 65536, 65537])
