@@ -222,10 +222,18 @@ __device__ __forceinline__ uint32_t load_syms(const HC_G uint8_t *__restrict__ i
         }
         return kQuadSyms * QPT;
     }
-    const uint32_t m = tl.te - s;  // the ragged end of a block: byte loads
+    // the ragged end of a block: whole words, then the bytes of a last partial word
+    const uint32_t m = tl.te - s;
+    const uint32_t full = m >> 2;
+    const HC_G uint32_t *src32 = (const HC_G uint32_t *)src;
 #pragma unroll
-    for (uint32_t k = 0; k < kQuadSyms * QPT; ++k)
-        if (k < m) w[k >> 2] |= (uint32_t)src[k] << (8 * (k & 3));
+    for (uint32_t i = 0; i < 4 * QPT; ++i)
+        if (i < full) w[i] = src32[i];
+    uint32_t part = 0;
+    for (uint32_t b = 0; b < (m & 3u); ++b) part |= (uint32_t)src[4 * full + b] << (8 * b);
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * QPT; ++i)
+        if (i == full && (m & 3u)) w[i] = part;
     return m;
 }
 
@@ -318,8 +326,10 @@ __device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t
 // accumulator flushes (FPS * max_len <= 32); otherwise codes up to 64 bits.
 // QPT: 16-symbol loads per thread; a tile is 4096 * QPT symbols and thread i
 // codes its symbols [16 * QPT * i, 16 * QPT * (i + 1)).
+// The encoder is bound by the latency of its look-backs, so it is built for
+// 8 waves per SIMD (<= 64 VGPRs): 8 work-groups per CU in flight.
 template <bool kPacked, uint32_t FPS, uint32_t QPT>
-__global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B, uint32_t tpb, uint64_t *tstate,
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_encode(JobList jl, uint32_t B, uint32_t tpb, uint64_t *tstate,
                                                          uint64_t *bstate_all, uint32_t S, uint32_t cpb,
                                                          uint32_t lds_words, uint32_t *err)
 {
@@ -363,7 +373,7 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     if (tid < 32) s_next[tid] = tid < avail ? in[tl.blk_start + tl.te + tid] : 0u;
     const uint32_t s = tl.ts + kSyms * tid;
     uint32_t w[4 * QPT];
-    const uint32_t m = load_syms<QPT>(in, tl, s, w);
+    uint32_t m = load_syms<QPT>(in, tl, s, w);
     __syncthreads();  // code tables and the next tile's first symbols are in LDS
 
     // lengths: the thread's bit count, and the bits before each of its loads
@@ -372,9 +382,17 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     bool absent = false;
 #pragma unroll
     for (uint32_t k = 0; k < kSyms; ++k) {
-        if ((k & (kQuadSyms - 1)) == 0) qbits[k / kQuadSyms] = bits;
-        uint32_t L = 0;
-        if (k < m) L = kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
+        if ((k & (kQuadSyms - 1)) == 0) {
+            // one load's lookups at a time: bounds the registers held by reads in flight
+            if (k) __builtin_amdgcn_sched_barrier(0);
+            const uint32_t i = k / 4;  // this load's words become opaque here: no early address math
+            asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]), "+v"(bits));
+            qbits[k / kQuadSyms] = bits;
+        }
+        // the lookup is unconditional (symbols past m read entry 0) and the
+        // result masked, so no branch separates the reads
+        const uint32_t e = kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
+        const uint32_t L = k < m ? e : 0u;
         absent |= (k < m) && (L == 0);
         bits += L;
     }
@@ -385,6 +403,10 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
     if (tid == 0) st_publish(&tstate[t], tl.j == 0 ? kStPrefix : kStAgg, tile_total);
 
     {  // pack at alignment 0
+        // the table entries are read again rather than kept from the length
+        // pass: holding 16*QPT entries per thread across the scan would cost
+        // more registers than the LDS reads cost time
+        asm volatile("" : "+v"(m) : : "memory");  // and the (k < m) masks are recomputed too
         uint32_t widx = q >> 5;
         uint32_t nacc = q & 31u;  // leading zero bits keep the word aligned
         uint64_t acc = 0;
@@ -394,9 +416,15 @@ __global__ __launch_bounds__(kTileThreads) void k_encode(JobList jl, uint32_t B,
             // past m add nothing.
 #pragma unroll
             for (uint32_t k = 0; k < kSyms; k += FPS) {
+                if ((k & (kQuadSyms - 1)) == 0) {
+                    if (k) __builtin_amdgcn_sched_barrier(0);
+                    const uint32_t i = k / 4;
+                    asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]));
+                }
 #pragma unroll
                 for (uint32_t j = 0; j < FPS; ++j) {
-                    const uint32_t e = (k + j < m) ? s_packed[sym_at(w, k + j)] : 0u;
+                    const uint32_t e0 = s_packed[sym_at(w, k + j)];
+                    const uint32_t e = (k + j < m) ? e0 : 0u;
                     const uint32_t L = e & 255u;
                     acc = (acc << L) | (e >> 8);
                     nacc += L;
@@ -729,6 +757,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 // halves always hold what a round can consume.
 constexpr uint32_t kRingHalf = 16;
 constexpr uint32_t kRingWords = 2 * kRingHalf;  // one 128-byte line per lane
+constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
 
 __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32, uint64_t q, uint64_t in_words)
 {
@@ -746,7 +775,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
                                                              uint32_t *err)
 {
     __shared__ uint16_t s_lut[1 << kLutBits];
-    __shared__ uint32_t s_ring[kDecThreads * kRingWords];
+    __shared__ uint32_t s_ring[kDecThreads * kRingStride];
     __shared__ v4u s_stage[kDecThreads * 8];  // one output line per lane
     __shared__ uint32_t s_first[kPackedMaxLen + 1];
     __shared__ uint32_t s_count[kPackedMaxLen + 1];
@@ -856,14 +885,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     // ---- input ring: stream words are counted from the 128-byte line holding
     // the stream's first word (virtual word u = stream word + mis), so line L
     // is virtual words [32L, 32L + 32).  The ring holds halves h and h + 1
-    // (16 words each, word u at slot (u mod 32) ^ swizzle); registers f hold the
+    // (16 words each, word u at slot u mod 32); registers f hold the
     // line of half h + 2.
     const uint64_t in_words = in_bytes >> 2;
     const uint32_t mis = (uint32_t)(((uint64_t)in32 >> 2) & 31u);  // a multiple of 4
     const uint64_t pw0 = (o >> 2) + 1;                             // stream word of payload bit 0
-    uint32_t *ring = s_ring + tid * kRingWords;
-    const uint32_t rsw = (tid >> 1) & 31u;
-    auto rslot = [&](uint64_t u) -> uint32_t { return ((uint32_t)u & 31u) ^ rsw; };
+    uint32_t *ring = s_ring + tid * kRingStride;
+    auto rslot = [&](uint64_t u) -> uint32_t { return (uint32_t)u & (kRingWords - 1); };
     auto load_line = [&](uint64_t L, v4u f[8]) {
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) {
@@ -1000,47 +1028,45 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     uint32_t k = 0;
     if (has_zero_code) {
         // The code '0' (one bit) exists: it is the shortest canonical code, of
-        // symbol sorted[0].  A run of that symbol is a run of leading zero bits,
-        // so each step emits min(leading zeros, symbols left) copies at once and
-        // then, if a '1' follows, decodes one other symbol through the table.
-        // A step consumes at most 32 + max_len bits (two words), which the ring
-        // always holds after advance_ring.
+        // symbol sorted[0].  A run of that symbol is a run of leading zero bits.
+        // The output line is pre-filled with that symbol, so a step only counts
+        // the run (one count-leading-zeros) and, if a '1' follows, decodes one
+        // other symbol through the table and writes that one byte.  A step
+        // consumes at most 32 + max_len bits (two words), which the ring always
+        // holds after advance_ring; it crosses at most one line boundary.
         const uint32_t zsym = s_sorted[0];
-        const uint64_t rep = 0x0101010101010101ull * zsym;
-        uint64_t ob = 0;  // output bytes waiting for a full 8-byte append
-        uint32_t oc = 0;
-        auto emit = [&](uint64_t bytes, uint32_t cnt8) {  // append cnt8 (<= 8) bytes
-            const uint32_t take = cnt8 < 8 - oc ? cnt8 : 8 - oc;
-            ob |= (take == 8 ? bytes : (bytes & ((1ull << (8 * take)) - 1))) << (8 * oc);
-            oc += take;
-            if (oc == 8) {
-                put8(ob);
-                ob = (take < cnt8) ? (bytes >> (8 * take)) & ((1ull << (8 * (cnt8 - take))) - 1) : 0ull;
-                oc = cnt8 - take;
+        const uint32_t rep4 = 0x01010101u * zsym;
+        const v4u rep = v4u{rep4, rep4, rep4, rep4};
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) stage[j] = rep;
+        uint32_t lv = ph & ~127u;  // virtual start of the line being filled (0)
+        auto cross = [&]() {       // the line is complete once ph + k reaches its end
+            if (ph + k - lv >= 128u) {
+                flush_line(lv, 8);
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) stage[j] = rep;
+                lv += 128;
             }
         };
         while (k < nsym) {
             advance_ring();
             const uint32_t hi = (uint32_t)(buf >> 32);
             const uint32_t z = hi ? (uint32_t)__clz((int)hi) : 32u;
-            uint32_t r = nsym - k < z ? nsym - k : z;
+            const uint32_t r = nsym - k < z ? nsym - k : z;
             buf <<= r;
             nbits -= r;
             refill();
             k += r;
-            while (r) {
-                const uint32_t c = r < 8 ? r : 8;
-                emit(rep, c);
-                r -= c;
-            }
+            cross();
             if (z < 32 && k < nsym) {  // a '1' follows the run: one other symbol
-                emit(decode_sym(), 1);
+                const uint32_t v = ph + k;
+                reinterpret_cast<uint8_t *>(&stage[((v >> 4) & 7u) ^ osw])[v & 15u] = (uint8_t)decode_sym();
                 refill();
                 k += 1;
+                cross();
             }
         }
-        for (uint32_t q = 0; q < oc; ++q) put1((uint32_t)(ob >> (8 * q)) & 255u);
-        k = nsym;
+        ov = ph + nsym;  // the partial last line, if any, is stored by finish_output
     }
     for (; k + R <= nsym; k += R) {  // full rounds: SPR symbols between refills
         advance_ring();
