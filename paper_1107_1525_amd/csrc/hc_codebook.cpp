@@ -86,7 +86,7 @@ void build_dev_tables(const hc_codebook &cb, DevTables *t)
         if (L <= K) {
             const uint32_t lo = (uint32_t)(cb.code[v] << (K - L));
             const uint32_t hi = (uint32_t)((cb.code[v] + 1) << (K - L));
-            for (uint32_t e = lo; e < hi; ++e) t->lut[e] = (uint16_t)((L << 8) | (uint32_t)v);
+            for (uint32_t e = lo; e < hi; ++e) t->lut[e] = (uint16_t)(((uint32_t)v << 8) | L);
         } else {
             t->lut[cb.code[v] >> (L - K)] = kLutLong;
         }

@@ -10,11 +10,14 @@ namespace hc {
 constexpr int kNumSym = 256;
 constexpr int kMaxLen = 64;
 constexpr int kLutBits = 12;  // first-level decode table: 4096 entries
-// Decode table entry: (len << 8) | symbol for a code of len <= lut_bits bits;
-// kLutLong if the prefix starts a longer code; kLutInvalid (bit 15, length 1)
-// if no code starts with it.
+// Decode table entry: (symbol << 8) | len for a code of len <= lut_bits bits;
+// kLutLong if the prefix starts a longer code; kLutInvalid if no code starts
+// with it: flag bit 7 in the length byte, and a shift of 1 in its low 6 bits
+// (a decoder may shift by the entry's low 6 bits without a test; bit 7 then
+// marks the stream corrupt).
 constexpr uint16_t kLutLong = 0;
-constexpr uint16_t kLutInvalid = 0x8100;
+constexpr uint16_t kLutInvalid = 0x0081;
+constexpr uint32_t kLutBadFlag = 0x80;
 constexpr int kPackedMaxLen = 24;        // codes up to 24 bits fit (code << 8 | len) in a u32
 
 // Device-resident tables of one codebook (one contiguous allocation).
@@ -22,7 +25,7 @@ struct DevTables {
     uint32_t enc_packed[kNumSym];  // (code << 8) | len, valid when max_len <= kPackedMaxLen
     uint64_t enc_code[kNumSym];    // right-aligned canonical code values
     uint32_t enc_len[kNumSym];     // code lengths, 0 = no code
-    uint16_t lut[1 << kLutBits];   // next lut_bits bits -> (len << 8) | symbol
+    uint16_t lut[1 << kLutBits];   // next lut_bits bits -> (symbol << 8) | len
     uint64_t first[kMaxLen + 1];   // first canonical code value of each length
     uint32_t count[kMaxLen + 1];   // number of codes of each length
     uint32_t base[kMaxLen + 1];    // position in 'sorted' of the first code of each length

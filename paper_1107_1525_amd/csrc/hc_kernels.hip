@@ -13,6 +13,8 @@
 //                  per chunk of S symbols when a sub-block index is given
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "hc_internal.h"
 #include "hc_kernels.h"
 
@@ -376,66 +378,86 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     uint32_t m = load_syms<QPT>(in, tl, s, w);
     __syncthreads();  // code tables and the next tile's first symbols are in LDS
 
-    // lengths: the thread's bit count, and the bits before each of its loads
+    // The thread's symbols are coded twice from the LDS table: once for their
+    // bit count (before the group scan), once to pack them (after it).  Holding
+    // 16*QPT table entries per thread across the scan would cost more registers
+    // than the second reads cost time.  Waves whose threads all hold full
+    // loads take the variant without per-symbol masks (kMask false); only the
+    // wave with the ragged end of a block needs them (symbols past m then
+    // read entry 0 and are masked to zero).
+    const bool wave_full = __all(m == kSyms);
     uint32_t bits = 0;
     uint32_t qbits[QPT];
-    bool absent = false;
+    auto count_bits = [&](auto mask_tag) {
+        constexpr bool kMask = decltype(mask_tag)::value;
+        uint32_t mn = 255u;  // the smallest code length met: 0 = a symbol without a code
 #pragma unroll
-    for (uint32_t k = 0; k < kSyms; ++k) {
-        if ((k & (kQuadSyms - 1)) == 0) {
-            // one load's lookups at a time: bounds the registers held by reads in flight
-            if (k) __builtin_amdgcn_sched_barrier(0);
-            const uint32_t i = k / 4;  // this load's words become opaque here: no early address math
-            asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]), "+v"(bits));
-            qbits[k / kQuadSyms] = bits;
+        for (uint32_t k = 0; k < kSyms; ++k) {
+            if ((k & (kQuadSyms - 1)) == 0) {
+                // one load's lookups at a time: bounds the registers held by reads in flight
+                if (k) __builtin_amdgcn_sched_barrier(0);
+                const uint32_t i = k / 4;  // this load's words become opaque here: no early address math
+                asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]), "+v"(bits));
+                qbits[k / kQuadSyms] = bits;
+            }
+            const uint32_t e = kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
+            const uint32_t L = (!kMask || k < m) ? e : 0u;
+            mn = min(mn, (!kMask || k < m) ? e : 255u);
+            bits += L;
         }
-        // the lookup is unconditional (symbols past m read entry 0) and the
-        // result masked, so no branch separates the reads
-        const uint32_t e = kPacked ? (s_packed[sym_at(w, k)] & 255u) : s_len[sym_at(w, k)];
-        const uint32_t L = k < m ? e : 0u;
-        absent |= (k < m) && (L == 0);
-        bits += L;
-    }
-    if (absent) report(err, HC_ERR_SYMBOL_ABSENT);
+        if (mn == 0) report(err, HC_ERR_SYMBOL_ABSENT);
+    };
+    if (wave_full)
+        count_bits(std::integral_constant<bool, false>());
+    else
+        count_bits(std::integral_constant<bool, true>());
     uint32_t tile_total;
     const uint32_t q = group_exclusive_scan<uint32_t, kTileThreads>(bits, s_scan, &tile_total);
 
     if (tid == 0) st_publish(&tstate[t], tl.j == 0 ? kStPrefix : kStAgg, tile_total);
 
     {  // pack at alignment 0
-        // the table entries are read again rather than kept from the length
-        // pass: holding 16*QPT entries per thread across the scan would cost
-        // more registers than the LDS reads cost time
-        asm volatile("" : "+v"(m) : : "memory");  // and the (k < m) masks are recomputed too
+        asm volatile("" : "+v"(m) : : "memory");  // table reads and (k < m) masks are redone
         uint32_t widx = q >> 5;
         uint32_t nacc = q & 31u;  // leading zero bits keep the word aligned
         uint64_t acc = 0;
         if (kPacked) {
-            // FPS codes of <= 32/FPS bits between flushes: the accumulator never
-            // exceeds 63 bits, and one flush retires at most one word.  Symbols
-            // past m add nothing.
+            // FPS codes of <= 32/FPS bits are first joined in a 32-bit group
+            // code (the entry's low 5 bits are the length, so one shift-or per
+            // code), then appended to the accumulator, which never exceeds 63
+            // bits; one flush retires at most one word.
+            auto pack = [&](auto mask_tag) {
+                constexpr bool kMask = decltype(mask_tag)::value;
 #pragma unroll
-            for (uint32_t k = 0; k < kSyms; k += FPS) {
-                if ((k & (kQuadSyms - 1)) == 0) {
-                    if (k) __builtin_amdgcn_sched_barrier(0);
-                    const uint32_t i = k / 4;
-                    asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]));
-                }
+                for (uint32_t k = 0; k < kSyms; k += FPS) {
+                    if ((k & (kQuadSyms - 1)) == 0) {
+                        if (k) __builtin_amdgcn_sched_barrier(0);
+                        const uint32_t i = k / 4;
+                        asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]));
+                    }
+                    uint32_t gc = 0, gsum = 0;
 #pragma unroll
-                for (uint32_t j = 0; j < FPS; ++j) {
-                    const uint32_t e0 = s_packed[sym_at(w, k + j)];
-                    const uint32_t e = (k + j < m) ? e0 : 0u;
-                    const uint32_t L = e & 255u;
-                    acc = (acc << L) | (e >> 8);
-                    nacc += L;
+                    for (uint32_t j = 0; j < FPS; ++j) {
+                        const uint32_t e0 = s_packed[sym_at(w, k + j)];
+                        const uint32_t e = (!kMask || k + j < m) ? e0 : 0u;
+                        gc = (gc << (e & 31u)) | (e >> 8);
+                        gsum += e;  // the low byte sums the lengths (<= 32)
+                    }
+                    const uint32_t gl = gsum & 255u;
+                    acc = (acc << gl) | gc;
+                    nacc += gl;
+                    const uint32_t need = nacc >= 32 ? 1u : 0u;
+                    const uint32_t word = (uint32_t)(acc >> ((nacc - 32) & 63u));
+                    atomicOr(&words[widx], need ? word : 0u);
+                    nacc -= need << 5;
+                    acc &= (1ull << nacc) - 1ull;
+                    widx += need;
                 }
-                const uint32_t need = nacc >= 32 ? 1u : 0u;
-                const uint32_t word = (uint32_t)(acc >> ((nacc - 32) & 63u));
-                atomicOr(&words[widx], need ? word : 0u);
-                nacc -= need << 5;
-                acc &= (1ull << nacc) - 1ull;
-                widx += need;
-            }
+            };
+            if (wave_full)
+                pack(std::integral_constant<bool, false>());
+            else
+                pack(std::integral_constant<bool, true>());
         } else {
 #pragma unroll
             for (uint32_t k = 0; k < kSyms; ++k) {
@@ -622,15 +644,15 @@ __device__ __forceinline__ uint32_t decode_one(BitReader &br, const HC_G uint32_
         br.wi += 1;
     }
     const uint32_t e = lut[br.buf >> (64 - K)];
-    const uint32_t L = (e >> 8) & 0x7Fu;
-    if (e & 0x8000u) {  // no code starts with these bits
+    const uint32_t L = e & 0x7Fu;
+    if (e & kLutBadFlag) {  // no code starts with these bits
         bad = true;
         return 0;
     }
     if (L != 0) {
         br.buf <<= L;
         br.nbits -= L;
-        return e & 255u;
+        return e >> 8;
     }
     const uint64_t p = br.pos();
     const uint64_t W = window64(payload, nwords, p);
@@ -770,6 +792,9 @@ __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32,
     return r;
 }
 
+// R symbols per round (8 or 16); refills of the bit buffer follow symbols
+// SPR, 2*SPR, ... of a round and its last symbol (SPR * max_len <= 32);
+// kLong: codes may be longer than the table.
 template <uint32_t R, uint32_t SPR, bool kLong>
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
                                                              uint32_t *err)
@@ -868,8 +893,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         ov += 8;
         if ((ov & 127u) == 0) flush_line(ov - 128, 8);
     };
+    auto stage_byte = [&](uint32_t v) -> uint8_t & {  // the byte at virtual position v of the current line
+        return reinterpret_cast<uint8_t *>(&stage[((v >> 4) & 7u) ^ osw])[v & 15u];
+    };
     auto put1 = [&](uint32_t v) {
-        reinterpret_cast<uint8_t *>(&stage[((ov >> 4) & 7u) ^ osw])[ov & 15u] = (uint8_t)v;
+        stage_byte(ov) = (uint8_t)v;
         ov += 1;
         if ((ov & 127u) == 0) flush_line(ov - 128, 8);
     };
@@ -882,44 +910,46 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         }
     };
 
-    // ---- input ring: stream words are counted from the 128-byte line holding
-    // the stream's first word (virtual word u = stream word + mis), so line L
-    // is virtual words [32L, 32L + 32).  The ring holds halves h and h + 1
-    // (16 words each, word u at slot u mod 32); registers f hold the
-    // line of half h + 2.
+    // ---- input ring.  Stream words are counted from the 128-byte line that
+    // holds the stream's first word (virtual word = stream word + mis), and
+    // from the line of the chunk's first bit on in 32 bits ('local' words
+    // below; local line l = local words [32l, 32l + 32)).  The ring holds
+    // halves h and h + 1 (16 words each, word w at slot w mod 32); registers f
+    // hold the line of half h + 2.
     const uint64_t in_words = in_bytes >> 2;
     const uint32_t mis = (uint32_t)(((uint64_t)in32 >> 2) & 31u);  // a multiple of 4
     const uint64_t pw0 = (o >> 2) + 1;                             // stream word of payload bit 0
+    const uint64_t u0 = pw0 + (p0 >> 5) + mis;                     // virtual word of the chunk's first bit
+    const uint64_t ubase = u0 & ~(uint64_t)31;                     // virtual word of local word 0
+    const int64_t qbase = (int64_t)(ubase >> 2) - (int64_t)(mis >> 2);  // stream quad of local quad 0
     uint32_t *ring = s_ring + tid * kRingStride;
-    auto rslot = [&](uint64_t u) -> uint32_t { return (uint32_t)u & (kRingWords - 1); };
-    auto load_line = [&](uint64_t L, v4u f[8]) {
+    auto load_line = [&](uint32_t l, v4u f[8]) {
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) {
-            const uint64_t qa = 8 * L + j;
-            f[j] = qa >= mis / 4 ? load_quad(in32, qa - mis / 4, in_words) : v4u{0u, 0u, 0u, 0u};
+            const int64_t q = qbase + 8 * (int64_t)l + j;
+            f[j] = q >= 0 ? load_quad(in32, (uint64_t)q, in_words) : v4u{0u, 0u, 0u, 0u};
         }
     };
-    auto put_quad = [&](uint64_t u, v4u v) {
-        ring[rslot(u + 0)] = v.x;
-        ring[rslot(u + 1)] = v.y;
-        ring[rslot(u + 2)] = v.z;
-        ring[rslot(u + 3)] = v.w;
+    auto put_quad = [&](uint32_t w, v4u v) {
+        ring[(w + 0) & 31u] = v.x;
+        ring[(w + 1) & 31u] = v.y;
+        ring[(w + 2) & 31u] = v.z;
+        ring[(w + 3) & 31u] = v.w;
     };
-    const uint64_t u0 = pw0 + (p0 >> 5) + mis;  // virtual word of the chunk's first bit
-    uint64_t h = u0 >> 4;
+    uint32_t nxt = (uint32_t)(u0 - ubase);  // next local word to enter the bit buffer
+    uint32_t h = nxt >> 4;                  // 0 or 1
     v4u f[8];
     {
         v4u a[8];
-        load_line(h >> 1, a);
-        load_line((h >> 1) + 1, f);
+        load_line(0, a);
+        load_line(1, f);
 #pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) put_quad(32 * (h >> 1) + 4 * j, a[j]);
+        for (uint32_t j = 0; j < 8; ++j) put_quad(4 * j, a[j]);
         if (h & 1) {  // half h + 1 is the first half of the next line; h + 2 stays in f
 #pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) put_quad(32 * ((h >> 1) + 1) + 4 * j, f[j]);
+            for (uint32_t j = 0; j < 4; ++j) put_quad(32 + 4 * j, f[j]);
         }
     }
-    uint64_t nxt = u0;  // next virtual word to enter the bit buffer
     // Once nxt has left half h, its slots take half h + 2 from f; after the
     // second half of f's line is placed, f is refilled with the next line.
     auto advance_ring = [&]() {
@@ -949,7 +979,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         const uint32_t ncode = s_count[8];
         uint32_t bad8 = 0;
         auto code_at = [&](uint32_t q) -> uint32_t {  // code of symbol q of the round at nxt
-            const uint32_t c = (ring[rslot(nxt + (q >> 2))] >> (24 - 8 * (q & 3))) & 255u;
+            const uint32_t c = (ring[(nxt + (q >> 2)) & 31u] >> (24 - 8 * (q & 3))) & 255u;
             bad8 |= (uint32_t)(c >= ncode);
             return c;
         };
@@ -979,21 +1009,24 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         return;
     }
 
+    // ---- bit buffer: the next nbits payload bits, most significant first;
+    // 'pre' is the ring word at nxt, read ahead of its refill.
     const uint32_t r0 = (uint32_t)(p0 & 31);
-    uint64_t buf = (((uint64_t)ring[rslot(u0)] << 32) | ring[rslot(u0 + 1)]) << r0;
+    uint64_t buf = (((uint64_t)ring[nxt & 31u] << 32) | ring[(nxt + 1) & 31u]) << r0;
     uint32_t nbits = 64 - r0;
-    nxt = u0 + 2;
-    uint32_t pre = ring[rslot(nxt)];
-    uint32_t bad = 0;  // bit 15: an invalid prefix was met
+    nxt += 2;
+    uint32_t pre = ring[nxt & 31u];
+    uint32_t bad = 0;  // kLutBadFlag: an invalid prefix was met
 
-    // One symbol from the buffer (which holds >= max_len bits here).  Table
-    // entries of invalid prefixes carry bit 15 and length 1, so codes of at
-    // most lut_bits bits need no test; longer codes (kLong) take the
-    // canonical-range search on the buffered bits.
+    // One symbol from the buffer (which holds >= max_len bits here).  The
+    // entry's low byte is the code length; invalid prefixes carry kLutBadFlag
+    // and a shift of 1, so codes of at most lut_bits bits need no test; longer
+    // codes (kLong) take the canonical-range search on the buffered bits.
+    const uint32_t lut_shift = 32 - K;
     auto decode_sym = [&]() -> uint32_t {
-        const uint32_t e = s_lut[(uint32_t)(buf >> 32) >> (32 - K)];
-        uint32_t L = (e >> 8) & 0x7Fu;
-        uint32_t sym = e & 255u;
+        const uint32_t e = s_lut[(uint32_t)(buf >> 32) >> lut_shift];
+        uint32_t L = e & 255u;
+        uint32_t sym = e >> 8;
         bad |= e;
         if (kLong && L == 0) {
             for (uint32_t l = K + 1; l <= max_len; ++l) {
@@ -1006,23 +1039,23 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
                 }
             }
             if (L == 0) {
-                bad |= 0x8000u;
+                bad |= kLutBadFlag;
                 L = 1;
             }
         }
-        buf <<= L;
+        buf <<= (L & 63u);
         nbits -= L;
         return sym;
     };
-    // Tops the buffer up to >= 32 bits with the prefetched next word, without
-    // a branch; the ring word after it is read for the next refill.
+    // Tops the buffer up to >= 32 bits with the word read ahead, without a
+    // branch; the ring word after it is read for the next refill.
     auto refill = [&]() {
-        const uint32_t need = nbits < 32 ? 1u : 0u;
-        const uint64_t add = (uint64_t)pre << ((32 - nbits) & 63u);
-        buf |= need ? add : 0ull;
-        nbits += need << 5;
-        nxt += need;
-        pre = ring[rslot(nxt)];
+        const bool need = nbits < 32;
+        const uint32_t w = need ? pre : 0u;
+        buf |= (uint64_t)w << ((32 - nbits) & 63u);
+        nbits += need ? 32u : 0u;
+        nxt += need ? 1u : 0u;
+        pre = ring[nxt & 31u];
     };
 
     uint32_t k = 0;
@@ -1031,53 +1064,50 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         // symbol sorted[0].  A run of that symbol is a run of leading zero bits.
         // The output line is pre-filled with that symbol, so a step only counts
         // the run (one count-leading-zeros) and, if a '1' follows, decodes one
-        // other symbol through the table and writes that one byte.  A step
-        // consumes at most 32 + max_len bits (two words), which the ring always
-        // holds after advance_ring; it crosses at most one line boundary.
-        const uint32_t zsym = s_sorted[0];
-        const uint32_t rep4 = 0x01010101u * zsym;
+        // other symbol through the table and writes that one byte.  Steps are
+        // grouped in rounds of 16 output symbols (the last round: fewer), so
+        // every lane stores its lines at the same rounds.  A step consumes at
+        // most 16 + max_len bits.
+        const uint32_t rep4 = 0x01010101u * s_sorted[0];
         const v4u rep = v4u{rep4, rep4, rep4, rep4};
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) stage[j] = rep;
-        uint32_t lv = ph & ~127u;  // virtual start of the line being filled (0)
-        auto cross = [&]() {       // the line is complete once ph + k reaches its end
-            if (ph + k - lv >= 128u) {
-                flush_line(lv, 8);
-#pragma unroll
-                for (uint32_t j = 0; j < 8; ++j) stage[j] = rep;
-                lv += 128;
-            }
-        };
         while (k < nsym) {
             advance_ring();
-            const uint32_t hi = (uint32_t)(buf >> 32);
-            const uint32_t z = hi ? (uint32_t)__clz((int)hi) : 32u;
-            const uint32_t r = nsym - k < z ? nsym - k : z;
-            buf <<= r;
-            nbits -= r;
-            refill();
-            k += r;
-            cross();
-            if (z < 32 && k < nsym) {  // a '1' follows the run: one other symbol
-                const uint32_t v = ph + k;
-                reinterpret_cast<uint8_t *>(&stage[((v >> 4) & 7u) ^ osw])[v & 15u] = (uint8_t)decode_sym();
+            const uint32_t want = nsym - k < 16u ? nsym - k : 16u;
+            uint32_t t = 0;
+            while (t < want) {
+                const uint32_t hi = (uint32_t)(buf >> 32);
+                const uint32_t z = hi ? (uint32_t)__clz((int)hi) : 32u;
+                const uint32_t r = want - t < z ? want - t : z;
+                buf <<= r;
+                nbits -= r;
+                t += r;
+                if (t < want) {  // a '1' follows the run: one other symbol
+                    if (max_len > 16) refill();
+                    stage_byte(ov + t) = (uint8_t)decode_sym();
+                    t += 1;
+                }
                 refill();
-                k += 1;
-                cross();
+            }
+            k += want;
+            ov += want;
+            if ((ov & 127u) == 0) {
+                flush_line(ov - 128, 8);
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) stage[j] = rep;
             }
         }
-        ov = ph + nsym;  // the partial last line, if any, is stored by finish_output
     }
-    for (; k + R <= nsym; k += R) {  // full rounds: SPR symbols between refills
+    for (; k + R <= nsym; k += R) {  // full rounds
         advance_ring();
         uint32_t o4[R / 4];
 #pragma unroll
         for (uint32_t q = 0; q < R / 4; ++q) o4[q] = 0;
 #pragma unroll
-        for (uint32_t q = 0; q < R; q += SPR) {
-#pragma unroll
-            for (uint32_t j = 0; j < SPR; ++j) o4[(q + j) >> 2] |= decode_sym() << (8 * ((q + j) & 3));
-            refill();
+        for (uint32_t q = 0; q < R; ++q) {
+            o4[q >> 2] |= decode_sym() << (8 * (q & 3));
+            if ((q + 1) % SPR == 0 || q + 1 == R) refill();
         }
         if (R == 16)
             put16(v4u{o4[0], o4[1], o4[2], o4[3]});
@@ -1096,8 +1126,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         }
     }
     finish_output();
-    const uint64_t pos = 32 * (nxt - mis - pw0) - nbits;
-    if ((bad & 0x8000u) || pos != p1) {
+    const uint64_t pos = 32 * (ubase + nxt - mis - pw0) - nbits;
+    if ((bad & kLutBadFlag) || pos != p1) {
         report(err, HC_ERR_CORRUPT);
         return;
     }
@@ -1174,6 +1204,8 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     // a round of R symbols of <= 32 * 16 / R bits stays within one ring half (16 words)
     if (max_len <= 8)
         k_decode_ring<16, 4, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+    else if (max_len <= 10)
+        k_decode_ring<16, 3, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     else if (max_len <= (uint32_t)kLutBits)
         k_decode_ring<16, 2, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     else if (max_len <= 16)
