@@ -777,6 +777,12 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 //    it is stored as 8 consecutive 16-byte stores when full.
 // A round decodes R symbols with R * max_len <= 16 words, so the two ring
 // halves always hold what a round can consume.
+// Output staging: kSegBytes per lane, stored as whole segments.
+#ifndef HC_DEC_SEG_QUADS
+#define HC_DEC_SEG_QUADS 8
+#endif
+constexpr uint32_t kSegQuads = HC_DEC_SEG_QUADS;
+constexpr uint32_t kSegBytes = 16 * kSegQuads;
 constexpr uint32_t kRingHalf = 16;
 constexpr uint32_t kRingWords = 2 * kRingHalf;  // one 128-byte line per lane
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
@@ -799,9 +805,9 @@ template <uint32_t R, uint32_t SPR, bool kLong>
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
                                                              uint32_t *err)
 {
-    __shared__ uint16_t s_lut[1 << kLutBits];
+    extern __shared__ uint16_t s_lut[];  // 2^lut_bits entries (the launch sizes it for the largest)
     __shared__ uint32_t s_ring[kDecThreads * kRingStride];
-    __shared__ v4u s_stage[kDecThreads * 8];  // one output line per lane
+    __shared__ v4u s_stage[kDecThreads * kSegQuads];  // one output segment per lane
     __shared__ uint32_t s_first[kPackedMaxLen + 1];
     __shared__ uint32_t s_count[kPackedMaxLen + 1];
     __shared__ uint32_t s_base[kPackedMaxLen + 1];
@@ -868,42 +874,42 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         return;
     }
 
-    // ---- output line: bytes are appended at virtual position ov = ph + bytes
-    // written, ph = the chunk start's offset in its 128-byte line (a multiple
-    // of 16); quad j of the lane's line sits at LDS quad j ^ (lane & 7) so 8
-    // consecutive lanes touch distinct banks.
+    // ---- output segment: bytes are appended at virtual position ov = ph +
+    // bytes written, ph = the chunk start's offset in its kSegBytes-aligned
+    // segment (a multiple of 16); quad j of the lane's segment sits at LDS quad
+    // j ^ (lane mod kSegQuads) so consecutive lanes touch distinct banks.
     HC_G uint8_t *const dst = out + blk_start + s0;
-    const uint32_t ph = (uint32_t)((uint64_t)dst & 127u);
+    const uint32_t ph = (uint32_t)((uint64_t)dst & (kSegBytes - 1));
     uint32_t ov = ph;
-    v4u *stage = s_stage + tid * 8;
-    const uint32_t osw = tid & 7u;
-    auto flush_line = [&](uint32_t lv, uint32_t jto) {  // quads [.., jto) of the line at virtual lv
+    v4u *stage = s_stage + tid * kSegQuads;
+    const uint32_t osw = tid & (kSegQuads - 1);
+    auto flush_line = [&](uint32_t lv, uint32_t jto) {  // quads [.., jto) of the segment at virtual lv
         const uint32_t jfrom = lv < ph ? (ph - lv) >> 4 : 0u;
 #pragma unroll
-        for (uint32_t j = 0; j < 8; ++j)
+        for (uint32_t j = 0; j < kSegQuads; ++j)
             if (j >= jfrom && j < jto) *(HC_G v4u *)(dst + ((int64_t)(lv + 16 * j) - (int64_t)ph)) = stage[j ^ osw];
     };
     auto put16 = [&](v4u v) {  // ov is a multiple of 16
-        stage[((ov >> 4) & 7u) ^ osw] = v;
+        stage[((ov >> 4) & (kSegQuads - 1)) ^ osw] = v;
         ov += 16;
-        if ((ov & 127u) == 0) flush_line(ov - 128, 8);
+        if ((ov & (kSegBytes - 1)) == 0) flush_line(ov - kSegBytes, kSegQuads);
     };
     auto put8 = [&](uint64_t v) {  // ov is a multiple of 8
-        reinterpret_cast<uint64_t *>(&stage[((ov >> 4) & 7u) ^ osw])[(ov >> 3) & 1u] = v;
+        reinterpret_cast<uint64_t *>(&stage[((ov >> 4) & (kSegQuads - 1)) ^ osw])[(ov >> 3) & 1u] = v;
         ov += 8;
-        if ((ov & 127u) == 0) flush_line(ov - 128, 8);
+        if ((ov & (kSegBytes - 1)) == 0) flush_line(ov - kSegBytes, kSegQuads);
     };
-    auto stage_byte = [&](uint32_t v) -> uint8_t & {  // the byte at virtual position v of the current line
-        return reinterpret_cast<uint8_t *>(&stage[((v >> 4) & 7u) ^ osw])[v & 15u];
+    auto stage_byte = [&](uint32_t v) -> uint8_t & {  // the byte at virtual position v of the current segment
+        return reinterpret_cast<uint8_t *>(&stage[((v >> 4) & (kSegQuads - 1)) ^ osw])[v & 15u];
     };
     auto put1 = [&](uint32_t v) {
         stage_byte(ov) = (uint8_t)v;
         ov += 1;
-        if ((ov & 127u) == 0) flush_line(ov - 128, 8);
+        if ((ov & (kSegBytes - 1)) == 0) flush_line(ov - kSegBytes, kSegQuads);
     };
-    auto finish_output = [&]() {  // the last line, in part
-        if (ov & 127u) {
-            const uint32_t lv = ov & ~127u, jl = (ov & 127u) >> 4, tail = ov & 15u;
+    auto finish_output = [&]() {  // the last segment, in part
+        if (ov & (kSegBytes - 1)) {
+            const uint32_t lv = ov & ~(kSegBytes - 1), jl = (ov & (kSegBytes - 1)) >> 4, tail = ov & 15u;
             flush_line(lv, jl);
             const uint8_t *sb = reinterpret_cast<const uint8_t *>(&stage[jl ^ osw]);
             for (uint32_t q = 0; q < tail; ++q) dst[(int64_t)(lv + 16 * jl + q) - (int64_t)ph] = sb[q];
@@ -1065,16 +1071,16 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         // The output line is pre-filled with that symbol, so a step only counts
         // the run (one count-leading-zeros) and, if a '1' follows, decodes one
         // other symbol through the table and writes that one byte.  Steps are
-        // grouped in rounds of 16 output symbols (the last round: fewer), so
-        // every lane stores its lines at the same rounds.  A step consumes at
-        // most 16 + max_len bits.
+        // grouped in rounds of R output symbols (the last round: fewer), so
+        // every lane stores its segments at the same rounds.  A step consumes
+        // at most R + max_len bits, a round at most R * max_len.
         const uint32_t rep4 = 0x01010101u * s_sorted[0];
         const v4u rep = v4u{rep4, rep4, rep4, rep4};
 #pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) stage[j] = rep;
+        for (uint32_t j = 0; j < kSegQuads; ++j) stage[j] = rep;
         while (k < nsym) {
             advance_ring();
-            const uint32_t want = nsym - k < 16u ? nsym - k : 16u;
+            const uint32_t want = nsym - k < R ? nsym - k : R;
             uint32_t t = 0;
             while (t < want) {
                 const uint32_t hi = (uint32_t)(buf >> 32);
@@ -1092,10 +1098,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             }
             k += want;
             ov += want;
-            if ((ov & 127u) == 0) {
-                flush_line(ov - 128, 8);
+            if ((ov & (kSegBytes - 1)) == 0) {
+                flush_line(ov - kSegBytes, kSegQuads);
 #pragma unroll
-                for (uint32_t j = 0; j < 8; ++j) stage[j] = rep;
+                for (uint32_t j = 0; j < kSegQuads; ++j) stage[j] = rep;
             }
         }
     }
@@ -1201,17 +1207,19 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     const uint32_t S_eff = with_index ? S : B;
     const uint32_t cpb = with_index ? (B + S - 1) / S : 1;
     const dim3 grid((uint32_t)groups);
+    // the table has 2^lut_bits entries, lut_bits = min(max_len, kLutBits) of the longest code
+    const size_t lut = (size_t)2 << (max_len < (uint32_t)kLutBits ? max_len : (uint32_t)kLutBits);
     // a round of R symbols of <= 32 * 16 / R bits stays within one ring half (16 words)
     if (max_len <= 8)
-        k_decode_ring<16, 4, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 4, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
     else if (max_len <= 10)
-        k_decode_ring<16, 3, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 3, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
     else if (max_len <= (uint32_t)kLutBits)
-        k_decode_ring<16, 2, false><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 2, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
     else if (max_len <= 16)
-        k_decode_ring<16, 2, true><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 2, true><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
     else if (max_len <= (uint32_t)kPackedMaxLen)  // 8 symbols of <= 24 bits: 6 words
-        k_decode_ring<8, 1, true><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<8, 1, true><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
     else
         k_decode<<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     return hipGetLastError();
