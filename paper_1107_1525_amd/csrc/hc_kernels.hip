@@ -787,15 +787,16 @@ constexpr uint32_t kRingHalf = 16;
 constexpr uint32_t kRingWords = 2 * kRingHalf;  // one 128-byte line per lane
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
 
-__device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32, uint64_t q, uint64_t in_words)
+// Stream quad q (16 bytes), with q clamped to the quads that hold stream
+// words: one load, no branch, so nothing waits for it before its data is
+// used.  The stream is 16-byte aligned, so the quad of its last word lies in
+// the same page and may be read whole; words past the stream end (or before
+// its start) only ever reach bit-buffer positions after a chunk's last code,
+// which no decoded symbol depends on.
+__device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32, int64_t q, int64_t q_last)
 {
-    const uint64_t w = q * 4;
-    if (w + 4 <= in_words) return *(const HC_G v4u *)(in32 + w);
-    v4u r = {0u, 0u, 0u, 0u};
-    if (w + 0 < in_words) r.x = in32[w + 0];
-    if (w + 1 < in_words) r.y = in32[w + 1];
-    if (w + 2 < in_words) r.z = in32[w + 2];
-    return r;
+    q = q < 0 ? 0 : (q > q_last ? q_last : q);
+    return *(const HC_G v4u *)(in32 + 4 * q);
 }
 
 // R symbols per round (8 or 16); refills of the bit buffer follow symbols
@@ -885,9 +886,20 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     const uint32_t osw = tid & (kSegQuads - 1);
     auto flush_line = [&](uint32_t lv, uint32_t jto) {  // quads [.., jto) of the segment at virtual lv
         const uint32_t jfrom = lv < ph ? (ph - lv) >> 4 : 0u;
+        HC_G uint8_t *seg = dst + ((int64_t)lv - (int64_t)ph);
+        if (jfrom == 0 && jto == kSegQuads) {
+            // a whole segment: all quads read first, then stored back to back,
+            // so no store waits for an earlier one to release its registers
+            v4u q[kSegQuads];
 #pragma unroll
-        for (uint32_t j = 0; j < kSegQuads; ++j)
-            if (j >= jfrom && j < jto) *(HC_G v4u *)(dst + ((int64_t)(lv + 16 * j) - (int64_t)ph)) = stage[j ^ osw];
+            for (uint32_t j = 0; j < kSegQuads; ++j) q[j] = stage[j ^ osw];
+#pragma unroll
+            for (uint32_t j = 0; j < kSegQuads; ++j) *(HC_G v4u *)(seg + 16 * j) = q[j];
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < kSegQuads; ++j)
+                if (j >= jfrom && j < jto) *(HC_G v4u *)(seg + 16 * j) = stage[j ^ osw];
+        }
     };
     auto put16 = [&](v4u v) {  // ov is a multiple of 16
         stage[((ov >> 4) & (kSegQuads - 1)) ^ osw] = v;
@@ -929,12 +941,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     const uint64_t ubase = u0 & ~(uint64_t)31;                     // virtual word of local word 0
     const int64_t qbase = (int64_t)(ubase >> 2) - (int64_t)(mis >> 2);  // stream quad of local quad 0
     uint32_t *ring = s_ring + tid * kRingStride;
+    const int64_t q_last = (int64_t)((in_words - 1) >> 2);  // quad of the stream's last word
     auto load_line = [&](uint32_t l, v4u f[8]) {
 #pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) {
-            const int64_t q = qbase + 8 * (int64_t)l + j;
-            f[j] = q >= 0 ? load_quad(in32, (uint64_t)q, in_words) : v4u{0u, 0u, 0u, 0u};
-        }
+        for (uint32_t j = 0; j < 8; ++j) f[j] = load_quad(in32, qbase + 8 * (int64_t)l + j, q_last);
     };
     auto put_quad = [&](uint32_t w, v4u v) {
         ring[(w + 0) & 31u] = v.x;
