@@ -291,77 +291,43 @@ __device__ __forceinline__ uint64_t st_peek(const uint64_t *p)
 
 // Called by all 64 lanes of one wave.  Returns the sum of the values of
 // elements [lo, idx) of a segment whose first element lo publishes PREFIX.
-// One poll reads a window of 4 * 64 predecessors (four loads per lane in
-// flight) and consumes it chunk by chunk from the nearest: an all-AGGREGATE
-// chunk is added and the walk goes on; a chunk with a PREFIX ends it; a chunk
-// with an unpublished element makes the wave sleep briefly and poll again
-// from there.  On success the wave also publishes PREFIX for every element of
-// its last window that had only its aggregate (the inclusive sums follow from
-// the prefix found and the aggregates read), so the walks of later elements
-// stop near them instead of walking back over the same aggregates.
-__device__ uint64_t wave_lookback(uint64_t *states, uint64_t idx, uint64_t lo, uint32_t *err)
+__device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t lo, uint32_t *err)
 {
-    constexpr uint32_t kChunks = 4;
     const uint32_t lane = threadIdx.x & 63;
     uint64_t acc = 0;
-    uint64_t end = idx;  // chunk r of a poll covers elements end - 1 - lane - 64r
+    uint64_t end = idx;  // the window covers elements end-1-lane
     for (uint32_t spins = 0;; ++spins) {
         if (spins == kLookbackSpinLimit) {
             report(err, HC_ERR_TIMEOUT);
             return acc;
         }
-        uint64_t st[kChunks];
-#pragma unroll
-        for (uint32_t r = 0; r < kChunks; ++r) {
-            const uint64_t back = 1 + lane + 64 * r;
-            st[r] = end >= lo + back ? st_peek(&states[end - back]) : kStPrefix;
-        }
-        const uint64_t end0 = end;
-        uint64_t tot[kChunks];  // totals of the all-aggregate chunks consumed in this poll
-        bool wait = false;
-#pragma unroll
-        for (uint32_t r = 0; r < kChunks; ++r) {
-            const uint64_t flag = st[r] >> 62;
-            const uint64_t v = st[r] & kStValue;
-            const uint64_t prefix_mask = __ballot(flag == 2);
-            const uint64_t missing_mask = __ballot(flag == 0);
-            if (prefix_mask) {
-                const uint32_t first = (uint32_t)__ffsll((unsigned long long)prefix_mask) - 1;
-                const uint64_t before = first ? ((1ull << first) - 1) : 0ull;
-                if (missing_mask & before) {  // an element nearer than the prefix is not published yet
-                    wait = true;
-                    break;
-                }
-                // inclusive sums, from the prefix towards idx: chunk r, lanes first-1 .. 0,
-                // then chunks r-1 .. 0 of this poll, lanes 63 .. 0
-                const uint64_t pv = __shfl(v, (int)first, 64);  // inclusive sum at the prefix element
-                const uint64_t x = lane < first ? v : 0ull;
-                const uint64_t t_r = wave_sum(x);
-                const uint64_t sfx = t_r - (wave_inclusive_scan(x) - x);  // sum of x over lanes >= lane
-                if (lane < first && flag == 1) st_publish(&states[end0 - 1 - lane - 64 * r], kStPrefix, pv + sfx);
-                uint64_t base = pv + t_r;
-                const uint64_t found = acc + base;
-#pragma unroll
-                for (uint32_t q = r; q-- > 0;) {  // chunks nearer than r, all aggregates
-                    const uint64_t vq = st[q] & kStValue;
-                    const uint64_t sq = tot[q] - (wave_inclusive_scan(vq) - vq);
-                    st_publish(&states[end0 - 1 - lane - 64 * q], kStPrefix, base + sq);
-                    base += tot[q];
-                }
-                return found;
+        const bool inside = end >= lo + 1 + lane;
+        const uint64_t st = inside ? st_peek(&states[end - 1 - lane]) : kStPrefix;
+        const uint64_t flag = st >> 62;
+        const uint64_t prefix_mask = __ballot(flag == 2);
+        const uint64_t missing_mask = __ballot(flag == 0);
+        if (prefix_mask) {
+            const uint32_t first = (uint32_t)__ffsll((unsigned long long)prefix_mask) - 1;
+            const uint64_t before = first ? ((1ull << first) - 1) : 0ull;
+            if (missing_mask & before) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
             }
-            if (missing_mask) {
-                wait = true;
-                break;
-            }
-            tot[r] = wave_sum(v);
-            acc += tot[r];
-            end -= 64;
+            return acc + wave_sum(lane <= first ? (st & kStValue) : 0ull);
         }
-        if (wait) __builtin_amdgcn_s_sleep(1);
+        if (missing_mask) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        acc += wave_sum(st & kStValue);
+        end -= 64;
     }
 }
 
+// kPacked: codes of <= 24 bits from the packed table, FPS codes between
+// accumulator flushes (FPS * max_len <= 32); otherwise codes up to 64 bits.
+// QPT: 16-symbol loads per thread; a tile is 4096 * QPT symbols and thread i
+// codes its symbols [16 * QPT * i, 16 * QPT * (i + 1)).
 // The encoder is bound by the latency of its look-backs, so it is built for
 // 8 waves per SIMD (<= 64 VGPRs): 8 work-groups per CU in flight.
 template <bool kPacked, uint32_t FPS, uint32_t QPT>
@@ -812,7 +778,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 // A round decodes R symbols with R * max_len <= 16 words, so the two ring
 // halves always hold what a round can consume.
 // Output staging: kSegBytes per lane, stored as whole segments.
-constexpr uint32_t kSegQuads = 8;  // one 128-byte line
+#ifndef HC_DEC_SEG_QUADS
+#define HC_DEC_SEG_QUADS 8
+#endif
+constexpr uint32_t kSegQuads = HC_DEC_SEG_QUADS;
 constexpr uint32_t kSegBytes = 16 * kSegQuads;
 constexpr uint32_t kRingHalf = 16;
 constexpr uint32_t kRingWords = 2 * kRingHalf;  // one 128-byte line per lane
