@@ -219,7 +219,7 @@ extern "C" uint64_t hc_encode_workspace_bytes(uint64_t n, uint32_t block_size)
 {
     if (block_size == 0) return 0;
     const uint64_t nb = num_blocks(n, block_size);
-    return 8 * encode_state_words(nb * tiles_per_block(block_size, 1), nb);  // the smallest tile: an upper bound
+    return 8 * encode_scratch_words(nb * tiles_per_block(block_size, 1));  // the smallest tile: an upper bound
 }
 
 extern "C" uint64_t hc_sub_index_entries(uint64_t n, uint32_t block_size, uint32_t sub_block)
@@ -340,7 +340,7 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
     const uint32_t qpt = encode_qpt(block_size, cb->host.max_len);
     const uint64_t tiles = nb * tiles_per_block(block_size, qpt);
     if (!d_ws || !aligned(d_ws, 8)) return HC_ERR_INVALID_ARG;
-    if (ws_bytes < 8 * encode_state_words(tiles, nb)) return HC_ERR_NO_SPACE;
+    if (ws_bytes < 8 * encode_scratch_words(tiles)) return HC_ERR_NO_SPACE;
     if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;  // grid limit
     Job j = empty_job();
     j.in = d_in;
@@ -349,7 +349,7 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
     j.out = d_out;
     j.block_off = d_block_off;
     j.sub_idx = d_sub_idx;
-    return hip_status(launch_encode(single(j), tiles, nb, block_size, qpt, cb->host.max_len, sub_block,
+    return hip_status(launch_encode(single(j), tiles, block_size, qpt, cb->host.max_len, sub_block,
                                     static_cast<uint64_t *>(d_ws), d_err, s));
 }
 
@@ -386,13 +386,9 @@ extern "C" hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, ui
 extern "C" uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size)
 {
     if (!items || block_size == 0) return 0;
-    uint64_t tiles = 0, blocks = 0;
-    for (uint32_t k = 0; k < count; ++k) {
-        const uint64_t nb = num_blocks(items[k].n, block_size);
-        blocks += nb;
-        tiles += nb * tiles_per_block(block_size, 1);
-    }
-    return job_table_bytes(count) + 8 * encode_state_words(tiles, blocks);
+    uint64_t tiles = 0;
+    for (uint32_t k = 0; k < count; ++k) tiles += num_blocks(items[k].n, block_size) * tiles_per_block(block_size, 1);
+    return job_table_bytes(count) + 8 * encode_scratch_words(tiles);
 }
 
 extern "C" hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes,
@@ -433,7 +429,7 @@ extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint3
     if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
     std::vector<Job> jobs(count);
-    uint64_t tiles = 0, blocks = 0;
+    uint64_t tiles = 0;
     uint32_t max_len = 1;
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
@@ -455,15 +451,12 @@ extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint3
         j.block_off = it.block_off;
         j.sub_idx = it.sub_idx;
         j.unit_begin = tiles;
-        j.block_begin = blocks;
-        const uint64_t nb = num_blocks(it.n, block_size);
-        tiles += nb * tpb;
-        blocks += nb;
+        tiles += num_blocks(it.n, block_size) * tpb;
         jobs[k] = j;
     }
     if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
     const uint64_t head = job_table_bytes(count);
-    if (ws_bytes < head + 8 * encode_state_words(tiles, blocks)) return HC_ERR_NO_SPACE;
+    if (ws_bytes < head + 8 * encode_scratch_words(tiles)) return HC_ERR_NO_SPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     JobList jl;
     hc_status st = upload_jobs(jobs, tiles, d_ws, s, &jl);
@@ -471,7 +464,7 @@ extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint3
     for (uint32_t k = 0; k < count; ++k)
         if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
     uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(d_ws) + head);
-    return hip_status(launch_encode(jl, tiles, blocks, block_size, qpt, max_len, sub_block, state, d_err, s));
+    return hip_status(launch_encode(jl, tiles, block_size, qpt, max_len, sub_block, state, d_err, s));
 }
 
 extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,

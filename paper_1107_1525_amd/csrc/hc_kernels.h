@@ -15,10 +15,6 @@ constexpr int kHistTargetGroups = 512; // two 64 KiB-LDS groups per CU on 256 CU
 constexpr int kTileThreads = 256;      // encode work-group size (4 waves)
 constexpr uint32_t kQuadSyms = 16;     // symbols of one 16-byte load
 constexpr uint32_t kTileSyms = kTileThreads * kQuadSyms;  // tile of one load per thread
-// Bound on the look-back waits of the encoder (iterations of a short sleep,
-// about a second): a wait that long means a predecessor never ran, which is
-// reported as HC_ERR_TIMEOUT instead of hanging the device.
-constexpr uint32_t kLookbackSpinLimit = 1u << 20;
 
 constexpr int kDecThreads = 256;
 
@@ -35,7 +31,6 @@ struct Job {
     uint32_t *sub_idx;     // sub-block index or null
     uint64_t *hist;        // histogram: 256 counts
     uint64_t unit_begin;   // first launch unit of the job
-    uint64_t block_begin;  // encode: first entry of the job in the block states
 };
 
 // The jobs of a launch: a device array, or a single job passed by value.
@@ -71,12 +66,13 @@ inline uint64_t hist_chunk(uint64_t total)
     return chunk;
 }
 
-// Encode scratch: tile counter, then one look-back state per tile and per block.
-inline uint64_t encode_state_words(uint64_t tiles, uint64_t blocks) { return 2 + tiles + blocks; }
+// Encode scratch, in 8-byte words: the bit count and the in-block position of
+// every tile (two u32 per tile).
+inline uint64_t encode_scratch_words(uint64_t tiles) { return tiles; }
 
 hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, hipStream_t s);
-hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uint32_t B, uint32_t qpt,
-                         uint32_t max_len, uint32_t S, uint64_t *state, uint32_t *err, hipStream_t s);
+hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t qpt, uint32_t max_len, uint32_t S,
+                         uint64_t *scratch, uint32_t *err, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s);
 hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64_t *block_off,
                        uint32_t *err, hipStream_t s);

@@ -259,81 +259,119 @@ __device__ __forceinline__ void put_bits(uint64_t &acc, uint32_t &nacc, uint32_t
     }
 }
 
-// ---------------------------------------------------------------- single-pass encode
-// One launch does the length pass, the offset scan and the packing.  Work-group
-// t encodes tile t: it packs its code words into LDS at bit alignment 0,
-// publishes its bit count, and learns where its bits go through two decoupled
-// look-backs:
-//   tile states  (per tile)  bits of the block before the tile,
-//   block states (per block) bytes of the stream before the block.
-// A state word holds a 2-bit flag and a 62-bit value: AGGREGATE = this
-// element's own total, PREFIX = the total through this element (from the
-// start of its segment).  The first tile of every block publishes PREFIX at
-// once, so every look-back ends.  The last tile of a block publishes the
-// block's size, then its offset.  A group waits only for tiles with smaller
-// indices; work-groups are dispatched in index order on each XCD, so the
-// smallest unfinished tile is always running and the launch drains.  The
-// waits are bounded all the same: one that outlasts kLookbackSpinLimit
-// reports HC_ERR_TIMEOUT and the group finishes without hanging the device.
-constexpr uint64_t kStAgg = 1ull << 62;
-constexpr uint64_t kStPrefix = 2ull << 62;
-constexpr uint64_t kStValue = (1ull << 62) - 1;
+// ---------------------------------------------------------------- encode
+// Three launches, in the paper's order (section 2.1): the length pass counts
+// the bits of every tile, the offset pass turns them into the position of
+// every tile inside its block and the byte offset of every block, and the
+// packing pass writes each tile's code words there.  No launch waits on
+// another work-group, so every work-group runs from start to end at once.
 
-__device__ __forceinline__ void st_publish(uint64_t *p, uint64_t flag, uint64_t v)
+// Length pass: work-group t sums the code lengths of tile t (the same tile
+// shape as the packing pass) and reports a symbol without a code.
+template <bool kPacked, uint32_t QPT>
+__global__ __launch_bounds__(kTileThreads) void k_count(JobList jl, uint32_t B, uint32_t tpb, uint32_t *tile_bits,
+                                                        uint32_t *err)
 {
-    __hip_atomic_store(p, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t st_peek(const uint64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Called by all 64 lanes of one wave.  Returns the sum of the values of
-// elements [lo, idx) of a segment whose first element lo publishes PREFIX.
-__device__ uint64_t wave_lookback(const uint64_t *states, uint64_t idx, uint64_t lo, uint32_t *err)
-{
-    const uint32_t lane = threadIdx.x & 63;
-    uint64_t acc = 0;
-    uint64_t end = idx;  // the window covers elements end-1-lane
-    for (uint32_t spins = 0;; ++spins) {
-        if (spins == kLookbackSpinLimit) {
-            report(err, HC_ERR_TIMEOUT);
-            return acc;
-        }
-        const bool inside = end >= lo + 1 + lane;
-        const uint64_t st = inside ? st_peek(&states[end - 1 - lane]) : kStPrefix;
-        const uint64_t flag = st >> 62;
-        const uint64_t prefix_mask = __ballot(flag == 2);
-        const uint64_t missing_mask = __ballot(flag == 0);
-        if (prefix_mask) {
-            const uint32_t first = (uint32_t)__ffsll((unsigned long long)prefix_mask) - 1;
-            const uint64_t before = first ? ((1ull << first) - 1) : 0ull;
-            if (missing_mask & before) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            return acc + wave_sum(lane <= first ? (st & kStValue) : 0ull);
-        }
-        if (missing_mask) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        acc += wave_sum(st & kStValue);
-        end -= 64;
+    constexpr uint32_t kSyms = kQuadSyms * QPT;
+    __shared__ uint32_t s_len[kNumSym];
+    __shared__ uint32_t s_red[kTileThreads / 64];
+    __shared__ Job s_job;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t t = blockIdx.x;
+    if (tid < 64) {
+        const uint32_t k = wave_job_of_unit(jl, t);
+        if (tid == 0) s_job = job_at(jl, k);
     }
+    __syncthreads();
+    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
+    s_len[tid] = kPacked ? (tb->enc_packed[tid] & 255u) : tb->enc_len[tid];
+    const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
+    const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
+    const uint32_t s = tl.ts + kSyms * tid;
+    uint32_t w[4 * QPT];
+    const uint32_t m = load_syms<QPT>(in, tl, s, w);  // 0 past the end of the tile
+    __syncthreads();
+    uint32_t bits = 0, mn = 255u;
+#pragma unroll
+    for (uint32_t k = 0; k < kSyms; ++k) {
+        const uint32_t L = s_len[sym_at(w, k)];
+        bits += k < m ? L : 0u;
+        mn = min(mn, k < m ? L : 255u);
+    }
+    if (mn == 0) report(err, HC_ERR_SYMBOL_ABSENT);
+    bits = wave_sum(bits);
+    if ((tid & 63) == 0) s_red[tid >> 6] = bits;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t total = 0;
+#pragma unroll
+        for (int wv = 0; wv < kTileThreads / 64; ++wv) total += s_red[wv];
+        tile_bits[t] = total;
+    }
+}
+
+// Offset pass: work-group k scans job k.  Each thread takes kOffBlocks
+// consecutive blocks per round: the exclusive sums of their tiles' bit counts
+// are the tiles' positions inside the block, the block's size is a 4-byte
+// header plus its payload padded to whole 32-bit words, and a group scan of
+// the threads' byte totals gives every block's offset (the last entry of the
+// table is the stream size).
+constexpr uint32_t kOffThreads = 256;
+constexpr uint32_t kOffBlocks = 16;
+
+__global__ __launch_bounds__(kOffThreads) void k_offsets(JobList jl, uint32_t B, uint32_t tpb,
+                                                         const uint32_t *tile_bits, uint32_t *tile_pos,
+                                                         uint32_t *err)
+{
+    __shared__ uint64_t s_scan[kOffThreads / 64];
+    const Job jb = job_at(jl, blockIdx.x);
+    if (jb.n == 0) return;  // the empty stream's table is written on its own
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nb = num_blocks_dev(jb.n, B);
+    const HC_G uint32_t *tbits = (const HC_G uint32_t *)tile_bits + jb.unit_begin;
+    HC_G uint32_t *tpos = (HC_G uint32_t *)tile_pos + jb.unit_begin;
+    HC_G uint64_t *block_off = (HC_G uint64_t *)jb.block_off;
+    uint64_t carry = 0;
+    for (uint64_t b0 = 0; b0 < nb; b0 += (uint64_t)kOffThreads * kOffBlocks) {
+        const uint64_t first = b0 + (uint64_t)tid * kOffBlocks;
+        uint32_t bytes[kOffBlocks];
+        uint64_t mine = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kOffBlocks; ++i) {
+            const uint64_t b = first + i;
+            bytes[i] = 0;
+            if (b < nb) {
+                uint64_t bits = 0;
+                for (uint32_t j = 0; j < tpb; ++j) {
+                    tpos[b * tpb + j] = (uint32_t)bits;
+                    bits += tbits[b * tpb + j];
+                }
+                if (bits > 0xFFFFFFFFull) report(err, HC_ERR_BLOCK_OVERFLOW);
+                bytes[i] = (uint32_t)(4 + 4 * ((bits + 31) / 32));
+                mine += bytes[i];
+            }
+        }
+        uint64_t total;
+        uint64_t off = carry + group_exclusive_scan<uint64_t, kOffThreads>(mine, s_scan, &total);
+#pragma unroll
+        for (uint32_t i = 0; i < kOffBlocks; ++i) {
+            if (first + i < nb) block_off[first + i] = off;
+            off += bytes[i];
+        }
+        carry += total;
+    }
+    if (tid == 0) block_off[nb] = carry;
 }
 
 // kPacked: codes of <= 24 bits from the packed table, FPS codes between
 // accumulator flushes (FPS * max_len <= 32); otherwise codes up to 64 bits.
 // QPT: 16-symbol loads per thread; a tile is 4096 * QPT symbols and thread i
 // codes its symbols [16 * QPT * i, 16 * QPT * (i + 1)).
-// The encoder is bound by the latency of its look-backs, so it is built for
-// 8 waves per SIMD (<= 64 VGPRs): 8 work-groups per CU in flight.
+// Built for 8 waves per SIMD (<= 64 VGPRs): 8 work-groups per CU in flight.
 template <bool kPacked, uint32_t FPS, uint32_t QPT>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_encode(JobList jl, uint32_t B, uint32_t tpb, uint64_t *tstate,
-                                                         uint64_t *bstate_all, uint32_t S, uint32_t cpb,
-                                                         uint32_t lds_words, uint32_t *err)
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_encode(
+    JobList jl, uint32_t B, uint32_t tpb, const uint32_t *tile_pos, uint32_t S, uint32_t cpb, uint32_t lds_words,
+    uint32_t *err)
 {
     constexpr uint32_t kSyms = kQuadSyms * QPT;  // symbols per thread
     extern __shared__ uint32_t words[];  // the tile's code bits from bit 0, MSB first
@@ -341,7 +379,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     __shared__ uint64_t s_code[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_len[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_scan[kTileThreads / 64];
-    __shared__ uint32_t s_lead, s_bits;
+    __shared__ uint32_t s_lead;
     __shared__ uint32_t s_next[32];  // the first symbols of the next tile of the block
     __shared__ uint64_t s_P, s_O;
     __shared__ Job s_job;
@@ -365,7 +403,6 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
     HC_G uint32_t *__restrict__ out32 = (HC_G uint32_t *)s_job.out;
     HC_G uint32_t *__restrict__ sub_idx = (HC_G uint32_t *)s_job.sub_idx;
-    uint64_t *bstate = bstate_all + s_job.block_begin;
     const uint64_t nb = num_blocks_dev(s_job.n, B);
     const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
     if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
@@ -373,6 +410,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const bool last_tile = tl.te == tl.cnt;
     const uint32_t avail = last_tile ? 0u : (tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32u);
     if (tid < 32) s_next[tid] = tid < avail ? in[tl.blk_start + tl.te + tid] : 0u;
+    if (tid == 32) {  // where the tile's bits go: from the offset pass
+        s_P = tile_pos[t];
+        s_O = ((const HC_G uint64_t *)s_job.block_off)[tl.blk];
+    }
     const uint32_t s = tl.ts + kSyms * tid;
     uint32_t w[4 * QPT];
     uint32_t m = load_syms<QPT>(in, tl, s, w);
@@ -413,8 +454,6 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         count_bits(std::integral_constant<bool, true>());
     uint32_t tile_total;
     const uint32_t q = group_exclusive_scan<uint32_t, kTileThreads>(bits, s_scan, &tile_total);
-
-    if (tid == 0) st_publish(&tstate[t], tl.j == 0 ? kStPrefix : kStAgg, tile_total);
 
     {  // pack at alignment 0
         asm volatile("" : "+v"(m) : : "memory");  // table reads and (k < m) masks are redone
@@ -510,36 +549,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         s_lead = (uint32_t)(lead << (32 - got));
     }
 
-    if (tid < 64) {
-        uint64_t P = 0;
-        if (tl.j > 0) {
-            P = wave_lookback(tstate, t, t - tl.j, err);
-            if (tid == 0) st_publish(&tstate[t], kStPrefix, P + tile_total);
-        }
-        const uint64_t blk_bits = P + tile_total;
-        const uint64_t blk_bytes = 4 + 4 * ((blk_bits + 31) / 32);
-        if (last_tile && tid == 0) {
-            if (blk_bits > 0xFFFFFFFFull) report(err, HC_ERR_BLOCK_OVERFLOW);
-            st_publish(&bstate[tl.blk], tl.blk == 0 ? kStPrefix : kStAgg, blk_bytes);
-        }
-        uint64_t O = 0;
-        if (tl.blk > 0) {
-            O = wave_lookback(bstate, tl.blk, 0, err);
-            if (last_tile && tid == 0) st_publish(&bstate[tl.blk], kStPrefix, O + blk_bytes);
-        }
-        if (tid == 0) {
-            s_P = P;
-            s_O = O;
-            s_bits = (uint32_t)blk_bits;
-            if (last_tile) {
-                HC_G uint64_t *block_off = (HC_G uint64_t *)s_job.block_off;
-                block_off[tl.blk] = O;
-                if (tl.blk + 1 == nb) block_off[nb] = O + blk_bytes;
-            }
-        }
-    }
     __syncthreads();
-
     const uint64_t P = s_P, O = s_O;
     const uint32_t a = (uint32_t)(P & 31);
     HC_G uint32_t *payload = out32 + (O >> 2) + 1 + (P >> 5);
@@ -555,7 +565,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             payload[k] = v;
         }
     }
-    if (last_tile && tid == 0) out32[O >> 2] = s_bits;
+    const uint32_t blk_bits = (uint32_t)P + tile_total;  // the block's bit count, for its last tile
+    if (last_tile && tid == 0) out32[O >> 2] = blk_bits;
     if (sub_idx) {
         // S is a multiple of 16: entries fall on the first symbol of a load
 #pragma unroll
@@ -564,7 +575,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             if (m > kQuadSyms * j && (sj % S) == 0) sub_idx[tl.blk * cpb + sj / S] = (uint32_t)P + q + qbits[j];
         }
         if (last_tile && tid == 0)
-            for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = s_bits;
+            for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = blk_bits;
     }
 }
 
@@ -1161,22 +1172,32 @@ hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, h
     return hipGetLastError();
 }
 
-hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint64_t blocks, uint32_t B, uint32_t qpt,
-                         uint32_t max_len, uint32_t S, uint64_t *state, uint32_t *err, hipStream_t s)
+hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t qpt, uint32_t max_len, uint32_t S,
+                         uint64_t *scratch, uint32_t *err, hipStream_t s)
 {
-    const uint64_t words = encode_state_words(tiles, blocks);
-    uint64_t fill_groups = (words + 255) / 256;
-    if (fill_groups > 4096) fill_groups = 4096;
-    k_fill_u64<<<dim3((uint32_t)fill_groups), 256, 0, s>>>(state, words, 0);
-    if (tiles == 0) return hipGetLastError();
+    if (tiles == 0) return hipSuccess;
     const uint32_t tpb = tiles_per_block(B, qpt);
     const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * qpt * max_len + 31ull) / 32ull + 2);
     const uint32_t cpb = S ? (B + S - 1) / S : 1;
-    uint64_t *tstate = state + 2, *bstate = state + 2 + tiles;
+    uint32_t *tile_bits = reinterpret_cast<uint32_t *>(scratch);
+    uint32_t *tile_pos = tile_bits + tiles;
     const dim3 grid((uint32_t)tiles);
     const size_t lds = lds_words * 4;
-#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tstate, bstate, S, cpb, lds_words, err)
-    if (max_len > (uint32_t)kPackedMaxLen) {
+    const bool packed = max_len <= (uint32_t)kPackedMaxLen;
+    // 1. lengths
+    if (!packed)
+        k_count<false, 1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
+    else if (qpt == 4)
+        k_count<true, 4><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
+    else if (qpt == 2)
+        k_count<true, 2><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
+    else
+        k_count<true, 1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
+    // 2. offsets
+    k_offsets<<<dim3(jl.count), kOffThreads, 0, s>>>(jl, B, tpb, tile_bits, tile_pos, err);
+    // 3. packing
+#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tile_pos, S, cpb, lds_words, err)
+    if (!packed) {
         HC_ENC(false, 1, 1);
     } else {
         // FPS codes between accumulator flushes: FPS * max_len <= 32
