@@ -38,6 +38,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, vendor figure
 METRIC = "compress/decompress GB/s (uncompressed) and % HBM peak; batched p50/p99 latency"
 WORKLOAD = "mixed-4GiB-64x64MiB"
+# the device function each timed launch runs (rocprofv3 names)
+KERNEL_SYMBOL = {"k_hist": "k_hist", "k_count": "k_count", "k_offsets": "k_offsets", "k_encode": "k_encode",
+                 "k_decode": "k_decode_ring"}
 
 
 def parse():
@@ -158,30 +161,94 @@ class Workload:
         hc.hc_decode_batch(self.dec_items, self.B, self.S, self.ws, self.err)
         mark("dec", 1)
 
+    def step_by_kernel(self, ev):
+        """The same pass with the encoder's three steps issued as separate calls
+        (one kernel each), HIP events around every kernel."""
+        hc, torch = self.hc, self.torch
+        it, B, S, ws, err = self.enc_items, self.B, self.S, self.ws, self.err
+        ev["k_hist"][0].record()
+        hc.hc_histogram_batch(self.hist_items, self.hist_ws)
+        ev["k_hist"][1].record()
+        self.hist_host.copy_(self.hist, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        self.cbset.build(self.hist_host.numpy().view("uint64"))
+        for name, fn in (("k_count", hc.hc_encode_lengths_batch), ("k_offsets", hc.hc_encode_offsets_batch),
+                         ("k_encode", hc.hc_encode_pack_batch)):
+            ev[name][0].record()
+            fn(it, B, S, ws, err)
+            ev[name][1].record()
+        ev["k_decode"][0].record()
+        hc.hc_decode_batch(self.dec_items, B, S, ws, err)
+        ev["k_decode"][1].record()
+
+
+KERNELS = ("k_hist", "k_count", "k_offsets", "k_encode", "k_decode")
+
+
+def kernel_times(w, torch, np, reps=20, warmup=3):
+    """Per-kernel GPU time (ms): HIP events recorded around each launch on the
+    stream the library launches on (torch's current stream); warm-ups, then
+    'reps' passes."""
+    E = torch.cuda.Event
+    out = {k: [] for k in KERNELS}
+    for r in range(warmup + reps):
+        ev = {k: (E(enable_timing=True), E(enable_timing=True)) for k in KERNELS}
+        w.step_by_kernel(ev)
+        torch.cuda.synchronize()
+        if r >= warmup:
+            for k in KERNELS:
+                out[k].append(ev[k][0].elapsed_time(ev[k][1]))
+    return out
+
 
 def cpu_baseline(w, oracle, np):
-    """The oracle, single-threaded, on segments 0..2 (one of each kind) of the
-    same workload: counts, code, block encode and strict decode."""
-    t_total = 0.0
-    nbytes = 0
-    for t in range(3):
-        x = w.xs(t).cpu().numpy()
+    """The oracle on segments 0..2 (one of each kind, 192 MiB) of the same
+    workload: counts, code, block encode and strict decode.  Timed twice: on
+    one thread, and block-parallel on every host core the process may use (a
+    thread pool over independent blocks; the oracle's C calls release the
+    interpreter lock), which is the shape of the paper's multi-core coder."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    xs = [w.xs(t).cpu().numpy() for t in range(3)]
+    nbytes = sum(x.size for x in xs)
+    B = w.B
+
+    def one_thread():
+        for x in xs:
+            h = oracle.histogram(x)
+            L, C = oracle.codebook(h)
+            s, off, bits = oracle.encode(x, B, L, C)
+            y = oracle.decode(s, x.size, B, L)
+            assert np.array_equal(y, x)
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+
+    def block_parallel(pool):
+        for x in xs:
+            blocks = [x[i:i + B] for i in range(0, x.size, B)]
+            h = sum(pool.map(oracle.histogram, blocks))
+            L, C = oracle.codebook(h)
+            enc = list(pool.map(lambda b: oracle.encode(b, B, L, C)[0], blocks))
+            dec = list(pool.map(lambda sb: oracle.decode(sb[0], sb[1].size, B, L), zip(enc, blocks)))
+            assert all(np.array_equal(d, b) for d, b in zip(dec, blocks))
+
+    t0 = time.perf_counter()
+    one_thread()
+    t1 = time.perf_counter() - t0
+    with ThreadPoolExecutor(cores) as pool:
         t0 = time.perf_counter()
-        h = oracle.histogram(x)
-        L, C = oracle.codebook(h)
-        s, off, bits = oracle.encode(x, w.B, L, C)
-        y = oracle.decode(s, x.size, w.B, L)
-        t_total += time.perf_counter() - t0
-        assert np.array_equal(y, x)
-        nbytes += x.size
+        block_parallel(pool)
+        tp = time.perf_counter() - t0
     return {
-        "value": round(nbytes / t_total / 1e9, 4),
+        "value": round(nbytes / tp / 1e9, 4),
         "unit": "GB/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
         "sample": f"segments 0-2 (uniform, skewed, fp32) of the 4 GiB mixed workload, {nbytes >> 20} MiB, "
-                  f"B={w.B}: counts + code + block encode + strict decode, one thread",
-        "seconds": round(t_total, 2),
+                  f"B={B}: counts + code + block encode + strict decode, block-parallel over {cores} threads",
+        "seconds": round(tp, 2),
+        "single_core_GBps": round(nbytes / t1 / 1e9, 4),
+        "single_core_seconds": round(t1, 2),
     }
 
 
@@ -454,34 +521,48 @@ def main():
         ms_step = wall * 1e3 / args.steps
         avg = lambda k: float(np.mean([e[k][0].elapsed_time(e[k][1]) for e in evs]))
         hist_ms, enc_ms, dec_ms = avg("hist"), avg("enc"), avg("dec")
+        kt = kernel_times(w, torch, np)
+        if hc.read_error(w.err):
+            raise hc.HcError(hc.read_error(w.err), "kernel timing")
+        assert torch.equal(w.y, w.x), "round trip failed (kernel timing)"
         n = w.n
         C = sum(w.C)
         off_bytes = 8 * (w.nb + 1) * w.nseg
         sub_bytes = 4 * w.nsub * w.nseg
         gb = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
-        # algorithmic bytes: what each phase must move, not what it happens to move
-        hist_alg = n + 8 * 256 * w.nseg
-        enc_alg = n + C + off_bytes + sub_bytes
-        dec_alg = C + n + off_bytes + sub_bytes
+        # algorithmic bytes per launch: what each step must move (scratch of the
+        # implementation, such as per-tile counts, is not counted)
+        alg = {
+            "k_hist": n + 8 * 256 * w.nseg,
+            "k_count": n,
+            "k_offsets": off_bytes,
+            "k_encode": n + C + off_bytes + sub_bytes,
+            "k_decode": C + n + off_bytes + sub_bytes,
+        }
+        kavg = {k: float(np.mean(v)) for k, v in kt.items()}
+        kernels = {
+            k: {"avg_ms": round(kavg[k], 4), "p10_ms": round(float(np.percentile(kt[k], 10)), 4),
+                "p50_ms": round(float(np.percentile(kt[k], 50)), 4), "p90_ms": round(float(np.percentile(kt[k], 90)), 4),
+                "GBps_alg": round(gb(alg[k], kavg[k]), 1), "pct_hbm": round(100 * gb(alg[k], kavg[k]) / HBM_PEAK_GBPS, 1)}
+            for k in KERNELS
+        }
         phases = {
             "hist_GBps": round(gb(n, hist_ms), 1),
             "encode_GBps": round(gb(n, enc_ms), 1),
             "decode_GBps": round(gb(n, dec_ms), 1),
             "compress_GBps": round(gb(n, hist_ms + enc_ms), 1),
             "hist_ms": round(hist_ms, 3), "encode_ms": round(enc_ms, 3), "decode_ms": round(dec_ms, 3),
-            "hist_pct_hbm": round(100 * gb(hist_alg, hist_ms) / HBM_PEAK_GBPS, 1),
-            "encode_pct_hbm": round(100 * gb(enc_alg, enc_ms) / HBM_PEAK_GBPS, 1),
-            "decode_pct_hbm": round(100 * gb(dec_alg, dec_ms) / HBM_PEAK_GBPS, 1),
+            "encode_pct_hbm": round(100 * gb(n + C + off_bytes + sub_bytes, enc_ms) / HBM_PEAK_GBPS, 1),
+            "decode_pct_hbm": round(100 * gb(alg["k_decode"], dec_ms) / HBM_PEAK_GBPS, 1),
             "ratio": round(C / n, 5),
         }
-        cands = {"k_decode_ring": (dec_ms, dec_alg), "k_encode": (enc_ms, enc_alg), "k_hist": (hist_ms, hist_alg)}
-        dominant = max(cands, key=lambda k: cands[k][0])
-        launch_ms, per_launch = cands[dominant]
+        dominant = max(KERNELS, key=lambda k: kavg[k])
+        launch_ms, per_launch = kavg[dominant], alg[dominant]
         achieved = per_launch / (launch_ms * 1e-3) / 1e9
         roofline = {
-            "bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "bound": "hbm", "kernel": KERNEL_SYMBOL[dominant], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": load_traffic(dominant, B, S),
+            "traffic": load_traffic(KERNEL_SYMBOL[dominant], B, S),
             "bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4),
         }
         line = {
@@ -490,7 +571,7 @@ def main():
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": WORKLOAD, "bytes": n, "segments": w.nseg, "block_size": B, "sub_block": S,
                        "parallelism": "single-gpu"},
-            "phases": phases, "roofline": roofline,
+            "phases": phases, "kernels": kernels, "roofline": roofline,
         }
         if not args.no_cpu_baseline and not args.sweep:
             print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)

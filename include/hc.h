@@ -67,9 +67,7 @@ typedef enum {
     HC_ERR_SYMBOL_ABSENT = 4,  /* the input holds a symbol the codebook has no code for */
     HC_ERR_BLOCK_OVERFLOW = 5, /* a block's bit count does not fit the 4-byte header */
     HC_ERR_CORRUPT = 6,        /* the compressed stream is not a valid encoding */
-    HC_ERR_CODE_TOO_LONG = 7,  /* a Huffman code would be longer than 64 bits */
-    HC_ERR_TIMEOUT = 8         /* a bounded wait of a kernel expired (an earlier work-group of the
-                                  encoder never published its size); the outputs are invalid */
+    HC_ERR_CODE_TOO_LONG = 7   /* a Huffman code would be longer than 64 bits */
 } hc_status;
 
 /* Host description of a code: lengths and canonical code values.
@@ -280,9 +278,28 @@ hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, u
 /* launch: tiles of all items are packed by the same kernel; each item's   */
 /* offsets start at 0 in its own stream.                                   */
 /* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: SYMBOL_ABSENT,   */
-/* BLOCK_OVERFLOW, TIMEOUT.                                                 */
+/* BLOCK_OVERFLOW.                                                          */
 hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
+
+/* The three steps of hc_encode_batch as separate calls (section 2.1: the  */
+/* block lengths, the offsets "where the block starts and ends", then the  */
+/* packing), for callers that time or schedule them one by one.  Same      */
+/* arguments as hc_encode_batch; issue them in this order on one stream    */
+/* with the same items and workspace (the workspace carries each tile's    */
+/* bit count from the first step to the second and its in-block position  */
+/* from the second to the third).  Together they equal hc_encode_batch.   */
+/*   lengths: per tile of the input, the sum of its code lengths;           */
+/*            in *d_err: SYMBOL_ABSENT.                                    */
+/*   offsets: block_off of every item (C = block_off[nb]);                  */
+/*            in *d_err: BLOCK_OVERFLOW.                                   */
+/*   pack:    the stream (headers, code words, zero pad) and sub_idx.      */
+hc_status hc_encode_lengths_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                                  void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
+hc_status hc_encode_offsets_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                                  void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
+hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                               void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
 /* hc_decode_blocks for every item (uses in, in_bytes, n, cb, block_off,   */
 /* sub_idx, out).  One launch.                                             */

@@ -9,7 +9,8 @@ names of the C ABI in ``include/hc.h``:
     hc_codebook_upload, hc_codebook_update, hc_codebook_destroy, hc_encode_bound,
     hc_encode_workspace_bytes, hc_sub_index_entries, hc_encode_blocks,
     hc_walk_blocks, hc_decode_blocks, hc_status_str, hc_batch_workspace_bytes,
-    hc_histogram_batch, hc_encode_batch, hc_decode_batch, hc_cbset_create,
+    hc_histogram_batch, hc_encode_batch, hc_encode_lengths_batch, hc_encode_offsets_batch,
+    hc_encode_pack_batch, hc_decode_batch, hc_cbset_create,
     hc_cbset_handle, hc_cbset_build, hc_cbset_destroy (as CodebookSet)
 
 and add two conveniences, ``compress`` and ``decompress``, that chain them.
@@ -37,7 +38,6 @@ HC_ERR_SYMBOL_ABSENT = 4
 HC_ERR_BLOCK_OVERFLOW = 5
 HC_ERR_CORRUPT = 6
 HC_ERR_CODE_TOO_LONG = 7
-HC_ERR_TIMEOUT = 8
 
 
 class HcError(RuntimeError):
@@ -111,6 +111,9 @@ _sigs = {
     "hc_batch_workspace_bytes": ([ctypes.POINTER(hc_item), _u32, _u32], _u64),
     "hc_histogram_batch": ([ctypes.POINTER(hc_item), _u32, _vp, _u64, _vp], _st),
     "hc_encode_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
+    "hc_encode_lengths_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
+    "hc_encode_offsets_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
+    "hc_encode_pack_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_decode_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
 }
 for _name, (_args, _res) in _sigs.items():
@@ -408,6 +411,24 @@ def hc_encode_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, er
                     stream=None) -> None:
     _check(_lib.hc_encode_batch(items, len(items), block_size, sub_block, _ptr(ws), ws.numel(), _ptr(err),
                                 _stream(stream)), "hc_encode_batch")
+
+
+def hc_encode_lengths_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, err: torch.Tensor,
+                            stream=None) -> None:
+    _check(_lib.hc_encode_lengths_batch(items, len(items), block_size, sub_block, _ptr(ws), ws.numel(), _ptr(err),
+                                        _stream(stream)), "hc_encode_lengths_batch")
+
+
+def hc_encode_offsets_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, err: torch.Tensor,
+                            stream=None) -> None:
+    _check(_lib.hc_encode_offsets_batch(items, len(items), block_size, sub_block, _ptr(ws), ws.numel(), _ptr(err),
+                                        _stream(stream)), "hc_encode_offsets_batch")
+
+
+def hc_encode_pack_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, err: torch.Tensor,
+                         stream=None) -> None:
+    _check(_lib.hc_encode_pack_batch(items, len(items), block_size, sub_block, _ptr(ws), ws.numel(), _ptr(err),
+                                     _stream(stream)), "hc_encode_pack_batch")
 
 
 def hc_decode_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, err: torch.Tensor,

@@ -35,7 +35,6 @@ extern "C" const char *hc_status_str(int status)
     case HC_ERR_BLOCK_OVERFLOW: return "HC_ERR_BLOCK_OVERFLOW";
     case HC_ERR_CORRUPT: return "HC_ERR_CORRUPT";
     case HC_ERR_CODE_TOO_LONG: return "HC_ERR_CODE_TOO_LONG";
-    case HC_ERR_TIMEOUT: return "HC_ERR_TIMEOUT";
     default: return "HC_ERR_UNKNOWN";
     }
 }
@@ -350,7 +349,7 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
     j.block_off = d_block_off;
     j.sub_idx = d_sub_idx;
     return hip_status(launch_encode(single(j), tiles, block_size, qpt, cb->host.max_len, sub_block,
-                                    static_cast<uint64_t *>(d_ws), d_err, s));
+                                    static_cast<uint64_t *>(d_ws), d_err, s, kStepAll));
 }
 
 extern "C" hc_status hc_walk_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t nb, uint64_t *d_block_off,
@@ -423,8 +422,14 @@ extern "C" hc_status hc_histogram_batch(const hc_item *items, uint32_t count, vo
     return hip_status(launch_histogram(jl, units, chunk, s));
 }
 
-extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
-                                     void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream)
+namespace {
+
+// The three encode steps over a batch; 'steps' selects which run (bit 0:
+// lengths, bit 1: offsets, bit 2: packing).  Every step re-derives the same
+// job table from the items, so the steps may be issued as separate calls on
+// one stream, with the same workspace.
+hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                             void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream, uint32_t steps)
 {
     if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
@@ -461,10 +466,40 @@ extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint3
     JobList jl;
     hc_status st = upload_jobs(jobs, tiles, d_ws, s, &jl);
     if (st != HC_OK) return st;
-    for (uint32_t k = 0; k < count; ++k)
-        if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
-    uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(d_ws) + head);
-    return hip_status(launch_encode(jl, tiles, block_size, qpt, max_len, sub_block, state, d_err, s));
+    if (steps & kStepOffsets)
+        for (uint32_t k = 0; k < count; ++k)
+            if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(static_cast<char *>(d_ws) + head);
+    return hip_status(launch_encode(jl, tiles, block_size, qpt, max_len, sub_block, scratch, d_err, s, steps));
+}
+
+}  // namespace
+
+extern "C" hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
+                                     void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream)
+{
+    return encode_batch_steps(items, count, block_size, sub_block, d_ws, ws_bytes, d_err, stream, kStepAll);
+}
+
+extern "C" hc_status hc_encode_lengths_batch(const hc_item *items, uint32_t count, uint32_t block_size,
+                                             uint32_t sub_block, void *d_ws, uint64_t ws_bytes, uint32_t *d_err,
+                                             void *stream)
+{
+    return encode_batch_steps(items, count, block_size, sub_block, d_ws, ws_bytes, d_err, stream, kStepLengths);
+}
+
+extern "C" hc_status hc_encode_offsets_batch(const hc_item *items, uint32_t count, uint32_t block_size,
+                                             uint32_t sub_block, void *d_ws, uint64_t ws_bytes, uint32_t *d_err,
+                                             void *stream)
+{
+    return encode_batch_steps(items, count, block_size, sub_block, d_ws, ws_bytes, d_err, stream, kStepOffsets);
+}
+
+extern "C" hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, uint32_t block_size,
+                                          uint32_t sub_block, void *d_ws, uint64_t ws_bytes, uint32_t *d_err,
+                                          void *stream)
+{
+    return encode_batch_steps(items, count, block_size, sub_block, d_ws, ws_bytes, d_err, stream, kStepPack);
 }
 
 extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,

@@ -1173,7 +1173,7 @@ hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, h
 }
 
 hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t qpt, uint32_t max_len, uint32_t S,
-                         uint64_t *scratch, uint32_t *err, hipStream_t s)
+                         uint64_t *scratch, uint32_t *err, hipStream_t s, uint32_t steps)
 {
     if (tiles == 0) return hipSuccess;
     const uint32_t tpb = tiles_per_block(B, qpt);
@@ -1185,7 +1185,9 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t
     const size_t lds = lds_words * 4;
     const bool packed = max_len <= (uint32_t)kPackedMaxLen;
     // 1. lengths
-    if (!packed)
+    if (!(steps & kStepLengths))
+        ;
+    else if (!packed)
         k_count<false, 1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
     else if (qpt == 4)
         k_count<true, 4><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
@@ -1194,10 +1196,11 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t
     else
         k_count<true, 1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
     // 2. offsets
-    k_offsets<<<dim3(jl.count), kOffThreads, 0, s>>>(jl, B, tpb, tile_bits, tile_pos, err);
+    if (steps & kStepOffsets) k_offsets<<<dim3(jl.count), kOffThreads, 0, s>>>(jl, B, tpb, tile_bits, tile_pos, err);
     // 3. packing
 #define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tile_pos, S, cpb, lds_words, err)
-    if (!packed) {
+    if (!(steps & kStepPack)) {
+    } else if (!packed) {
         HC_ENC(false, 1, 1);
     } else {
         // FPS codes between accumulator flushes: FPS * max_len <= 32

@@ -403,6 +403,24 @@ def test_batch_matches_single_and_oracle(hc, oracle, B, S):
     err = hc.new_error_word("cuda")
     hc.hc_encode_batch(items, B, S, ws, err)
     assert hc.read_error(err) == 0
+    # the three step calls give the same bytes as the one-call encode
+    whole = [(o.clone(), f.clone(), None if u is None else u.clone()) for o, f, u in zip(outs, offs, subs)]
+    for o, f, u in zip(outs, offs, subs):
+        o.fill_(0x5A)
+        f.fill_(-1)
+        if u is not None:
+            u.fill_(-1)
+    hc.hc_encode_lengths_batch(items, B, S, ws, err)
+    hc.hc_encode_offsets_batch(items, B, S, ws, err)
+    hc.hc_encode_pack_batch(items, B, S, ws, err)
+    assert hc.read_error(err) == 0
+    for k in range(cnt):
+        C = int(whole[k][1][-1].item())
+        assert torch.equal(outs[k][:C], whole[k][0][:C]), k
+        assert torch.equal(offs[k], whole[k][1]), k
+        if S:
+            m = hc.hc_sub_index_entries(xs[k].size, B, S)
+            assert torch.equal(subs[k][:m], whole[k][2][:m]), k
     ys = []
     for k in range(cnt):
         n = xs[k].size
