@@ -437,6 +437,18 @@ def traffic_summary(root: str, B: int, S: int):
             "bytes_per_launch": int(fetch[k] * 1024 * f_scale + write.get(k, 0.0) * 1024 * w_scale),
             "kernel_source_hash": kernel_source_hash(), "workload": WORKLOAD, "block_size": B, "sub_block": S,
             "copy_kernel": copy_name, "copy_bytes": copy_bytes,
+            "commands": [
+                f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- "
+                f"python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --block {B} --sub-block {S}",
+                f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- "
+                f"python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --block {B} --sub-block {S}",
+                "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/copy_fetch -o run -- "
+                "python -u bench.py --copy-probe",
+                "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/copy_write -o run -- "
+                "python -u bench.py --copy-probe",
+                f"python bench.py --traffic-summary OUT --block {B} --sub-block {S}",
+            ],
+            "OUT": "the directory the four rocprofv3 runs wrote (any path)",
         }
         path = os.path.join(ROOT, "profiles", f"traffic_{short}_{WORKLOAD}_B{B}_S{S}.json")
         if short in out:  # several instantiations: keep the busiest
