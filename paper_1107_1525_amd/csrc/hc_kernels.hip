@@ -403,7 +403,6 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
     HC_G uint32_t *__restrict__ out32 = (HC_G uint32_t *)s_job.out;
     HC_G uint32_t *__restrict__ sub_idx = (HC_G uint32_t *)s_job.sub_idx;
-    const uint64_t nb = num_blocks_dev(s_job.n, B);
     const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
     if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
 
@@ -943,8 +942,17 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     // holds the stream's first word (virtual word = stream word + mis), and
     // from the line of the chunk's first bit on in 32 bits ('local' words
     // below; local line l = local words [32l, 32l + 32)).  The ring holds
-    // halves h and h + 1 (16 words each, word w at slot w mod 32); registers f
-    // hold the line of half h + 2.
+    // halves h and h + 1 (16 words each, word w at slot w mod 32).  Registers
+    // g hold the landed line of half h + 2 (land_halves of its halves still to be
+    // placed: both, or the second), registers f the line after it, in flight.
+    //
+    // A wait for a global load stalls the whole wave, and lanes need their
+    // lines at different times.  So lines are requested only at sync points,
+    // every second round, all lanes together: a lane whose landed line is used
+    // up takes f (requested two rounds ago or earlier) and requests the next
+    // line into f.  Two rounds consume at most 16 words (R * max_len <= 256
+    // bits), so between sync points a lane leaves at most one half and the
+    // landed line always has a half to give.
     const uint64_t in_words = in_bytes >> 2;
     const uint32_t mis = (uint32_t)(((uint64_t)in32 >> 2) & 31u);  // a multiple of 4
     const uint64_t pw0 = (o >> 2) + 1;                             // stream word of payload bit 0
@@ -965,30 +973,44 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     };
     uint32_t nxt = (uint32_t)(u0 - ubase);  // next local word to enter the bit buffer
     uint32_t h = nxt >> 4;                  // 0 or 1
-    v4u f[8];
+    v4u land[8], f[8];
+    uint32_t land_halves, next_line = 3;
     {
         v4u a[8];
         load_line(0, a);
-        load_line(1, f);
+        load_line(1, land);
+        load_line(2, f);
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) put_quad(4 * j, a[j]);
-        if (h & 1) {  // half h + 1 is the first half of the next line; h + 2 stays in f
+        land_halves = 2;
+        if (h & 1) {  // half h + 1 is the first half of line 1
 #pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) put_quad(32 + 4 * j, f[j]);
+            for (uint32_t j = 0; j < 4; ++j) put_quad(32 + 4 * j, land[j]);
+            land_halves = 1;
         }
     }
-    // Once nxt has left half h, its slots take half h + 2 from f; after the
-    // second half of f's line is placed, f is refilled with the next line.
+    auto take_f = [&]() {  // land <- f (landed), f <- the next line
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) land[j] = f[j];
+        land_halves = 2;
+        load_line(next_line++, f);
+    };
+    uint32_t rnd = 0;
+    auto sync_lines = [&]() {  // at the start of every round; acts on every second one
+        if ((rnd++ & 1u) == 0 && land_halves == 0) take_f();
+    };
+    // Once nxt has left half h, its slots take half h + 2 from the landed line.
     auto advance_ring = [&]() {
         if (nxt >= 16 * h + 16) {
-            if ((h & 1) == 0) {
+            if (land_halves == 0) take_f();  // not expected (see above); waits for f
+            if (land_halves == 2) {
 #pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) put_quad(16 * (h + 2) + 4 * j, f[j]);
+                for (uint32_t j = 0; j < 4; ++j) put_quad(16 * (h + 2) + 4 * j, land[j]);
             } else {
 #pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) put_quad(16 * (h + 2) + 4 * j, f[4 + j]);
-                load_line((h + 3) >> 1, f);
+                for (uint32_t j = 0; j < 4; ++j) put_quad(16 * (h + 2) + 4 * j, land[4 + j]);
             }
+            land_halves -= 1;
             h += 1;
         }
     };
@@ -1012,6 +1034,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         };
         uint32_t k = 0;
         for (; k + 16 <= nsym; k += 16) {
+            sync_lines();
             advance_ring();
             uint32_t o4[4];
 #pragma unroll
@@ -1022,6 +1045,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             put16(v4u{o4[0], o4[1], o4[2], o4[3]});
         }
         if (k < nsym) {  // fewer than 16 symbols: at most 4 words from nxt
+            sync_lines();
             advance_ring();
 #pragma unroll
             for (uint32_t q = 0; q < 16; ++q)
@@ -1100,6 +1124,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
 #pragma unroll
         for (uint32_t j = 0; j < kSegQuads; ++j) stage[j] = rep;
         while (k < nsym) {
+            sync_lines();
             advance_ring();
             const uint32_t want = nsym - k < R ? nsym - k : R;
             uint32_t t = 0;
@@ -1127,6 +1152,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         }
     }
     for (; k + R <= nsym; k += R) {  // full rounds
+        sync_lines();
         advance_ring();
         uint32_t o4[R / 4];
 #pragma unroll
@@ -1142,6 +1168,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             put8(((uint64_t)o4[1] << 32) | o4[0]);
     }
     if (k < nsym) {  // the ragged last round: one symbol between refills
+        sync_lines();
         advance_ring();
         const uint32_t m = nsym - k;
 #pragma unroll
