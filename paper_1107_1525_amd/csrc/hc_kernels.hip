@@ -778,23 +778,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 // Same lane mapping and checks as k_decode; what differs is how a lane meets
 // HBM.  Thousands of lanes each stream their own chunk, so a lane that read or
 // wrote 16 bytes at a time would leave partly used 128-byte lines in L2 long
-// enough to be evicted and fetched (or written) again.  Here every HBM access
-// of a lane is a whole line:
-//  * input: a private LDS ring of two 16-word halves; the lane loads a whole
-//    line (8 consecutive 16-byte loads) into registers one half ahead of use
-//    and moves it into the ring half by half as it leaves a half;
-//  * output: a private 128-byte LDS line; decoded bytes are appended to it and
-//    it is stored as 8 consecutive 16-byte stores when full.
-// A round decodes R symbols with R * max_len <= 16 words, so the two ring
-// halves always hold what a round can consume.
-// Output staging: kSegBytes per lane, stored as whole segments.
-#ifndef HC_DEC_SEG_QUADS
-#define HC_DEC_SEG_QUADS 8
-#endif
-constexpr uint32_t kSegQuads = HC_DEC_SEG_QUADS;
-constexpr uint32_t kSegBytes = 16 * kSegQuads;
-constexpr uint32_t kRingHalf = 16;
-constexpr uint32_t kRingWords = 2 * kRingHalf;  // one 128-byte line per lane
+// enough to be evicted and fetched (or written) again.  Here every access of
+// a lane is a whole line: compressed input arrives a 128-byte line at a time
+// (8 consecutive 16-byte loads) into a private LDS ring, and decoded output is
+// gathered in registers and stored a line at a time.
+constexpr uint32_t kRingWords = 64;               // four 16-word halves: two lines
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
 
 // Stream quad q (16 bytes), with q clamped to the quads that hold stream
@@ -812,13 +800,17 @@ __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32,
 // R symbols per round (8 or 16); refills of the bit buffer follow symbols
 // SPR, 2*SPR, ... of a round and its last symbol (SPR * max_len <= 32);
 // kLong: codes may be longer than the table.
+// R symbols per round (8 or 16); refills of the bit buffer follow symbols
+// SPR, 2*SPR, ... of a round and its last symbol (SPR * max_len <= 32);
+// kLong: codes may be longer than the table.
 template <uint32_t R, uint32_t SPR, bool kLong>
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
                                                              uint32_t *err)
 {
+    constexpr uint32_t kRoundWords = R / 4;             // output words of a round
+    constexpr uint32_t kLineRounds = 128 / R;           // rounds of one 128-byte output line
     extern __shared__ uint16_t s_lut[];  // 2^lut_bits entries (the launch sizes it for the largest)
     __shared__ uint32_t s_ring[kDecThreads * kRingStride];
-    __shared__ v4u s_stage[kDecThreads * kSegQuads];  // one output segment per lane
     __shared__ uint32_t s_first[kPackedMaxLen + 1];
     __shared__ uint32_t s_count[kPackedMaxLen + 1];
     __shared__ uint32_t s_base[kPackedMaxLen + 1];
@@ -884,75 +876,30 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         report(err, HC_ERR_CORRUPT);
         return;
     }
-
-    // ---- output segment: bytes are appended at virtual position ov = ph +
-    // bytes written, ph = the chunk start's offset in its kSegBytes-aligned
-    // segment (a multiple of 16); quad j of the lane's segment sits at LDS quad
-    // j ^ (lane mod kSegQuads) so consecutive lanes touch distinct banks.
-    HC_G uint8_t *const dst = out + blk_start + s0;
-    const uint32_t ph = (uint32_t)((uint64_t)dst & (kSegBytes - 1));
-    uint32_t ov = ph;
-    v4u *stage = s_stage + tid * kSegQuads;
-    const uint32_t osw = tid & (kSegQuads - 1);
-    auto flush_line = [&](uint32_t lv, uint32_t jto) {  // quads [.., jto) of the segment at virtual lv
-        const uint32_t jfrom = lv < ph ? (ph - lv) >> 4 : 0u;
-        HC_G uint8_t *seg = dst + ((int64_t)lv - (int64_t)ph);
-        if (jfrom == 0 && jto == kSegQuads) {
-            // a whole segment: all quads read first, then stored back to back,
-            // so no store waits for an earlier one to release its registers
-            v4u q[kSegQuads];
-#pragma unroll
-            for (uint32_t j = 0; j < kSegQuads; ++j) q[j] = stage[j ^ osw];
-#pragma unroll
-            for (uint32_t j = 0; j < kSegQuads; ++j) *(HC_G v4u *)(seg + 16 * j) = q[j];
-        } else {
-#pragma unroll
-            for (uint32_t j = 0; j < kSegQuads; ++j)
-                if (j >= jfrom && j < jto) *(HC_G v4u *)(seg + 16 * j) = stage[j ^ osw];
-        }
-    };
-    auto put16 = [&](v4u v) {  // ov is a multiple of 16
-        stage[((ov >> 4) & (kSegQuads - 1)) ^ osw] = v;
-        ov += 16;
-        if ((ov & (kSegBytes - 1)) == 0) flush_line(ov - kSegBytes, kSegQuads);
-    };
-    auto put8 = [&](uint64_t v) {  // ov is a multiple of 8
-        reinterpret_cast<uint64_t *>(&stage[((ov >> 4) & (kSegQuads - 1)) ^ osw])[(ov >> 3) & 1u] = v;
-        ov += 8;
-        if ((ov & (kSegBytes - 1)) == 0) flush_line(ov - kSegBytes, kSegQuads);
-    };
-    auto stage_byte = [&](uint32_t v) -> uint8_t & {  // the byte at virtual position v of the current segment
-        return reinterpret_cast<uint8_t *>(&stage[((v >> 4) & (kSegQuads - 1)) ^ osw])[v & 15u];
-    };
-    auto put1 = [&](uint32_t v) {
-        stage_byte(ov) = (uint8_t)v;
-        ov += 1;
-        if ((ov & (kSegBytes - 1)) == 0) flush_line(ov - kSegBytes, kSegQuads);
-    };
-    auto finish_output = [&]() {  // the last segment, in part
-        if (ov & (kSegBytes - 1)) {
-            const uint32_t lv = ov & ~(kSegBytes - 1), jl = (ov & (kSegBytes - 1)) >> 4, tail = ov & 15u;
-            flush_line(lv, jl);
-            const uint8_t *sb = reinterpret_cast<const uint8_t *>(&stage[jl ^ osw]);
-            for (uint32_t q = 0; q < tail; ++q) dst[(int64_t)(lv + 16 * jl + q) - (int64_t)ph] = sb[q];
-        }
-    };
+    if (fixed8 && (p0 != 8ull * s0 || p1 != 8ull * s1 || hdr != 8ull * cnt)) {
+        // all codes are 8 bits: the index, the header and the pad must agree
+        report(err, HC_ERR_CORRUPT);
+        return;
+    }
 
     // ---- input ring.  Stream words are counted from the 128-byte line that
     // holds the stream's first word (virtual word = stream word + mis), and
     // from the line of the chunk's first bit on in 32 bits ('local' words
-    // below; local line l = local words [32l, 32l + 32)).  The ring holds
-    // halves h and h + 1 (16 words each, word w at slot w mod 32).  Registers
-    // g hold the landed line of half h + 2 (land_halves of its halves still to be
-    // placed: both, or the second), registers f the line after it, in flight.
+    // below; local line l = local words [32l, 32l + 32)).  The ring holds the
+    // local words of halves [nxt / 16, vend) (16 words each, word w at slot
+    // w mod 64): up to four halves, two lines.
     //
     // A wait for a global load stalls the whole wave, and lanes need their
     // lines at different times.  So lines are requested only at sync points,
-    // every second round, all lanes together: a lane whose landed line is used
-    // up takes f (requested two rounds ago or earlier) and requests the next
-    // line into f.  Two rounds consume at most 16 words (R * max_len <= 256
-    // bits), so between sync points a lane leaves at most one half and the
-    // landed line always has a half to give.
+    // every fourth round (rounds 2 and 6 of an output line, away from the line
+    // stores, which a wait would also cover), by all lanes together: each lane
+    // requests the line
+    // after its ring's end into registers f, and at the next sync point (four
+    // rounds later, when the load has landed) moves it into the ring if two
+    // halves are free, else requests it again (a cache hit).  Four rounds
+    // consume at most 32 words (4 * R * max_len <= 1024 bits), and after a
+    // sync point the ring holds at least three halves from the current word
+    // on, so a round never reads a word the ring does not hold.
     const uint64_t in_words = in_bytes >> 2;
     const uint32_t mis = (uint32_t)(((uint64_t)in32 >> 2) & 31u);  // a multiple of 4
     const uint64_t pw0 = (o >> 2) + 1;                             // stream word of payload bit 0
@@ -965,93 +912,94 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) f[j] = load_quad(in32, qbase + 8 * (int64_t)l + j, q_last);
     };
-    auto put_quad = [&](uint32_t w, v4u v) {
-        ring[(w + 0) & 31u] = v.x;
-        ring[(w + 1) & 31u] = v.y;
-        ring[(w + 2) & 31u] = v.z;
-        ring[(w + 3) & 31u] = v.w;
+    auto put_line = [&](uint32_t l, const v4u f[8]) {  // local line l into its two ring halves
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            const uint32_t w = 32 * l + 4 * j;
+            ring[(w + 0) & 63u] = f[j].x;
+            ring[(w + 1) & 63u] = f[j].y;
+            ring[(w + 2) & 63u] = f[j].z;
+            ring[(w + 3) & 63u] = f[j].w;
+        }
     };
-    uint32_t nxt = (uint32_t)(u0 - ubase);  // next local word to enter the bit buffer
-    uint32_t h = nxt >> 4;                  // 0 or 1
-    v4u land[8], f[8];
-    uint32_t land_halves, next_line = 3;
+    uint32_t nxt = (uint32_t)(u0 - ubase);  // next local word to enter the bit buffer (< 32)
+    uint32_t vend = 4;                      // halves [0, 4) are in the ring after the set-up
+    v4u f[8];
     {
-        v4u a[8];
+        v4u a[8], b[8];
         load_line(0, a);
-        load_line(1, land);
+        load_line(1, b);
         load_line(2, f);
-#pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) put_quad(4 * j, a[j]);
-        land_halves = 2;
-        if (h & 1) {  // half h + 1 is the first half of line 1
-#pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) put_quad(32 + 4 * j, land[j]);
-            land_halves = 1;
-        }
+        put_line(0, a);
+        put_line(1, b);
     }
-    auto take_f = [&]() {  // land <- f (landed), f <- the next line
-#pragma unroll
-        for (uint32_t j = 0; j < 8; ++j) land[j] = f[j];
-        land_halves = 2;
-        load_line(next_line++, f);
+    auto sync_lines = [&]() {
+        if (vend - (nxt >> 4) <= 2) {  // two halves free: f (line vend / 2) moves in
+            put_line(vend >> 1, f);
+            vend += 2;
+        }
+        load_line(vend >> 1, f);
     };
-    uint32_t rnd = 0;
-    auto sync_lines = [&]() {  // at the start of every round; acts on every second one
-        if ((rnd++ & 1u) == 0 && land_halves == 0) take_f();
-    };
-    // Once nxt has left half h, its slots take half h + 2 from the landed line.
-    auto advance_ring = [&]() {
-        if (nxt >= 16 * h + 16) {
-            if (land_halves == 0) take_f();  // not expected (see above); waits for f
-            if (land_halves == 2) {
+
+    // ---- output: a line of 128 bytes in registers, stored whole.  Round v
+    // (counted from the line holding the chunk's first byte) fills words
+    // [kRoundWords * (v mod kLineRounds), +kRoundWords) of line v / kLineRounds;
+    // the rounds before the chunk's first byte and after its last full round
+    // do not exist and are skipped.
+    HC_G uint8_t *const dst = out + blk_start + s0;
+    const uint32_t nsym = s1 - s0;
+    const uint32_t ph = (uint32_t)((uint64_t)dst & 127u);  // a multiple of 16
+    const uint32_t v_first = ph / R;                       // round of the chunk's first byte
+    const uint32_t v_end = v_first + nsym / R;             // after the last full round
+    HC_G uint8_t *const line0 = dst - ph;                  // the line holding the first byte
+    uint32_t ow[32];
+    auto store_line = [&](uint32_t lb) {  // the rounds [lb, lb + kLineRounds) that exist
 #pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) put_quad(16 * (h + 2) + 4 * j, land[j]);
-            } else {
-#pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) put_quad(16 * (h + 2) + 4 * j, land[4 + j]);
+        for (uint32_t r = 0; r < kLineRounds; ++r) {
+            const uint32_t v = lb + r;
+            if (v >= v_first && v < v_end) {
+                HC_G uint8_t *p = line0 + (uint64_t)R * v;
+                if (R == 16)
+                    *(HC_G v4u *)p = v4u{ow[4 * r], ow[4 * r + 1], ow[4 * r + 2], ow[4 * r + 3]};
+                else
+                    *(HC_G v2u *)p = v2u{ow[2 * r], ow[2 * r + 1]};
             }
-            land_halves -= 1;
-            h += 1;
         }
     };
-    const uint32_t nsym = s1 - s0;
+    uint32_t k = 0;  // symbols of the full rounds
 
     if (fixed8) {
-        // Every code is 8 bits: symbol k of the block is byte 3 - (k & 3) of
-        // payload word k >> 2, so the chunk decodes word by word with
-        // independent table lookups.  The index, the header and the pad must
-        // agree with that layout.
-        if (p0 != 8ull * s0 || p1 != 8ull * s1 || hdr != 8ull * cnt) {
-            report(err, HC_ERR_CORRUPT);
-            return;
-        }
+        // Every code is 8 bits: symbol q of a round is byte 3 - (q & 3) of
+        // word nxt + q / 4, so a round is four ring words and sixteen table
+        // lookups.
         const uint32_t ncode = s_count[8];
         uint32_t bad8 = 0;
-        auto code_at = [&](uint32_t q) -> uint32_t {  // code of symbol q of the round at nxt
-            const uint32_t c = (ring[(nxt + (q >> 2)) & 31u] >> (24 - 8 * (q & 3))) & 255u;
-            bad8 |= (uint32_t)(c >= ncode);
-            return c;
+        auto code_at = [&](uint32_t q) -> uint32_t {
+            const uint32_t cd = (ring[(nxt + (q >> 2)) & 63u] >> (24 - 8 * (q & 3))) & 255u;
+            bad8 |= (uint32_t)(cd >= ncode);
+            return cd;
         };
-        uint32_t k = 0;
-        for (; k + 16 <= nsym; k += 16) {
-            sync_lines();
-            advance_ring();
-            uint32_t o4[4];
+        for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q)
-                o4[q] = s_sorted[code_at(4 * q)] | (s_sorted[code_at(4 * q + 1)] << 8) |
-                        (s_sorted[code_at(4 * q + 2)] << 16) | (s_sorted[code_at(4 * q + 3)] << 24);
-            nxt += 4;
-            put16(v4u{o4[0], o4[1], o4[2], o4[3]});
-        }
-        if (k < nsym) {  // fewer than 16 symbols: at most 4 words from nxt
-            sync_lines();
-            advance_ring();
+            for (uint32_t r = 0; r < kLineRounds; ++r) {
+                if (r % 4 == 2) sync_lines();
+                const uint32_t v = lb + r;
+                if (v >= v_first && v < v_end) {
 #pragma unroll
-            for (uint32_t q = 0; q < 16; ++q)
-                if (k + q < nsym) put1(s_sorted[code_at(q)]);
+                    for (uint32_t q = 0; q < kRoundWords; ++q)
+                        ow[kRoundWords * r + q] = s_sorted[code_at(4 * q)] | (s_sorted[code_at(4 * q + 1)] << 8) |
+                                                  (s_sorted[code_at(4 * q + 2)] << 16) |
+                                                  (s_sorted[code_at(4 * q + 3)] << 24);
+                    nxt += R / 4;
+                }
+            }
+            store_line(lb);
         }
-        finish_output();
+        k = nsym - nsym % R;
+        if (k < nsym) {  // fewer than R symbols: at most R/4 words from nxt
+            sync_lines();
+            for (uint32_t q = 0; q < nsym - k; ++q) dst[k + q] = (uint8_t)s_sorted[code_at(q)];
+        }
         if (s1 == cnt && (hdr & 31u)) {
             const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
             bad8 |= (in32[pw0 + nwords - 1] & mask) ? 1u : 0u;
@@ -1063,10 +1011,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     // ---- bit buffer: the next nbits payload bits, most significant first;
     // 'pre' is the ring word at nxt, read ahead of its refill.
     const uint32_t r0 = (uint32_t)(p0 & 31);
-    uint64_t buf = (((uint64_t)ring[nxt & 31u] << 32) | ring[(nxt + 1) & 31u]) << r0;
+    uint64_t buf = (((uint64_t)ring[nxt & 63u] << 32) | ring[(nxt + 1) & 63u]) << r0;
     uint32_t nbits = 64 - r0;
     nxt += 2;
-    uint32_t pre = ring[nxt & 31u];
+    uint32_t pre = ring[nxt & 63u];
     uint32_t bad = 0;  // kLutBadFlag: an invalid prefix was met
 
     // One symbol from the buffer (which holds >= max_len bits here).  The
@@ -1106,27 +1054,18 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         buf |= (uint64_t)w << ((32 - nbits) & 63u);
         nbits += need ? 32u : 0u;
         nxt += need ? 1u : 0u;
-        pre = ring[nxt & 31u];
+        pre = ring[nxt & 63u];
     };
 
-    uint32_t k = 0;
     if (has_zero_code) {
         // The code '0' (one bit) exists: it is the shortest canonical code, of
         // symbol sorted[0].  A run of that symbol is a run of leading zero bits.
-        // The output line is pre-filled with that symbol, so a step only counts
-        // the run (one count-leading-zeros) and, if a '1' follows, decodes one
-        // other symbol through the table and writes that one byte.  Steps are
-        // grouped in rounds of R output symbols (the last round: fewer), so
-        // every lane stores its segments at the same rounds.  A step consumes
-        // at most R + max_len bits, a round at most R * max_len.
+        // A round's words start filled with that symbol; a step counts a run
+        // (one count-leading-zeros) and, if a '1' follows, decodes one other
+        // symbol through the table and writes that byte into the round's words.
+        // A step consumes at most R + max_len bits.
         const uint32_t rep4 = 0x01010101u * s_sorted[0];
-        const v4u rep = v4u{rep4, rep4, rep4, rep4};
-#pragma unroll
-        for (uint32_t j = 0; j < kSegQuads; ++j) stage[j] = rep;
-        while (k < nsym) {
-            sync_lines();
-            advance_ring();
-            const uint32_t want = nsym - k < R ? nsym - k : R;
+        auto run_round = [&](uint32_t want, uint32_t *w) {  // want symbols into words w[0 .. R/4)
             uint32_t t = 0;
             while (t < want) {
                 const uint32_t hi = (uint32_t)(buf >> 32);
@@ -1136,50 +1075,71 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
                 nbits -= r;
                 t += r;
                 if (t < want) {  // a '1' follows the run: one other symbol
-                    if (max_len > 16) refill();
-                    stage_byte(ov + t) = (uint8_t)decode_sym();
+                    if (max_len > 32 - R) refill();
+                    const uint32_t sym = decode_sym();
+                    const uint32_t sh = 8 * (t & 3u);
+#pragma unroll
+                    for (uint32_t q = 0; q < kRoundWords; ++q)
+                        if ((t >> 2) == q) w[q] = (w[q] & ~(255u << sh)) | (sym << sh);
                     t += 1;
                 }
                 refill();
             }
-            k += want;
-            ov += want;
-            if ((ov & (kSegBytes - 1)) == 0) {
-                flush_line(ov - kSegBytes, kSegQuads);
+        };
+        for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
 #pragma unroll
-                for (uint32_t j = 0; j < kSegQuads; ++j) stage[j] = rep;
+            for (uint32_t r = 0; r < kLineRounds; ++r) {
+                if (r % 4 == 2) sync_lines();
+                const uint32_t v = lb + r;
+                if (v >= v_first && v < v_end) {
+#pragma unroll
+                    for (uint32_t q = 0; q < kRoundWords; ++q) ow[kRoundWords * r + q] = rep4;
+                    run_round(R, ow + kRoundWords * r);
+                }
             }
+            store_line(lb);
         }
-    }
-    for (; k + R <= nsym; k += R) {  // full rounds
-        sync_lines();
-        advance_ring();
-        uint32_t o4[R / 4];
+        k = nsym - nsym % R;
+        if (k < nsym) {  // the ragged last round
+            sync_lines();
+            uint32_t w[kRoundWords];
 #pragma unroll
-        for (uint32_t q = 0; q < R / 4; ++q) o4[q] = 0;
+            for (uint32_t q = 0; q < kRoundWords; ++q) w[q] = rep4;
+            run_round(nsym - k, w);
 #pragma unroll
-        for (uint32_t q = 0; q < R; ++q) {
-            o4[q >> 2] |= decode_sym() << (8 * (q & 3));
-            if ((q + 1) % SPR == 0 || q + 1 == R) refill();
+            for (uint32_t q = 0; q < R; ++q)
+                if (q < nsym - k) dst[k + q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
         }
-        if (R == 16)
-            put16(v4u{o4[0], o4[1], o4[2], o4[3]});
-        else
-            put8(((uint64_t)o4[1] << 32) | o4[0]);
-    }
-    if (k < nsym) {  // the ragged last round: one symbol between refills
-        sync_lines();
-        advance_ring();
-        const uint32_t m = nsym - k;
+    } else {
+        for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
 #pragma unroll
-        for (uint32_t q = 0; q < R; ++q) {
-            if (q < m) {
-                put1(decode_sym());
+            for (uint32_t r = 0; r < kLineRounds; ++r) {
+                if (r % 4 == 2) sync_lines();
+                const uint32_t v = lb + r;
+                if (v >= v_first && v < v_end) {
+                    uint32_t o4[kRoundWords];
+#pragma unroll
+                    for (uint32_t q = 0; q < kRoundWords; ++q) o4[q] = 0;
+#pragma unroll
+                    for (uint32_t q = 0; q < R; ++q) {
+                        o4[q >> 2] |= decode_sym() << (8 * (q & 3));
+                        if ((q + 1) % SPR == 0 || q + 1 == R) refill();
+                    }
+#pragma unroll
+                    for (uint32_t q = 0; q < kRoundWords; ++q) ow[kRoundWords * r + q] = o4[q];
+                }
+            }
+            store_line(lb);
+        }
+        k = nsym - nsym % R;
+        if (k < nsym) {  // the ragged last round: one symbol between refills
+            sync_lines();
+            for (uint32_t q = 0; q < nsym - k; ++q) {
+                dst[k + q] = (uint8_t)decode_sym();
                 refill();
             }
         }
     }
-    finish_output();
     const uint64_t pos = 32 * (ubase + nxt - mis - pw0) - nbits;
     if ((bad & kLutBadFlag) || pos != p1) {
         report(err, HC_ERR_CORRUPT);
