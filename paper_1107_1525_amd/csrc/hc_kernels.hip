@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
 #pragma unroll
             for (uint32_t r = 0; r < kLineRounds; ++r) {
-                if (r % 4 == 2) sync_lines();
+                if (r % 8 == 2) sync_lines();  // 8 rounds take 32 words: one sync per line of output
                 const uint32_t v = lb + r;
                 if (v >= v_first && v < v_end) {
 #pragma unroll
