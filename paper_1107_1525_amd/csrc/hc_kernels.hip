@@ -800,9 +800,6 @@ __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32,
 // R symbols per round (8 or 16); refills of the bit buffer follow symbols
 // SPR, 2*SPR, ... of a round and its last symbol (SPR * max_len <= 32);
 // kLong: codes may be longer than the table.
-// R symbols per round (8 or 16); refills of the bit buffer follow symbols
-// SPR, 2*SPR, ... of a round and its last symbol (SPR * max_len <= 32);
-// kLong: codes may be longer than the table.
 template <uint32_t R, uint32_t SPR, bool kLong>
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
                                                              uint32_t *err)
@@ -833,7 +830,6 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
     const bool fixed8 = tb->fixed_len == 8;  // uniform over the group: one job per group
-    const bool has_zero_code = tb->count[1] != 0;
     if (!fixed8)
         for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
     if (tid <= (uint32_t)kPackedMaxLen) {
@@ -1057,87 +1053,32 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         pre = ring[nxt & 63u];
     };
 
-    if (has_zero_code) {
-        // The code '0' (one bit) exists: it is the shortest canonical code, of
-        // symbol sorted[0].  A run of that symbol is a run of leading zero bits.
-        // A round's words start filled with that symbol; a step counts a run
-        // (one count-leading-zeros) and, if a '1' follows, decodes one other
-        // symbol through the table and writes that byte into the round's words.
-        // A step consumes at most R + max_len bits.
-        const uint32_t rep4 = 0x01010101u * s_sorted[0];
-        auto run_round = [&](uint32_t want, uint32_t *w) {  // want symbols into words w[0 .. R/4)
-            uint32_t t = 0;
-            while (t < want) {
-                const uint32_t hi = (uint32_t)(buf >> 32);
-                const uint32_t z = hi ? (uint32_t)__clz((int)hi) : 32u;
-                const uint32_t r = want - t < z ? want - t : z;
-                buf <<= r;
-                nbits -= r;
-                t += r;
-                if (t < want) {  // a '1' follows the run: one other symbol
-                    if (max_len > 32 - R) refill();
-                    const uint32_t sym = decode_sym();
-                    const uint32_t sh = 8 * (t & 3u);
+    for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
 #pragma unroll
-                    for (uint32_t q = 0; q < kRoundWords; ++q)
-                        if ((t >> 2) == q) w[q] = (w[q] & ~(255u << sh)) | (sym << sh);
-                    t += 1;
+        for (uint32_t r = 0; r < kLineRounds; ++r) {
+            if (r % 4 == 2) sync_lines();
+            const uint32_t v = lb + r;
+            if (v >= v_first && v < v_end) {
+                uint32_t o4[kRoundWords];
+#pragma unroll
+                for (uint32_t q = 0; q < kRoundWords; ++q) o4[q] = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < R; ++q) {
+                    o4[q >> 2] |= decode_sym() << (8 * (q & 3));
+                    if ((q + 1) % SPR == 0 || q + 1 == R) refill();
                 }
-                refill();
-            }
-        };
-        for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
 #pragma unroll
-            for (uint32_t r = 0; r < kLineRounds; ++r) {
-                if (r % 4 == 2) sync_lines();
-                const uint32_t v = lb + r;
-                if (v >= v_first && v < v_end) {
-#pragma unroll
-                    for (uint32_t q = 0; q < kRoundWords; ++q) ow[kRoundWords * r + q] = rep4;
-                    run_round(R, ow + kRoundWords * r);
-                }
+                for (uint32_t q = 0; q < kRoundWords; ++q) ow[kRoundWords * r + q] = o4[q];
             }
-            store_line(lb);
         }
-        k = nsym - nsym % R;
-        if (k < nsym) {  // the ragged last round
-            sync_lines();
-            uint32_t w[kRoundWords];
-#pragma unroll
-            for (uint32_t q = 0; q < kRoundWords; ++q) w[q] = rep4;
-            run_round(nsym - k, w);
-#pragma unroll
-            for (uint32_t q = 0; q < R; ++q)
-                if (q < nsym - k) dst[k + q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
-        }
-    } else {
-        for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
-#pragma unroll
-            for (uint32_t r = 0; r < kLineRounds; ++r) {
-                if (r % 4 == 2) sync_lines();
-                const uint32_t v = lb + r;
-                if (v >= v_first && v < v_end) {
-                    uint32_t o4[kRoundWords];
-#pragma unroll
-                    for (uint32_t q = 0; q < kRoundWords; ++q) o4[q] = 0;
-#pragma unroll
-                    for (uint32_t q = 0; q < R; ++q) {
-                        o4[q >> 2] |= decode_sym() << (8 * (q & 3));
-                        if ((q + 1) % SPR == 0 || q + 1 == R) refill();
-                    }
-#pragma unroll
-                    for (uint32_t q = 0; q < kRoundWords; ++q) ow[kRoundWords * r + q] = o4[q];
-                }
-            }
-            store_line(lb);
-        }
-        k = nsym - nsym % R;
-        if (k < nsym) {  // the ragged last round: one symbol between refills
-            sync_lines();
-            for (uint32_t q = 0; q < nsym - k; ++q) {
-                dst[k + q] = (uint8_t)decode_sym();
-                refill();
-            }
+        store_line(lb);
+    }
+    k = nsym - nsym % R;
+    if (k < nsym) {  // the ragged last round: one symbol between refills
+        sync_lines();
+        for (uint32_t q = 0; q < nsym - k; ++q) {
+            dst[k + q] = (uint8_t)decode_sym();
+            refill();
         }
     }
     const uint64_t pos = 32 * (ubase + nxt - mis - pw0) - nbits;
