@@ -785,12 +785,12 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 constexpr uint32_t kRingWords = 64;               // four 16-word halves: two lines
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
 
-// Stream quad q (16 bytes), with q clamped to the quads that hold stream
-// words: one load, no branch, so nothing waits for it before its data is
-// used.  The stream is 16-byte aligned, so the quad of its last word lies in
-// the same page and may be read whole; words past the stream end (or before
-// its start) only ever reach bit-buffer positions after a chunk's last code,
-// which no decoded symbol depends on.
+// Stream quad q (16 bytes), with q clamped to [0, q_last] (q_last at most the
+// quad of the stream's last word): one load, no branch, so nothing waits for
+// it before its data is used.  The stream is 16-byte aligned, so the quad of
+// its last word lies in the same page and may be read whole; the words a
+// clamped request stands in for only ever reach bit-buffer positions after a
+// chunk's last code, which no decoded symbol depends on.
 __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32, int64_t q, int64_t q_last)
 {
     q = q < 0 ? 0 : (q > q_last ? q_last : q);
@@ -889,10 +889,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     // lines at different times.  So lines are requested only at sync points,
     // every fourth round (rounds 2 and 6 of an output line, away from the line
     // stores, which a wait would also cover), by all lanes together: each lane
-    // requests the line
-    // after its ring's end into registers f, and at the next sync point (four
-    // rounds later, when the load has landed) moves it into the ring if two
-    // halves are free, else requests it again (a cache hit).  Four rounds
+    // requests the line after its ring's end into registers f, and at the
+    // next sync point (four rounds later, when the load has landed) moves it
+    // into the ring if two halves are free, else requests it again (a cache
+    // hit).  Four rounds
     // consume at most 32 words (4 * R * max_len <= 1024 bits), and after a
     // sync point the ring holds at least three halves from the current word
     // on, so a round never reads a word the ring does not hold.
@@ -903,7 +903,12 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     const uint64_t ubase = u0 & ~(uint64_t)31;                     // virtual word of local word 0
     const int64_t qbase = (int64_t)(ubase >> 2) - (int64_t)(mis >> 2);  // stream quad of local quad 0
     uint32_t *ring = s_ring + tid * kRingStride;
-    const int64_t q_last = (int64_t)((in_words - 1) >> 2);  // quad of the stream's last word
+    // Requests stop at the quad of the chunk's last payload word: a line past
+    // it would only fill bit-buffer positions after the chunk's last code, and
+    // is the next chunk's, read by its lane long before, so it would come from
+    // HBM a second time.  Clamped requests hit the lane's own recent line.
+    const uint64_t w_last = pw0 + (p1 ? (p1 - 1) >> 5 : 0);
+    const int64_t q_last = (int64_t)((w_last < in_words ? w_last : in_words - 1) >> 2);
     auto load_line = [&](uint32_t l, v4u f[8]) {
 #pragma unroll
         for (uint32_t j = 0; j < 8; ++j) f[j] = load_quad(in32, qbase + 8 * (int64_t)l + j, q_last);
