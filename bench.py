@@ -202,14 +202,14 @@ def kernel_times(w, torch, np, reps=20, warmup=3):
 
 
 def cpu_baseline(w, oracle, np):
-    """The oracle on segments 0..2 (one of each kind, 192 MiB) of the same
+    """The oracle on segments 0..5 (two of each kind, 384 MiB) of the same
     workload: counts, code, block encode and strict decode.  Timed twice: on
     one thread, and block-parallel on every host core the process may use (a
     thread pool over independent blocks; the oracle's C calls release the
     interpreter lock), which is the shape of the paper's multi-core coder."""
     from concurrent.futures import ThreadPoolExecutor
 
-    xs = [w.xs(t).cpu().numpy() for t in range(3)]
+    xs = [w.xs(t).cpu().numpy() for t in range(6)]
     nbytes = sum(x.size for x in xs)
     B = w.B
 
@@ -244,7 +244,7 @@ def cpu_baseline(w, oracle, np):
         "unit": "GB/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"segments 0-2 (uniform, skewed, fp32) of the 4 GiB mixed workload, {nbytes >> 20} MiB, "
+        "sample": f"segments 0-5 (uniform, skewed, fp32, twice) of the 4 GiB mixed workload, {nbytes >> 20} MiB, "
                   f"B={B}: counts + code + block encode + strict decode, block-parallel over {cores} threads",
         "seconds": round(tp, 2),
         "single_core_GBps": round(nbytes / t1 / 1e9, 4),

@@ -43,7 +43,8 @@ struct JobList {
 
 inline uint64_t num_blocks(uint64_t n, uint32_t B) { return (n + B - 1) / B; }
 // Loads (16 symbols each) per encode thread: a tile is qpt * 4096 symbols.
-// Large tiles give each work-group more bytes per look-back; they need
+// Large tiles give each work-group more bytes to pack per fixed set-up cost
+// (tables, the tile's position, the next tile's first symbols); they need
 // qpt * 4096 * max_len bits of LDS, so long codes keep the small tile.
 inline uint32_t encode_qpt(uint32_t B, uint32_t max_len)
 {

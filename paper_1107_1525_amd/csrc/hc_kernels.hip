@@ -2,15 +2,20 @@
 //
 //   k_hist         symbol counts (paper section 2) with LDS-privatised
 //                  sub-histograms, one replica per lane of a wavefront
-//   k_encode       one pass per tile of 4096 symbols (a tile never crosses a
-//                  block boundary): length pass (section 2.1), the block-offset
-//                  scan by decoupled look-back (section 2.1: "where the block
-//                  starts and ends"), and bit packing (section 2.1, Fig. 3-4):
-//                  code words OR-ed into LDS words, stored coalesced at the
-//                  block's offset in the stream with the header and zero pad
+//   k_count        length pass (section 2.1): bits of every tile of 4096 * QPT
+//                  symbols (a tile never crosses a block boundary)
+//   k_offsets      offset pass (section 2.1: "where the block starts and
+//                  ends"): each tile's bit position inside its block and each
+//                  block's byte offset in the stream, one work-group per stream
+//   k_encode       bit packing (section 2.1, Fig. 3-4): a tile's code words
+//                  OR-ed into LDS words, stored coalesced at the block's offset
+//                  in the stream with the header and zero pad
 //   k_walk         offset table rebuilt from the length delimiters
-//   k_decode       table decode (sections 2.1 and 3.2): one lane per block, or
-//                  per chunk of S symbols when a sub-block index is given
+//   k_decode_ring  table decode (sections 2.1 and 3.2) of codes <= 24 bits:
+//                  one lane per chunk of S symbols (or per block), whole
+//                  128-byte lines in from HBM through an LDS ring per lane and
+//                  out from registers
+//   k_decode       the same decode for codes of up to 64 bits
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
