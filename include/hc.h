@@ -264,7 +264,8 @@ typedef struct {
 
 /* Device workspace (256-byte aligned, caller-owned) any of the three batch */
 /* calls needs for these items and block size: the job table copied from  */
-/* the host, then the encoder's look-back states.                          */
+/* the host, then the encoder's per-tile (and per-thread) bit counts and  */
+/* positions.                                                              */
 uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size);
 
 /* hc_histogram for every item (uses in, n, hist).  The item table is       */
@@ -287,8 +288,10 @@ hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_s
 /* packing), for callers that time or schedule them one by one.  Same      */
 /* arguments as hc_encode_batch; issue them in this order on one stream    */
 /* with the same items and workspace (the workspace carries each tile's    */
-/* bit count from the first step to the second and its in-block position  */
-/* from the second to the third).  Together they equal hc_encode_batch.   */
+/* bit count from the first step to the second, its in-block position     */
+/* from the second to the third, and for tiles of more than 4096 symbols  */
+/* the bit count of each of the tile's 256 threads from the first to the  */
+/* third).  Together they equal hc_encode_batch.                           */
 /*   lengths: per tile of the input, the sum of its code lengths;           */
 /*            in *d_err: SYMBOL_ABSENT.                                    */
 /*   offsets: block_off of every item (C = block_off[nb]);                  */

@@ -218,7 +218,7 @@ extern "C" uint64_t hc_encode_workspace_bytes(uint64_t n, uint32_t block_size)
 {
     if (block_size == 0) return 0;
     const uint64_t nb = num_blocks(n, block_size);
-    return 8 * encode_scratch_words(nb * tiles_per_block(block_size, 1));  // the smallest tile: an upper bound
+    return encode_scratch_bound(nb, block_size);
 }
 
 extern "C" uint64_t hc_sub_index_entries(uint64_t n, uint32_t block_size, uint32_t sub_block)
@@ -339,7 +339,7 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
     const uint32_t qpt = encode_qpt(block_size, cb->host.max_len);
     const uint64_t tiles = nb * tiles_per_block(block_size, qpt);
     if (!d_ws || !aligned(d_ws, 8)) return HC_ERR_INVALID_ARG;
-    if (ws_bytes < 8 * encode_scratch_words(tiles)) return HC_ERR_NO_SPACE;
+    if (ws_bytes < encode_scratch_bytes(tiles, qpt)) return HC_ERR_NO_SPACE;
     if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;  // grid limit
     Job j = empty_job();
     j.in = d_in;
@@ -349,7 +349,7 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
     j.block_off = d_block_off;
     j.sub_idx = d_sub_idx;
     return hip_status(launch_encode(single(j), tiles, block_size, qpt, cb->host.max_len, sub_block,
-                                    static_cast<uint64_t *>(d_ws), d_err, s, kStepAll));
+                                    d_ws, d_err, s, kStepAll));
 }
 
 extern "C" hc_status hc_walk_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t nb, uint64_t *d_block_off,
@@ -385,9 +385,9 @@ extern "C" hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, ui
 extern "C" uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size)
 {
     if (!items || block_size == 0) return 0;
-    uint64_t tiles = 0;
-    for (uint32_t k = 0; k < count; ++k) tiles += num_blocks(items[k].n, block_size) * tiles_per_block(block_size, 1);
-    return job_table_bytes(count) + 8 * encode_scratch_words(tiles);
+    uint64_t nb = 0;
+    for (uint32_t k = 0; k < count; ++k) nb += num_blocks(items[k].n, block_size);
+    return job_table_bytes(count) + encode_scratch_bound(nb, block_size);
 }
 
 extern "C" hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes,
@@ -461,7 +461,7 @@ hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t bloc
     }
     if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
     const uint64_t head = job_table_bytes(count);
-    if (ws_bytes < head + 8 * encode_scratch_words(tiles)) return HC_ERR_NO_SPACE;
+    if (ws_bytes < head + encode_scratch_bytes(tiles, qpt)) return HC_ERR_NO_SPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     JobList jl;
     hc_status st = upload_jobs(jobs, tiles, d_ws, s, &jl);
@@ -469,7 +469,7 @@ hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t bloc
     if (steps & kStepOffsets)
         for (uint32_t k = 0; k < count; ++k)
             if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
-    uint64_t *scratch = reinterpret_cast<uint64_t *>(static_cast<char *>(d_ws) + head);
+    void *scratch = static_cast<char *>(d_ws) + head;
     return hip_status(launch_encode(jl, tiles, block_size, qpt, max_len, sub_block, scratch, d_err, s, steps));
 }
 

@@ -59,6 +59,7 @@ void build_dev_tables(const hc_codebook &cb, DevTables *t)
 
     for (int v = 0; v < kNumSym; ++v) {
         t->enc_len[v] = cb.len[v];
+        t->len4[v >> 2] |= (uint32_t)cb.len[v] << (8 * (v & 3));
         t->enc_code[v] = cb.code[v];
         t->enc_packed[v] = cb.max_len <= (uint32_t)kPackedMaxLen
                                ? (uint32_t)((cb.code[v] << 8) | cb.len[v])

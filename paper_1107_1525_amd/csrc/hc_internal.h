@@ -25,6 +25,7 @@ struct DevTables {
     uint32_t enc_packed[kNumSym];  // (code << 8) | len, valid when max_len <= kPackedMaxLen
     uint64_t enc_code[kNumSym];    // right-aligned canonical code values
     uint32_t enc_len[kNumSym];     // code lengths, 0 = no code
+    alignas(16) uint32_t len4[kNumSym / 4];  // the same lengths, four per word: symbol 4i + j in byte j of word i
     uint16_t lut[1 << kLutBits];   // next lut_bits bits -> (symbol << 8) | len
     uint64_t first[kMaxLen + 1];   // first canonical code value of each length
     uint32_t count[kMaxLen + 1];   // number of codes of each length

@@ -67,15 +67,30 @@ inline uint64_t hist_chunk(uint64_t total)
     return chunk;
 }
 
-// Encode scratch, in 8-byte words: the bit count and the in-block position of
-// every tile (two u32 per tile).
-inline uint64_t encode_scratch_words(uint64_t tiles) { return tiles; }
+// Encode scratch, in bytes, for 'tiles' tiles of qpt * 4096 symbols: the bit
+// count and the in-block bit position of every tile (u32 each), then, when
+// qpt >= 2, the bit count of every thread of every tile (u16), which the
+// length pass hands to the packing pass.
+inline uint64_t encode_scratch_bytes(uint64_t tiles, uint32_t qpt)
+{
+    return tiles * (8ull + (qpt >= 2 ? 2ull * kTileThreads : 0ull));
+}
+// The most any code needs for nb blocks of B symbols (every tile shape B allows).
+inline uint64_t encode_scratch_bound(uint64_t nb, uint32_t B)
+{
+    uint64_t most = 0;
+    for (uint32_t qpt = 1; qpt <= encode_qpt(B, 1); qpt *= 2) {
+        const uint64_t b = encode_scratch_bytes(nb * tiles_per_block(B, qpt), qpt);
+        most = b > most ? b : most;
+    }
+    return most;
+}
 
 hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, hipStream_t s);
 // Encode steps (bit mask): the length pass, the offset scan, the packing.
 constexpr uint32_t kStepLengths = 1, kStepOffsets = 2, kStepPack = 4, kStepAll = 7;
 hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t qpt, uint32_t max_len, uint32_t S,
-                         uint64_t *scratch, uint32_t *err, hipStream_t s, uint32_t steps);
+                         void *scratch, uint32_t *err, hipStream_t s, uint32_t steps);
 hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s);
 hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64_t *block_off,
                        uint32_t *err, hipStream_t s);

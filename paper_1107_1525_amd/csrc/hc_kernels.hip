@@ -272,16 +272,23 @@ __device__ __forceinline__ void put_bits(uint64_t &acc, uint32_t &nacc, uint32_t
 // another work-group, so every work-group runs from start to end at once.
 
 // Length pass: work-group t sums the code lengths of tile t (the same tile
-// shape as the packing pass) and reports a symbol without a code.
-template <bool kPacked, uint32_t QPT>
-__global__ __launch_bounds__(kTileThreads) void k_count(JobList jl, uint32_t B, uint32_t tpb, uint32_t *tile_bits,
-                                                        uint32_t *err)
+// shape as the packing pass) and reports a symbol without a code.  The
+// lengths come from 64 LDS replicas of the table, four lengths per word, and
+// lane r reads replica r (word i at [64 i + r]): a wave's 64 lookups then
+// hit 64 distinct banks whatever the symbols, where one shared table makes
+// uniform data conflict several ways per lookup.  With thread_bits, each
+// thread's own sum is kept for the packing pass too.  Built for 8 waves per
+// SIMD, as the packing pass.
+template <uint32_t QPT>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_count(JobList jl, uint32_t B, uint32_t tpb, uint32_t *tile_bits,
+                                                        uint16_t *thread_bits, uint32_t *err)
 {
     constexpr uint32_t kSyms = kQuadSyms * QPT;
-    __shared__ uint32_t s_len[kNumSym];
+    constexpr uint32_t kWords = kNumSym / 4;  // length words per replica
+    __shared__ __attribute__((aligned(16))) uint32_t s_len4[64 * kWords];
     __shared__ uint32_t s_red[kTileThreads / 64];
     __shared__ Job s_job;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint64_t t = blockIdx.x;
     if (tid < 64) {
         const uint32_t k = wave_job_of_unit(jl, t);
@@ -289,23 +296,51 @@ __global__ __launch_bounds__(kTileThreads) void k_count(JobList jl, uint32_t B, 
     }
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
-    s_len[tid] = kPacked ? (tb->enc_packed[tid] & 255u) : tb->enc_len[tid];
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
     const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
     const uint32_t s = tl.ts + kSyms * tid;
     uint32_t w[4 * QPT];
     const uint32_t m = load_syms<QPT>(in, tl, s, w);  // 0 past the end of the tile
-    __syncthreads();
-    uint32_t bits = 0, mn = 255u;
+    {
+        // thread t holds words 4q..4q+3 (q = t / 16) and writes each into
+        // replicas 4g..4g+3 (g = t mod 16): one 16-byte load, four 16-byte LDS
+        // writes, and each write instruction covers all banks evenly
+        static_assert(kWords == 64 && kTileThreads == 256, "one length word group per 16 threads");
+        const uint32_t q = tid >> 4, g = tid & 15u;
+        const v4u x = ((const HC_G v4u *)tb->len4)[q];
+        const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-    for (uint32_t k = 0; k < kSyms; ++k) {
-        const uint32_t L = s_len[sym_at(w, k)];
-        bits += k < m ? L : 0u;
-        mn = min(mn, k < m ? L : 255u);
+        for (uint32_t j = 0; j < 4; ++j)
+            *(v4u *)(s_len4 + 64 * (4 * q + j) + 4 * g) = v4u{xs[j], xs[j], xs[j], xs[j]};
     }
+    __syncthreads();
+    const uint32_t *my = s_len4 + lane;
+    uint32_t bits = 0, mn = 255u;  // mn: the smallest code length met, 0 = a symbol without a code
+    // Only the wave holding a block's ragged end masks symbols past m.
+    auto count = [&](auto mask_tag) {
+        constexpr bool kMask = decltype(mask_tag)::value;
+#pragma unroll
+        for (uint32_t k = 0; k < kSyms; ++k) {
+            if ((k & (kQuadSyms - 1)) == 0 && k) {
+                // one load's lookups at a time: bounds the registers held by reads in flight
+                __builtin_amdgcn_sched_barrier(0);
+                const uint32_t i = k / 4;
+                asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]), "+v"(bits), "+v"(mn));
+            }
+            const uint32_t v = sym_at(w, k);
+            const uint32_t L = (my[64 * (v >> 2)] >> (8 * (v & 3u))) & 255u;
+            bits += (!kMask || k < m) ? L : 0u;
+            mn = min(mn, (!kMask || k < m) ? L : 255u);
+        }
+    };
+    if (__all(m == kSyms))
+        count(std::integral_constant<bool, false>());
+    else
+        count(std::integral_constant<bool, true>());
     if (mn == 0) report(err, HC_ERR_SYMBOL_ABSENT);
+    if (thread_bits) thread_bits[t * kTileThreads + tid] = (uint16_t)bits;  // <= 64 codes of <= 24 bits
     bits = wave_sum(bits);
-    if ((tid & 63) == 0) s_red[tid >> 6] = bits;
+    if (lane == 0) s_red[wave] = bits;
     __syncthreads();
     if (tid == 0) {
         uint32_t total = 0;
@@ -371,14 +406,19 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(JobList jl, uint32_t B,
 // kPacked: codes of <= 24 bits from the packed table, FPS codes between
 // accumulator flushes (FPS * max_len <= 32); otherwise codes up to 64 bits.
 // QPT: 16-symbol loads per thread; a tile is 4096 * QPT symbols and thread i
-// codes its symbols [16 * QPT * i, 16 * QPT * (i + 1)).
+// codes its symbols [16 * QPT * i, 16 * QPT * (i + 1)).  With QPT >= 2 the
+// length pass has kept every thread's bit count (thread_bits), so each symbol
+// is looked up once here; tiles of 4096 symbols count their bits again
+// rather than move a count per 16 symbols through HBM.
 // Built for 8 waves per SIMD (<= 64 VGPRs): 8 work-groups per CU in flight.
 template <bool kPacked, uint32_t FPS, uint32_t QPT>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_encode(
-    JobList jl, uint32_t B, uint32_t tpb, const uint32_t *tile_pos, uint32_t S, uint32_t cpb, uint32_t lds_words,
-    uint32_t *err)
+    JobList jl, uint32_t B, uint32_t tpb, const uint32_t *tile_pos, const uint16_t *thread_bits, uint32_t S,
+    uint32_t cpb, uint32_t lds_words, uint32_t *err)
 {
     constexpr uint32_t kSyms = kQuadSyms * QPT;  // symbols per thread
+    constexpr bool kHanded = QPT >= 2;           // bit counts from the length pass
+    static_assert(!kHanded || kPacked, "tiles of more than 4096 symbols hold codes of <= 24 bits");
     extern __shared__ uint32_t words[];  // the tile's code bits from bit 0, MSB first
     __shared__ uint32_t s_packed[kNumSym];
     __shared__ uint64_t s_code[kPacked ? 1 : kNumSym];
@@ -421,18 +461,18 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const uint32_t s = tl.ts + kSyms * tid;
     uint32_t w[4 * QPT];
     uint32_t m = load_syms<QPT>(in, tl, s, w);
+    uint32_t bits = kHanded ? (uint32_t)thread_bits[t * kTileThreads + tid] : 0u;
     __syncthreads();  // code tables and the next tile's first symbols are in LDS
 
-    // The thread's symbols are coded twice from the LDS table: once for their
-    // bit count (before the group scan), once to pack them (after it).  Holding
-    // 16*QPT table entries per thread across the scan would cost more registers
-    // than the second reads cost time.  Waves whose threads all hold full
-    // loads take the variant without per-symbol masks (kMask false); only the
-    // wave with the ragged end of a block needs them (symbols past m then
-    // read entry 0 and are masked to zero).
+    // Without handed counts the thread's symbols are coded twice from the LDS
+    // table: once for their bit count (before the group scan), once to pack
+    // them (after it).  Holding 16*QPT table entries per thread across the
+    // scan would cost more registers than the second reads cost time.  Waves
+    // whose threads all hold full loads take the variant without per-symbol
+    // masks (kMask false); only the wave with the ragged end of a block needs
+    // them (symbols past m then read entry 0 and are masked to zero).
     const bool wave_full = __all(m == kSyms);
-    uint32_t bits = 0;
-    uint32_t qbits[QPT];
+    uint32_t qbits[QPT];  // the thread's bits before each of its loads (sub-block index)
     auto count_bits = [&](auto mask_tag) {
         constexpr bool kMask = decltype(mask_tag)::value;
         uint32_t mn = 255u;  // the smallest code length met: 0 = a symbol without a code
@@ -452,7 +492,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         }
         if (mn == 0) report(err, HC_ERR_SYMBOL_ABSENT);
     };
-    if (wave_full)
+    if (kHanded)
+        ;
+    else if (wave_full)
         count_bits(std::integral_constant<bool, false>());
     else
         count_bits(std::integral_constant<bool, true>());
@@ -471,12 +513,14 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             // bits; one flush retires at most one word.
             auto pack = [&](auto mask_tag) {
                 constexpr bool kMask = decltype(mask_tag)::value;
+                uint32_t run = 0;  // the thread's bits so far
 #pragma unroll
                 for (uint32_t k = 0; k < kSyms; k += FPS) {
                     if ((k & (kQuadSyms - 1)) == 0) {
                         if (k) __builtin_amdgcn_sched_barrier(0);
                         const uint32_t i = k / 4;
                         asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]));
+                        if (kHanded) qbits[k / kQuadSyms] = run;
                     }
                     uint32_t gc = 0, gsum = 0;
 #pragma unroll
@@ -487,6 +531,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
                         gsum += e;  // the low byte sums the lengths (<= 32)
                     }
                     const uint32_t gl = gsum & 255u;
+                    run += gl;
                     acc = (acc << gl) | gc;
                     nacc += gl;
                     const uint32_t need = nacc >= 32 ? 1u : 0u;
@@ -1111,32 +1156,31 @@ hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, h
 }
 
 hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t qpt, uint32_t max_len, uint32_t S,
-                         uint64_t *scratch, uint32_t *err, hipStream_t s, uint32_t steps)
+                         void *scratch, uint32_t *err, hipStream_t s, uint32_t steps)
 {
     if (tiles == 0) return hipSuccess;
     const uint32_t tpb = tiles_per_block(B, qpt);
     const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * qpt * max_len + 31ull) / 32ull + 2);
     const uint32_t cpb = S ? (B + S - 1) / S : 1;
-    uint32_t *tile_bits = reinterpret_cast<uint32_t *>(scratch);
+    uint32_t *tile_bits = static_cast<uint32_t *>(scratch);
     uint32_t *tile_pos = tile_bits + tiles;
+    uint16_t *thread_bits = qpt >= 2 ? reinterpret_cast<uint16_t *>(tile_pos + tiles) : nullptr;
     const dim3 grid((uint32_t)tiles);
     const size_t lds = lds_words * 4;
     const bool packed = max_len <= (uint32_t)kPackedMaxLen;
     // 1. lengths
     if (!(steps & kStepLengths))
         ;
-    else if (!packed)
-        k_count<false, 1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
     else if (qpt == 4)
-        k_count<true, 4><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
+        k_count<4><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, err);
     else if (qpt == 2)
-        k_count<true, 2><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
+        k_count<2><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, err);
     else
-        k_count<true, 1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, err);
+        k_count<1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, err);
     // 2. offsets
     if (steps & kStepOffsets) k_offsets<<<dim3(jl.count), kOffThreads, 0, s>>>(jl, B, tpb, tile_bits, tile_pos, err);
     // 3. packing
-#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tile_pos, S, cpb, lds_words, err)
+#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tile_pos, thread_bits, S, cpb, lds_words, err)
     if (!(steps & kStepPack)) {
     } else if (!packed) {
         HC_ENC(false, 1, 1);
