@@ -833,6 +833,9 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 // (8 consecutive 16-byte loads) into a private LDS ring, and decoded output is
 // gathered in registers and stored a line at a time.
 constexpr uint32_t kRingWords = 64;               // four 16-word halves: two lines
+// Where a decode lane's output rounds that fall outside its chunk are stored
+// (16 bytes per lane of a work-group; the contents are never read).
+__device__ __attribute__((aligned(16))) uint8_t g_decode_sink[kDecThreads * 16];
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: lanes spread over the banks
 
 // Stream quad q (16 bytes), with q clamped to [0, q_last] (q_last at most the
@@ -939,10 +942,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     // lines at different times.  So lines are requested only at sync points,
     // every fourth round (rounds 2 and 6 of an output line, away from the line
     // stores, which a wait would also cover), by all lanes together: each lane
-    // requests the line after its ring's end into registers f, and at the
-    // next sync point (four rounds later, when the load has landed) moves it
-    // into the ring if two halves are free, else requests it again (a cache
-    // hit).  Four rounds
+    // requests the line after its ring's end into registers f, and at a
+    // later sync point (four rounds on or more, when the load has landed)
+    // moves it into the ring once two halves are free and requests the next.
+    // The line waits in registers meanwhile: requesting it again would find
+    // it evicted from L2 as often as not, with thousands of lanes streaming.  Four rounds
     // consume at most 32 words (4 * R * max_len <= 1024 bits), and after a
     // sync point the ring holds at least three halves from the current word
     // on, so a round never reads a word the ring does not hold.
@@ -977,19 +981,26 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     uint32_t vend = 4;                      // halves [0, 4) are in the ring after the set-up
     v4u f[8];
     {
+        // Nothing may be pending when the loops start: a load still pending
+        // there would make the compiler's waits for f in the loops count only
+        // the loads behind it, and so also wait for the line stores issued
+        // since the previous sync round.  So line 2 is requested first and
+        // waited for (the empty asm) with lines 0 and 1.
         v4u a[8], b[8];
+        load_line(2, f);
         load_line(0, a);
         load_line(1, b);
-        load_line(2, f);
         put_line(0, a);
         put_line(1, b);
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) asm volatile("" ::"v"(f[j].x), "v"(f[j].y), "v"(f[j].z), "v"(f[j].w));
     }
     auto sync_lines = [&]() {
-        if (vend - (nxt >> 4) <= 2) {  // two halves free: f (line vend / 2) moves in
+        if (vend - (nxt >> 4) <= 2) {  // two halves free: f (line vend / 2) moves in, the next line is requested
             put_line(vend >> 1, f);
             vend += 2;
+            load_line(vend >> 1, f);
         }
-        load_line(vend >> 1, f);
     };
 
     // ---- output: a line of 128 bytes in registers, stored whole.  Round v
@@ -1003,18 +1014,34 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     const uint32_t v_first = ph / R;                       // round of the chunk's first byte
     const uint32_t v_end = v_first + nsym / R;             // after the last full round
     HC_G uint8_t *const line0 = dst - ph;                  // the line holding the first byte
-    uint32_t ow[32];
+    //
+    // A store's data registers may not be written again before the store has
+    // completed, so the rounds of the next line must not write the registers
+    // of the line being stored: the line is copied into st and stored from
+    // there, and st is kept allocated until the next store (the empty asm),
+    // one line of decoding later, by when the store has long completed.
+    //
+    // Every line issues all its stores: a round the lane does not own goes
+    // to a sink instead of being skipped.  A path through the loop without
+    // stores would make the compiler count, at the next wait for the line in
+    // f, only the loads behind f, and so wait for these stores as well.
+    uint32_t ow[32], st[32];
+#pragma unroll
+    for (uint32_t i = 0; i < 32; ++i) st[i] = 0;
+    HC_G uint8_t *const sink = (HC_G uint8_t *)g_decode_sink + 16 * tid;
     auto store_line = [&](uint32_t lb) {  // the rounds [lb, lb + kLineRounds) that exist
+#pragma unroll
+        for (uint32_t i = 0; i < 32; i += 4) asm volatile("" ::"v"(st[i]), "v"(st[i + 1]), "v"(st[i + 2]), "v"(st[i + 3]));
+#pragma unroll
+        for (uint32_t i = 0; i < 32; ++i) st[i] = ow[i];
 #pragma unroll
         for (uint32_t r = 0; r < kLineRounds; ++r) {
             const uint32_t v = lb + r;
-            if (v >= v_first && v < v_end) {
-                HC_G uint8_t *p = line0 + (uint64_t)R * v;
-                if (R == 16)
-                    *(HC_G v4u *)p = v4u{ow[4 * r], ow[4 * r + 1], ow[4 * r + 2], ow[4 * r + 3]};
-                else
-                    *(HC_G v2u *)p = v2u{ow[2 * r], ow[2 * r + 1]};
-            }
+            HC_G uint8_t *p = (v >= v_first && v < v_end) ? line0 + (uint64_t)R * v : sink;
+            if (R == 16)
+                *(HC_G v4u *)p = v4u{st[4 * r], st[4 * r + 1], st[4 * r + 2], st[4 * r + 3]};
+            else
+                *(HC_G v2u *)p = v2u{st[2 * r], st[2 * r + 1]};
         }
     };
     uint32_t k = 0;  // symbols of the full rounds
