@@ -1048,8 +1048,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
 
     if (fixed8) {
         // Every code is 8 bits: symbol q of a round is byte 3 - (q & 3) of
-        // word nxt + q / 4, so a round is four ring words and sixteen table
-        // lookups.
+        // word nxt + q / 4 (a chunk starts on a word: S is a multiple of 16),
+        // so a round is four ring words and sixteen table lookups.
         const uint32_t ncode = s_count[8];
         uint32_t bad8 = 0;
         auto code_at = [&](uint32_t q) -> uint32_t {
@@ -1057,22 +1057,35 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             bad8 |= (uint32_t)(cd >= ncode);
             return cd;
         };
-        for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
+        // All 256 bytes coded (a complete code: 2^8 codes of 8 bits): canonical
+        // order is then value order, so every symbol is its own code and a
+        // payload word holds four symbols, first in its top byte.
+        const bool identity = ncode == kNumSym;  // uniform over the group: one job per group
+        auto lines = [&](auto identity_tag) {
+            constexpr bool kIdentity = decltype(identity_tag)::value;
+            for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
 #pragma unroll
-            for (uint32_t r = 0; r < kLineRounds; ++r) {
-                if (r % 8 == 2) sync_lines();  // 8 rounds take 32 words: one sync per line of output
-                const uint32_t v = lb + r;
-                if (v >= v_first && v < v_end) {
+                for (uint32_t r = 0; r < kLineRounds; ++r) {
+                    if (r % 8 == 2) sync_lines();  // 8 rounds take 32 words: one sync per line of output
+                    const uint32_t v = lb + r;
+                    if (v >= v_first && v < v_end) {
 #pragma unroll
-                    for (uint32_t q = 0; q < kRoundWords; ++q)
-                        ow[kRoundWords * r + q] = s_sorted[code_at(4 * q)] | (s_sorted[code_at(4 * q + 1)] << 8) |
-                                                  (s_sorted[code_at(4 * q + 2)] << 16) |
-                                                  (s_sorted[code_at(4 * q + 3)] << 24);
-                    nxt += R / 4;
+                        for (uint32_t q = 0; q < kRoundWords; ++q)
+                            ow[kRoundWords * r + q] =
+                                kIdentity ? __builtin_bswap32(ring[(nxt + q) & 63u])
+                                          : s_sorted[code_at(4 * q)] | (s_sorted[code_at(4 * q + 1)] << 8) |
+                                                (s_sorted[code_at(4 * q + 2)] << 16) |
+                                                (s_sorted[code_at(4 * q + 3)] << 24);
+                        nxt += R / 4;
+                    }
                 }
+                store_line(lb);
             }
-            store_line(lb);
-        }
+        };
+        if (identity)
+            lines(std::integral_constant<bool, true>());
+        else
+            lines(std::integral_constant<bool, false>());
         k = nsym - nsym % R;
         if (k < nsym) {  // fewer than R symbols: at most R/4 words from nxt
             sync_lines();
