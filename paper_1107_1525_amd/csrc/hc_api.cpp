@@ -289,22 +289,18 @@ uint64_t job_table_bytes(uint32_t count)
     return align256((uint64_t)count * sizeof(Job)) + align256(8 * ((uint64_t)count + 1));
 }
 
-// Copies a job list (and the table of job start units) into the head of the
-// caller's workspace.
+// Writes a job list (and the table of job start units) into the head of the
+// caller's workspace, in stream order and without waiting for the stream (a
+// copy from pageable host memory would wait for the stream's earlier work).
 hc_status upload_jobs(std::vector<Job> &jobs, uint64_t total_units, void *ws, hipStream_t s, JobList *jl)
 {
-    const uint64_t count = jobs.size();
-    // one staging buffer: jobs, pad, starts; copied in a single transfer
-    const uint64_t head = job_table_bytes((uint32_t)count);
-    std::vector<char> stage(head, 0);
-    memcpy(stage.data(), jobs.data(), count * sizeof(Job));
-    uint64_t *starts = reinterpret_cast<uint64_t *>(stage.data() + align256(count * sizeof(Job)));
-    for (uint64_t k = 0; k < count; ++k) starts[k] = jobs[k].unit_begin;
-    starts[count] = total_units;
-    if (hipMemcpyAsync(ws, stage.data(), head, hipMemcpyHostToDevice, s) != hipSuccess) return HC_ERR_HIP;
-    jl->jobs = static_cast<const Job *>(ws);
-    jl->starts = reinterpret_cast<const uint64_t *>(static_cast<char *>(ws) + align256(count * sizeof(Job)));
-    jl->count = (uint32_t)count;
+    const uint32_t count = (uint32_t)jobs.size();
+    Job *d_jobs = static_cast<Job *>(ws);
+    uint64_t *d_starts = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + align256((uint64_t)count * sizeof(Job)));
+    if (launch_put_jobs(jobs.data(), count, total_units, d_jobs, d_starts, s) != hipSuccess) return HC_ERR_HIP;
+    jl->jobs = d_jobs;
+    jl->starts = d_starts;
+    jl->count = count;
     jl->one = empty_job();
     return HC_OK;
 }

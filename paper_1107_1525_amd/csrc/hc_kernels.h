@@ -86,6 +86,11 @@ inline uint64_t encode_scratch_bound(uint64_t nb, uint32_t B)
     return most;
 }
 
+// Writes a job table and its start units (then 'total') to device memory
+// with kernel launches that carry the jobs as arguments: nothing waits for
+// the stream and the host array may be reused when the call returns.
+hipError_t launch_put_jobs(const Job *jobs, uint32_t count, uint64_t total, Job *d_jobs, uint64_t *d_starts,
+                           hipStream_t s);
 hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, hipStream_t s);
 // Encode steps (bit mask): the length pass, the offset scan, the packing.
 constexpr uint32_t kStepLengths = 1, kStepOffsets = 2, kStepPack = 4, kStepAll = 7;

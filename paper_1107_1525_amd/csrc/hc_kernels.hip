@@ -88,6 +88,25 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t count, uint64_t value)
         p[i] = value;
 }
 
+// Up to kJobsPerPut jobs of a table travel by value as one launch's arguments.
+constexpr uint32_t kJobsPerPut = 32;
+struct JobChunk {
+    Job jobs[kJobsPerPut];
+    uint32_t first, count;  // table entries [first, first + count)
+    uint32_t table_count;   // entries of the whole table
+    uint64_t total;         // units of the whole table, after the last start
+};
+
+__global__ void k_put_jobs(JobChunk c, Job *jobs, uint64_t *starts)
+{
+    const uint32_t t = threadIdx.x;
+    if (t < c.count) {
+        jobs[c.first + t] = c.jobs[t];
+        starts[c.first + t] = c.jobs[t].unit_begin;
+    }
+    if (t == 0 && c.first + c.count == c.table_count) starts[c.table_count] = c.total;
+}
+
 // The job owning launch unit u (the last job whose unit_begin <= u), found by
 // the 64 lanes of one wave together: each round samples 64 job starts and
 // keeps the bracket of the last one <= u, so 10^4 jobs take 3 rounds of one
@@ -1192,6 +1211,21 @@ hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, h
 {
     k_hist_zero<<<dim3(jl.count), kNumSym, 0, s>>>(jl);
     if (units) k_hist<<<dim3((uint32_t)units), kHistThreads, 0, s>>>(jl, chunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_jobs(const Job *jobs, uint32_t count, uint64_t total, Job *d_jobs, uint64_t *d_starts,
+                           hipStream_t s)
+{
+    for (uint32_t first = 0; first < count; first += kJobsPerPut) {
+        JobChunk c;
+        c.first = first;
+        c.count = count - first < kJobsPerPut ? count - first : kJobsPerPut;
+        c.table_count = count;
+        c.total = total;
+        for (uint32_t k = 0; k < c.count; ++k) c.jobs[k] = jobs[first + k];
+        k_put_jobs<<<1, kJobsPerPut, 0, s>>>(c, d_jobs, d_starts);
+    }
     return hipGetLastError();
 }
 

@@ -10,16 +10,21 @@ GPU:
      (input + output + offsets + index) fits the HBM budget;
   3. launches one batch per phase over the newly admitted requests: block
      decode of the decompress requests (hc_decode_batch) on the decode
-     stream; symbol counts of the compress requests (hc_histogram_batch),
-     the 2 KiB-per-request read-back, the host code build, and their block
-     encode (hc_encode_batch) on the encode stream.
+     stream; symbol counts of the compress requests (hc_histogram_batch) on
+     the count stream, with an asynchronous 2 KiB-per-request copy of the
+     counts to pinned host memory;
+  4. for every compress batch whose counts have arrived (its event fired):
+     builds the codes on the host and launches the block encode
+     (hc_encode_batch) on the encode stream, followed by an asynchronous
+     copy of the batch's offset tables (whose last entries are the stream
+     sizes) to pinned host memory.
 
-So requests that arrive while others are on the GPU are admitted as soon as
-memory frees up, and their kernels overlap the batches still running.  Code
-tables stay resident on the device for the life of the request.  A result
-does not depend on what it was batched with: the kernels treat every buffer
-as an independent job (one table per job, offsets relative to its own
-stream).
+The loop never blocks on the device: it only polls events, so requests that
+arrive while others are on the GPU are admitted as soon as memory frees up,
+and their kernels overlap the batches still running.  Code tables stay
+resident on the device for the life of the request.  A result does not
+depend on what it was batched with: the kernels treat every buffer as an
+independent job (one table per job, offsets relative to its own stream).
 """
 from __future__ import annotations
 
@@ -33,7 +38,7 @@ import torch
 
 from . import (DeviceCodebook, Encoded, HcError, hc_batch_workspace_bytes, hc_build_codebook,
                hc_codebook_from_lengths, hc_decode_batch, hc_encode_batch, hc_encode_bound, hc_histogram_batch,
-               hc_sub_index_entries, make_items, new_error_word, num_blocks, read_error, set_item)
+               hc_sub_index_entries, make_items, new_error_word, num_blocks, set_item)
 
 ALIGN = 256
 
@@ -118,22 +123,44 @@ class _Batch:
     requests: List[Request]
     event: torch.cuda.Event
     keep: list  # workspaces and item tables that must live until the batch ends
-    err: torch.Tensor
+    errh: torch.Tensor  # pinned copy of the batch's error word
+    offs: Optional[torch.Tensor] = None  # compress: pinned copy of the batch's offset tables
+    last: Optional[List[int]] = None  # compress: index in offs of every request's stream size
+
+
+@dataclass
+class _Counting:
+    """A compress batch whose symbol counts are on their way to the host."""
+
+    requests: List[Request]
+    event: torch.cuda.Event
+    hists: torch.Tensor  # pinned int64[count, 256]
+    keep: list
+    off_all: torch.Tensor  # the batch's offset tables, back to back
+    last: List[int]  # index in off_all of every request's stream size
 
 
 class Server:
     def __init__(self, block_size: int = 65536, sub_block: int = 1024, hbm_budget: int = 32 << 30,
-                 max_batch: int = 4096, device="cuda", clock=time.perf_counter):
+                 max_batch: int = 4096, device="cuda", clock=time.perf_counter, tables: int = 256):
         self.B, self.S = block_size, sub_block
         self.adm = Admission(hbm_budget, max_batch)
         self.device = torch.device(device)
         self.clock = clock
         self.inflight: List[_Batch] = []
+        self.counting: List[_Counting] = []
         self.done: List[Request] = []
         self.hist_stream = torch.cuda.Stream(device=self.device)
         self.enc_stream = torch.cuda.Stream(device=self.device)
         self.dec_stream = torch.cuda.Stream(device=self.device)
-        self._free_cb: List[DeviceCodebook] = []  # resident code tables handed back by recycle()
+        # Resident code tables, uploaded once here: a compress request takes
+        # one and refreshes it with an asynchronous copy, so no request waits
+        # for a table allocation or a synchronous upload.  Results keep
+        # theirs until handed back with recycle(); when none is free a new
+        # one is uploaded.
+        one = np.zeros(256, np.uint8)
+        one[0] = 1
+        self._free_cb: List[DeviceCodebook] = [DeviceCodebook(hc_codebook_from_lengths(one)) for _ in range(tables)]
         self._next_id = 0
         self.iterations = 0
         self.max_inflight_requests = 0
@@ -158,17 +185,22 @@ class Server:
     def in_use(self) -> int:
         return self.adm.in_use
 
+    @property
+    def idle(self) -> bool:
+        """Nothing waiting, counting or on the device."""
+        return not (self.waiting or self.counting or self.inflight)
+
     def _retire(self, now: float) -> int:
         still, retired = [], 0
         for b in self.inflight:
             if b.event.query():
-                e = read_error(b.err)
+                e = int(b.errh[0]) & 0xFFFFFFFF
                 if e:
                     raise HcError(e, "batch (device)")
-                for r in b.requests:
+                offs = b.offs.numpy() if b.offs is not None else None
+                for k, r in enumerate(b.requests):
                     if r.kind == "compress":
-                        nb = num_blocks(r.n, self.B)
-                        C = int(r.bufs["off"][nb].item())
+                        C = int(offs[b.last[k]])
                         # the result owns the tables it was encoded with (hand them back with recycle())
                         r.result = Encoded(r.bufs["out"][:C], r.bufs["off"], r.bufs["sub"], r.n, self.B, self.S,
                                            r.bufs["cb"])
@@ -205,27 +237,51 @@ class Server:
             ws = torch.empty(max(hc_batch_workspace_bytes(items, self.B), ALIGN), dtype=torch.uint8, device=dev)
             err = new_error_word(dev)
             hc_decode_batch(items, self.B, self.S, ws, err, stream=self.dec_stream)
+            errh = torch.empty(1, dtype=torch.int32, pin_memory=True)
+            errh.copy_(err, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.dec_stream)
-        self.inflight.append(_Batch(reqs, ev, [ws, items], err))
+        self.inflight.append(_Batch(reqs, ev, [ws, items, err], errh))
 
-    def _launch_compress(self, reqs: List[Request]):
+    def _launch_counts(self, reqs: List[Request]):
         dev, B, S = self.device, self.B, self.S
         items = make_items(len(reqs))
+        # the batch's counts, offset tables and index tables, each in one allocation
+        nbs = [num_blocks(r.n, B) for r in reqs]
+        subs = [max(hc_sub_index_entries(r.n, B, S), 1) for r in reqs] if S else None
+        hist_all = torch.empty((len(reqs), 256), dtype=torch.int64, device=dev)
+        off_all = torch.empty(sum(nbs) + len(reqs), dtype=torch.int64, device=dev)
+        sub_all = torch.empty(sum(subs), dtype=torch.int32, device=dev) if S else None
+        last, o, si = [], 0, 0
         for k, r in enumerate(reqs):
-            r.bufs["hist"] = torch.empty(256, dtype=torch.int64, device=dev)
-            r.bufs["off"] = torch.empty(num_blocks(r.n, B) + 1, dtype=torch.int64, device=dev)
-            r.bufs["sub"] = (torch.empty(max(hc_sub_index_entries(r.n, B, S), 1), dtype=torch.int32, device=dev)
-                             if S else None)
+            r.bufs["hist"] = hist_all[k]
+            r.bufs["off"] = off_all[o: o + nbs[k] + 1]
+            last.append(o + nbs[k])
+            o += nbs[k] + 1
+            if S:
+                r.bufs["sub"] = sub_all[si: si + subs[k]]
+                si += subs[k]
+            else:
+                r.bufs["sub"] = None
             set_item(items, k, x=r.data, hist=r.bufs["hist"])
-        main = torch.cuda.current_stream(dev)
-        self.hist_stream.wait_stream(main)
+        self.hist_stream.wait_stream(torch.cuda.current_stream(dev))
+        hists = torch.empty((len(reqs), 256), dtype=torch.int64, pin_memory=True)
         with torch.cuda.stream(self.hist_stream):
             hws = torch.empty(max(hc_batch_workspace_bytes(items, B), ALIGN), dtype=torch.uint8, device=dev)
             hc_histogram_batch(items, hws, stream=self.hist_stream)
-            # the read-back waits for the counting only, not for batches on the other streams
-            hists = torch.stack([r.bufs["hist"] for r in reqs]).cpu().numpy().view(np.uint64)
-        self.enc_stream.wait_stream(main)
+            hists.copy_(hist_all, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.hist_stream)
+        self.counting.append(_Counting(reqs, ev, hists, [hws, items], off_all, last))
+
+    def _launch_encode(self, c: _Counting):
+        dev, B, S = self.device, self.B, self.S
+        reqs = c.requests
+        hists = c.hists.numpy().view(np.uint64)
+        items = make_items(len(reqs))
+        self.enc_stream.wait_stream(torch.cuda.current_stream(dev))
+        self.enc_stream.wait_event(c.event)
+        offs = torch.empty(c.off_all.numel(), dtype=torch.int64, pin_memory=True)
         with torch.cuda.stream(self.enc_stream):
             for k, r in enumerate(reqs):
                 cb = hc_build_codebook(hists[k])
@@ -245,15 +301,27 @@ class Server:
             ws = torch.empty(max(hc_batch_workspace_bytes(items, B), ALIGN), dtype=torch.uint8, device=dev)
             err = new_error_word(dev)
             hc_encode_batch(items, B, S, ws, err, stream=self.enc_stream)
+            # every stream's size is its last offset: the batch's offset tables
+            # (8 bytes per block) come back in one copy
+            offs.copy_(c.off_all, non_blocking=True)
+            errh = torch.empty(1, dtype=torch.int32, pin_memory=True)
+            errh.copy_(err, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.enc_stream)
-        self.inflight.append(_Batch(reqs, ev, [hws, ws, items], err))
+        self.inflight.append(_Batch(reqs, ev, c.keep + [ws, items, err], errh, offs, c.last))
 
     # ------------------------------------------------------------ the loop
     def step(self) -> int:
         """One engine iteration; returns the number of requests retired."""
         now = self.clock()
         retired = self._retire(now)
+        still = []
+        for c in self.counting:
+            if c.event.query():
+                self._launch_encode(c)
+            else:
+                still.append(c)
+        self.counting = still
         admitted = self.adm.admit(now)
         if admitted:
             self.iterations += 1
@@ -262,15 +330,15 @@ class Server:
             if deco:
                 self._launch_decode(deco)
             if comp:
-                self._launch_compress(comp)
-        n_inflight = sum(len(b.requests) for b in self.inflight)
+                self._launch_counts(comp)
+        n_inflight = sum(len(b.requests) for b in self.inflight) + sum(len(c.requests) for c in self.counting)
         self.max_inflight_requests = max(self.max_inflight_requests, n_inflight)
         return retired
 
     def run_until_idle(self):
-        while self.waiting or self.inflight:
+        while not self.idle:
             self.step()
-            if not self.inflight and self.waiting:
+            if not self.inflight and not self.counting and self.waiting:
                 wait = self.waiting[0].arrival - self.clock()
                 if wait > 0:
                     time.sleep(min(wait, 0.002))

@@ -77,7 +77,7 @@ def test_budget_limits_concurrency(hc):
     for x in xs:
         srv.submit(Request("compress", data=x, arrival=0.0))
     peak = 0
-    while srv.waiting or srv.inflight:
+    while not srv.idle:
         srv.step()
         peak = max(peak, srv.in_use)
         assert srv.in_use <= srv.adm.budget
