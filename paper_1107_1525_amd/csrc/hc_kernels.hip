@@ -1127,17 +1127,19 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     uint32_t pre = ring[nxt & 63u];
     uint32_t bad = 0;  // kLutBadFlag: an invalid prefix was met
 
-    // One symbol from the buffer (which holds >= max_len bits here).  The
-    // entry's low byte is the code length; invalid prefixes carry kLutBadFlag
-    // and a shift of 1, so codes of at most lut_bits bits need no test; longer
-    // codes (kLong) take the canonical-range search on the buffered bits.
+    // One symbol from the buffer (which holds >= max_len bits here), as its
+    // table entry (symbol << 8) | length.  Invalid prefixes carry kLutBadFlag
+    // and a length of 1, so codes of at most lut_bits bits need no test;
+    // longer codes (kLong) take the canonical-range search on the buffered
+    // bits.  The lengths are summed as whole entries (esum): the symbols sit
+    // above bit 8 and the at most SPR lengths summed between refills total
+    // <= 32, so the low byte of the sum is their total.
     const uint32_t lut_shift = 32 - K;
-    auto decode_sym = [&]() -> uint32_t {
-        const uint32_t e = s_lut[(uint32_t)(buf >> 32) >> lut_shift];
-        uint32_t L = e & 255u;
-        uint32_t sym = e >> 8;
-        bad |= e;
-        if (kLong && L == 0) {
+    uint32_t esum = 0;
+    auto decode_entry = [&]() -> uint32_t {
+        uint32_t e = s_lut[(uint32_t)(buf >> 32) >> lut_shift];
+        if (kLong && (e & 255u) == 0) {
+            uint32_t L = 0, sym = 0;
             for (uint32_t l = K + 1; l <= max_len; ++l) {
                 const uint32_t cv = (uint32_t)(buf >> (64 - l));
                 const uint32_t d = cv - s_first[l];
@@ -1147,18 +1149,18 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
                     break;
                 }
             }
-            if (L == 0) {
-                bad |= kLutBadFlag;
-                L = 1;
-            }
+            e = L ? (sym << 8) | L : (kLutBadFlag | 1u);
         }
-        buf <<= (L & 63u);
-        nbits -= L;
-        return sym;
+        bad |= e;
+        buf <<= (e & 63u);
+        esum += e;
+        return e;
     };
     // Tops the buffer up to >= 32 bits with the word read ahead, without a
     // branch; the ring word after it is read for the next refill.
     auto refill = [&]() {
+        nbits -= esum & 255u;
+        esum = 0;
         const bool need = nbits < 32;
         const uint32_t w = need ? pre : 0u;
         buf |= (uint64_t)w << ((32 - nbits) & 63u);
@@ -1178,7 +1180,9 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
                 for (uint32_t q = 0; q < kRoundWords; ++q) o4[q] = 0;
 #pragma unroll
                 for (uint32_t q = 0; q < R; ++q) {
-                    o4[q >> 2] |= decode_sym() << (8 * (q & 3));
+                    // the entry's byte 1 (the symbol) into byte q & 3 of the word, the other bytes kept
+                    constexpr uint32_t kSel[4] = {0x03020105u, 0x03020500u, 0x03050100u, 0x05020100u};
+                    o4[q >> 2] = __builtin_amdgcn_perm(decode_entry(), o4[q >> 2], kSel[q & 3]);
                     if ((q + 1) % SPR == 0 || q + 1 == R) refill();
                 }
 #pragma unroll
@@ -1191,7 +1195,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     if (k < nsym) {  // the ragged last round: one symbol between refills
         sync_lines();
         for (uint32_t q = 0; q < nsym - k; ++q) {
-            dst[k + q] = (uint8_t)decode_sym();
+            dst[k + q] = (uint8_t)(decode_entry() >> 8);
             refill();
         }
     }
