@@ -158,7 +158,8 @@ hc_cb_handle hc_cbset_handle(hc_cbset set, uint32_t k);
 /* be NULL), and refreshes the device tables with one asynchronous copy   */
 /* on 'stream': work enqueued later on that stream sees the new tables.   */
 /* Waits (host side) for the set's previous copy before reusing the       */
-/* staging area.  Errors: INVALID_ARG, CODE_TOO_LONG, HIP.                 */
+/* staging area.  The codes are built on up to eight host threads, the    */
+/* calling one included.  Errors: INVALID_ARG, CODE_TOO_LONG, HIP.         */
 hc_status hc_cbset_build(hc_cbset set, const uint64_t *h_hists, hc_codebook *h_out, void *stream);
 
 /* Frees a set (NULL is accepted).  Waits for the device to finish.       */

@@ -1,10 +1,17 @@
 // C ABI entry points: argument checks, then kernel launches on the caller's
 // stream.  See include/hc.h for the contract of every call.
 #include <hip/hip_runtime_api.h>
+#include <sched.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
+#include <atomic>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "hc_internal.h"
@@ -21,6 +28,85 @@ bool valid_block_size(uint32_t B) { return B >= 16 && B <= (1u << 26) && (B % 16
 bool valid_sub_block(uint32_t S) { return S == 0 || (S % 16) == 0; }
 
 hc_status hip_status(hipError_t e) { return e == hipSuccess ? HC_OK : HC_ERR_HIP; }
+
+// A parallel for over [0, count) on a few host threads, the caller included,
+// for the per-stream code builds of a codebook set (independent, a few
+// microseconds each, and on the critical path between the counting and the
+// encoding kernels).  The workers live for the process (a forked child makes
+// its own); one loop runs at a time.
+class HostPool {
+public:
+    static HostPool &get()
+    {
+        static std::mutex m;
+        static HostPool *pool = nullptr;
+        std::lock_guard<std::mutex> g(m);
+        if (!pool || pool->pid_ != getpid()) pool = new HostPool();  // a forked child's workers did not survive
+        return *pool;
+    }
+
+    void run(uint32_t count, const std::function<void(uint32_t)> &f)
+    {
+        std::lock_guard<std::mutex> one_at_a_time(run_m_);
+        if (workers_ == 0 || count < 4) {
+            for (uint32_t i = 0; i < count; ++i) f(i);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(m_);
+            f_ = &f;
+            count_ = count;
+            next_.store(0);
+            busy_ = workers_;
+            ++generation_;
+        }
+        cv_.notify_all();
+        drain();
+        std::unique_lock<std::mutex> g(m_);
+        done_cv_.wait(g, [&] { return busy_ == 0; });
+        f_ = nullptr;
+    }
+
+private:
+    HostPool() : pid_(getpid())
+    {
+        cpu_set_t set;
+        unsigned cpus = std::thread::hardware_concurrency();
+        if (sched_getaffinity(0, sizeof(set), &set) == 0) cpus = (unsigned)CPU_COUNT(&set);
+        workers_ = cpus > 1 ? std::min(cpus - 1, 7u) : 0u;
+        for (unsigned w = 0; w < workers_; ++w) std::thread([this] { loop(); }).detach();
+    }
+
+    void drain()
+    {
+        for (uint32_t i = next_.fetch_add(1); i < count_; i = next_.fetch_add(1)) (*f_)(i);
+    }
+
+    void loop()
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> g(m_);
+                cv_.wait(g, [&] { return generation_ != seen; });
+                seen = generation_;
+            }
+            drain();
+            std::lock_guard<std::mutex> g(m_);
+            if (--busy_ == 0) done_cv_.notify_one();
+        }
+    }
+
+    pid_t pid_;
+    unsigned workers_ = 0;
+    std::mutex run_m_, m_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(uint32_t)> *f_ = nullptr;
+    uint32_t count_ = 0;
+    std::atomic<uint32_t> next_{0};
+    unsigned busy_ = 0;
+    uint64_t generation_ = 0;
+};
 
 }  // namespace
 
@@ -163,10 +249,16 @@ extern "C" hc_status hc_cbset_build(hc_cbset set, const uint64_t *h_hists, hc_co
     if (!set || !h_hists) return HC_ERR_INVALID_ARG;
     hipEvent_t ev = static_cast<hipEvent_t>(set->copy_done);
     if (hipEventSynchronize(ev) != hipSuccess) return HC_ERR_HIP;  // staging no longer being read
-    for (uint32_t k = 0; k < set->count; ++k) {
+    // the codes of the set's streams are independent: built on several host threads
+    std::atomic<int> first_error{HC_OK};
+    HostPool::get().run(set->count, [&](uint32_t k) {
         hc_codebook cb;
         hc_status st = hc_build_codebook(h_hists + (size_t)256 * k, &cb);
-        if (st != HC_OK) return st;
+        if (st != HC_OK) {
+            int ok = HC_OK;
+            first_error.compare_exchange_strong(ok, st);
+            return;
+        }
         if (cb.max_len == 0) {  // an empty buffer: a one-symbol code keeps the tables usable
             uint8_t len[kNumSym] = {0};
             len[0] = 1;
@@ -175,7 +267,8 @@ extern "C" hc_status hc_cbset_build(hc_cbset set, const uint64_t *h_hists, hc_co
         set->handles[k].host = cb;
         build_dev_tables(cb, &set->staging[k]);
         if (h_out) h_out[k] = cb;
-    }
+    });
+    if (first_error.load() != HC_OK) return static_cast<hc_status>(first_error.load());
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipMemcpyAsync(set->d_tables, set->staging, (size_t)set->count * sizeof(DevTables), hipMemcpyHostToDevice,
                        s) != hipSuccess ||
