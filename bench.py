@@ -145,15 +145,19 @@ class Workload:
         hc, torch = self.hc, self.torch
 
         def mark(k, i):
-            if ev is not None:
+            if ev is not None and k in ev:
                 ev[k][i].record()
 
         mark("hist", 0)
         hc.hc_histogram_batch(self.hist_items, self.hist_ws)
         mark("hist", 1)
         self.hist_host.copy_(self.hist, non_blocking=True)
+        mark("copy", 1)
         torch.cuda.current_stream().synchronize()
+        t1 = time.perf_counter()
         self.cbset.build(self.hist_host.numpy().view("uint64"))  # all codes, one table copy
+        if ev is not None and "copy" in ev:
+            ev["host"] = time.perf_counter() - t1
         mark("enc", 0)
         hc.hc_encode_batch(self.enc_items, self.B, self.S, self.ws, self.err)
         mark("enc", 1)
@@ -239,10 +243,17 @@ def cpu_baseline(w, oracle, np):
         t0 = time.perf_counter()
         block_parallel(pool)
         tp = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": round(nbytes / tp / 1e9, 4),
         "unit": "GB/s",
         "cores": cores,
+        "cpu": model,
         "kind": "oracle",
         "sample": f"segments 0-5 (uniform, skewed, fp32, twice) of the 4 GiB mixed workload, {nbytes >> 20} MiB, "
                   f"B={B}: counts + code + block encode + strict decode, block-parallel over {cores} threads",
@@ -333,11 +344,35 @@ def batched_bench(hc, synth, torch, np, count: int, B: int, S: int):
         raise hc.HcError(hc.read_error(err), "batched bench")
     for k in range(count):
         assert torch.equal(ys[k][: sizes[k]], xs[k]), f"buffer {k}"
+    # the batched calls captured once in a HIP graph, then replayed
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=side):
+        batched()
+    for y in ys:
+        y.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for k in range(count):
+        assert torch.equal(ys[k][: sizes[k]], xs[k]), f"buffer {k} (graph replay)"
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    res["graph"] = (time.perf_counter() - t0) / reps
+    if hc.read_error(err):
+        raise hc.HcError(hc.read_error(err), "batched bench (graph)")
     return {
         "buffers": count, "bytes": total, "sizes": "log-uniform 1 KiB-64 MiB", "data": "Zipf s~U[0.8,1.6]",
         "batched_GBps": round(total / res["batched"] / 1e9, 2), "plain_GBps": round(total / res["plain"] / 1e9, 2),
+        "graph_GBps": round(total / res["graph"] / 1e9, 2),
         "batched_ms": round(res["batched"] * 1e3, 3), "plain_ms": round(res["plain"] * 1e3, 3),
-        "phases": "counts + encode + decode (codebooks fixed)",
+        "graph_ms": round(res["graph"] * 1e3, 3),
+        "phases": "counts + encode + decode (codebooks fixed); graph: the same three batched calls replayed",
     }
 
 
@@ -484,7 +519,9 @@ def traffic_summary(root: str, B: int, S: int):
     print(json.dumps(out, indent=1))
 
 
-def copy_probe(torch):
+def copy_probe(torch, quiet=False):
+    """A plain 1 GiB device-to-device copy: the read + write rate this box
+    reaches on a streaming kernel (the achievable side of the roofline)."""
     n = 1 << 30
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
@@ -501,8 +538,12 @@ def copy_probe(torch):
     e.record()
     torch.cuda.synchronize()
     ms = s.elapsed_time(e) / reps
-    print(json.dumps({"probe": "device copy", "bytes_read": n, "bytes_written": n, "ms": round(ms, 4),
-                      "GBps_read_plus_write": round(2 * n / ms / 1e6, 1)}), flush=True)
+    del a, b
+    rate = 2 * n / ms / 1e6
+    if not quiet:
+        print(json.dumps({"probe": "device copy", "bytes_read": n, "bytes_written": n, "ms": round(ms, 4),
+                          "GBps_read_plus_write": round(rate, 1)}), flush=True)
+    return rate
 
 
 def main():
@@ -544,7 +585,7 @@ def main():
         # HIP events around every launch of the timed steps, on the stream the
         # library launches on (torch's current stream)
         E = torch.cuda.Event
-        evs = [{k: (E(enable_timing=True), E(enable_timing=True)) for k in ("hist", "enc", "dec")}
+        evs = [{k: (E(enable_timing=True), E(enable_timing=True)) for k in ("hist", "copy", "enc", "dec")}
                for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -557,6 +598,11 @@ def main():
         ms_step = wall * 1e3 / args.steps
         avg = lambda k: float(np.mean([e[k][0].elapsed_time(e[k][1]) for e in evs]))
         hist_ms, enc_ms, dec_ms = avg("hist"), avg("enc"), avg("dec")
+        # the 2 KiB-per-stream count read-back (GPU time of the copy) and the
+        # host code build (host clock), each alone
+        readback_ms = float(np.mean([e["hist"][1].elapsed_time(e["copy"][1]) for e in evs]))
+        build_ms = 1e3 * float(np.mean([e["host"] for e in evs]))
+        copy_rate = copy_probe(torch, quiet=True)
         kt = kernel_times(w, torch, np)
         if hc.read_error(w.err):
             raise hc.HcError(hc.read_error(w.err), "kernel timing")
@@ -591,6 +637,7 @@ def main():
             "encode_pct_hbm": round(100 * gb(n + C + off_bytes + sub_bytes, enc_ms) / HBM_PEAK_GBPS, 1),
             "decode_pct_hbm": round(100 * gb(alg["k_decode"], dec_ms) / HBM_PEAK_GBPS, 1),
             "ratio": round(C / n, 5),
+            "count_readback_ms": round(readback_ms, 3), "host_code_build_ms": round(build_ms, 3),
         }
         dominant = max(KERNELS, key=lambda k: kavg[k])
         launch_ms, per_launch = kavg[dominant], alg[dominant]
@@ -600,6 +647,8 @@ def main():
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": load_traffic(KERNEL_SYMBOL[dominant], B, S),
             "bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4),
+            # what a plain 1 GiB device copy reaches on this machine (read + write)
+            "achievable": round(copy_rate, 1), "frac_of_achievable": round(achieved / copy_rate, 4),
         }
         line = {
             "metric": METRIC, "value": round(gb(n, ms_step), 2), "unit": "GB/s", "n_gpus": 1,

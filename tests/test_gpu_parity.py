@@ -486,3 +486,91 @@ def test_codebook_set(hc, oracle):
             assert np.array_equal(enc.stream.cpu().numpy(), oracle.encode(x, 4096, L, C)[0])
             assert torch.equal(hc.decompress(enc), dev(x))
     cset.close()
+
+
+@pytest.mark.parametrize("B,S", [(4096, 0), (65536, 1024)])
+def test_batch_graph_replays(hc, oracle, B, S):
+    """The three batched calls captured once in a HIP graph and replayed: 70
+    buffers (job tables of three argument-carrying launches each), outputs
+    cleared eagerly between replays, every replay equal to the eager calls
+    and to the oracle on sampled buffers."""
+    rng = np.random.default_rng(B + S + 1)
+    cnt = 70
+    sizes = [0, 1, 5] + [int(v) for v in rng.integers(16, 150_000, cnt - 3)]
+    kinds = ["zipf", "uniform", "skewed", "fp32"]
+    xs = []
+    for k, n in enumerate(sizes):
+        kind = kinds[k % 4]
+        if kind == "zipf":
+            xs.append(synth.zipf_bytes(n, float(rng.uniform(0.8, 1.6)), 500 + k))
+        elif kind == "fp32":
+            xs.append(synth.fp32_bytes((n + 3) // 4 * 4, 500 + k)[:n])
+        else:
+            xs.append(synth.segment_bytes(kind, n, 500 + k))
+    xd = [dev(x) for x in xs]
+    hist = torch.zeros((cnt, 256), dtype=torch.int64, device="cuda")
+    h_items = hc.make_items(cnt)
+    for k in range(cnt):
+        hc.set_item(h_items, k, x=xd[k], hist=hist[k])
+    hws = torch.empty(max(hc.hc_batch_workspace_bytes(h_items, B), 256), dtype=torch.uint8, device="cuda")
+    hc.hc_histogram_batch(h_items, hws)
+    dcbs, outs, offs, subs, ys = [], [], [], [], []
+    e_items = hc.make_items(cnt)
+    for k in range(cnt):
+        cb = hc.hc_build_codebook(u64(hist[k]))
+        if cb.max_len == 0:
+            L0 = np.zeros(256, np.uint8)
+            L0[0] = 1
+            cb = hc.hc_codebook_from_lengths(L0)
+        dcbs.append(hc.DeviceCodebook(cb))
+        n = sizes[k]
+        outs.append(torch.zeros(max(hc.hc_encode_bound(n, B, cb.max_len), 16), dtype=torch.uint8, device="cuda"))
+        offs.append(torch.zeros(hc.num_blocks(n, B) + 1, dtype=torch.int64, device="cuda"))
+        subs.append(torch.zeros(max(hc.hc_sub_index_entries(n, B, S), 1), dtype=torch.int32, device="cuda")
+                    if S else None)
+        ys.append(torch.zeros(max(n, 16), dtype=torch.uint8, device="cuda"))
+        hc.set_item(e_items, k, x=xd[k], dcb=dcbs[k], out=outs[k], block_off=offs[k], sub_idx=subs[k])
+    ws = torch.empty(max(hc.hc_batch_workspace_bytes(e_items, B), 256), dtype=torch.uint8, device="cuda")
+    err = hc.new_error_word("cuda")
+    hc.hc_encode_batch(e_items, B, S, ws, err)
+    C = [int(o[-1].item()) for o in offs]
+    d_items = hc.make_items(cnt)
+    for k in range(cnt):
+        hc.set_item(d_items, k, x=outs[k], n=sizes[k], in_bytes=C[k], dcb=dcbs[k], out=ys[k], block_off=offs[k],
+                    sub_idx=subs[k])
+    hc.hc_decode_batch(d_items, B, S, ws, err)
+    torch.cuda.synchronize()
+    assert hc.read_error(err) == 0
+    eager = [(hist[k].clone(), outs[k][: C[k]].clone(), offs[k].clone(), None if S == 0 else subs[k].clone())
+             for k in range(cnt)]
+    for k in range(cnt):
+        assert torch.equal(ys[k][: sizes[k]], xd[k]), k
+    for k in (1, 2, 3, 10, cnt - 1):  # sampled buffers against the oracle's own code and encoder
+        L, Cw = oracle.codebook(oracle.histogram(xs[k]))
+        s_o, off_o, _ = oracle.encode(xs[k], B, L, Cw)
+        assert np.array_equal(eager[k][1].cpu().numpy(), s_o), k
+        assert np.array_equal(u64(eager[k][2]), off_o), k
+
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=side):
+        hc.hc_histogram_batch(h_items, hws)
+        hc.hc_encode_batch(e_items, B, S, ws, err)
+        hc.hc_decode_batch(d_items, B, S, ws, err)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in [hist] + outs + offs + ys + [u for u in subs if u is not None]:
+            t.zero_()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert hc.read_error(err) == 0, rep
+        for k in range(cnt):
+            assert torch.equal(hist[k], eager[k][0]), (rep, k)
+            assert torch.equal(outs[k][: C[k]], eager[k][1]), (rep, k)
+            assert torch.equal(offs[k], eager[k][2]), (rep, k)
+            if S:
+                assert torch.equal(subs[k], eager[k][3]), (rep, k)
+            assert torch.equal(ys[k][: sizes[k]], xd[k]), (rep, k)
