@@ -912,43 +912,111 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     s_sorted[tid] = tb->sorted[tid];
     __syncthreads();  // the last barrier: lanes may leave early from here on
 
+    // ---- the lane's chunk and its checks.  A lane without a chunk, or whose
+    // chunk fails a check, stays until the complete-code copy below (which
+    // every lane of a wave takes part in) and leaves after it.
     const uint64_t g = (uint64_t)(blockIdx.x - s_job.unit_begin) * kDecThreads + tid;
     const uint64_t i = g / cpb;
     const uint32_t c = (uint32_t)(g - i * cpb);
-    if (i >= nb) return;
-    const uint64_t blk_start = i * (uint64_t)B;
-    const uint64_t left = n - blk_start;
-    const uint32_t cnt = (uint32_t)(left < B ? left : B);
-    const uint32_t s0 = c * S_eff;
-    if (s0 >= cnt) return;
-    const uint32_t s1 = (cnt - s0 < S_eff) ? cnt : s0 + S_eff;
-
-    const uint64_t o = off[i], o1 = off[i + 1];
-    if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
-        report(err, HC_ERR_CORRUPT);
-        return;
+    bool ok = i < nb;
+    uint64_t blk_start = 0, o = 0, o1 = 0, p0 = 0, p1 = 0;
+    uint32_t cnt = 0, s0 = 0, s1 = 0, hdr = 0, nwords = 0;
+    if (ok) {
+        blk_start = i * (uint64_t)B;
+        const uint64_t left = n - blk_start;
+        cnt = (uint32_t)(left < B ? left : B);
+        s0 = c * S_eff;
+        ok = s0 < cnt;
     }
-    if (c == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
-    const uint32_t hdr = in32[o >> 2];
-    if (o + 4 + 4 * (((uint64_t)hdr + 31) / 32) != o1) {
-        report(err, HC_ERR_CORRUPT);
-        return;
+    if (ok) {
+        s1 = (cnt - s0 < S_eff) ? cnt : s0 + S_eff;
+        o = off[i];
+        o1 = off[i + 1];
+        if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
+            report(err, HC_ERR_CORRUPT);
+            ok = false;
+        }
     }
-    const uint32_t nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
-    uint64_t p0 = 0, p1 = hdr;
-    if (sub_idx) {
-        p0 = sub_idx[i * cpb + c];
-        if (s1 < cnt) p1 = sub_idx[i * cpb + c + 1];
+    if (ok) {
+        if (c == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
+        hdr = in32[o >> 2];
+        if (o + 4 + 4 * (((uint64_t)hdr + 31) / 32) != o1) {
+            report(err, HC_ERR_CORRUPT);
+            ok = false;
+        }
     }
-    if (p0 > p1 || p1 > hdr) {
-        report(err, HC_ERR_CORRUPT);
-        return;
+    if (ok) {
+        nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
+        p1 = hdr;
+        if (sub_idx) {
+            p0 = sub_idx[i * cpb + c];
+            if (s1 < cnt) p1 = sub_idx[i * cpb + c + 1];
+        }
+        if (p0 > p1 || p1 > hdr) {
+            report(err, HC_ERR_CORRUPT);
+            ok = false;
+        }
     }
-    if (fixed8 && (p0 != 8ull * s0 || p1 != 8ull * s1 || hdr != 8ull * cnt)) {
+    if (ok && fixed8 && (p0 != 8ull * s0 || p1 != 8ull * s1 || hdr != 8ull * cnt)) {
         // all codes are 8 bits: the index, the header and the pad must agree
         report(err, HC_ERR_CORRUPT);
+        ok = false;
+    }
+    const uint64_t pw0 = (o >> 2) + 1;  // stream word of payload bit 0
+
+    if (fixed8 && s_count[8] == kNumSym) {
+        // All 256 bytes coded (a complete code: 2^8 codes of 8 bits): canonical
+        // order is value order, every symbol is its own code, and a chunk
+        // decodes as a copy of its payload words, each byte-swapped (the
+        // first symbol is a word's top byte).  The wave copies its 64 chunks
+        // together, 16 bytes per lane, so that each load and store instruction
+        // moves a contiguous 1 KiB instead of 64 lanes touching 64 places;
+        // every lane keeps four such pieces in flight.  A chunk starts on a
+        // word (S is a multiple of 16) and its output on 16 bytes.
+        if (ok && s1 == cnt && (hdr & 31u)) {
+            const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
+            if (in32[pw0 + nwords - 1] & mask) report(err, HC_ERR_CORRUPT);
+        }
+        const uint32_t lane = tid & 63u;
+        const uint64_t src_w = pw0 + (s0 >> 2);                  // stream word of the chunk's first symbol
+        const uint64_t dst_a = (uint64_t)(out + blk_start + s0);  // 16-byte aligned
+        const uint32_t okns = ok ? s1 - s0 : 0u;                  // symbols to copy (0: none)
+        const uint32_t pc = S_eff / 16;                           // 16-symbol pieces of a full chunk
+        const uint32_t total = 64 * pc;                           // pieces of the wave's chunks
+        for (uint32_t base = 0; base < total; base += 4 * 64) {
+            uint32_t v[4][4];
+            uint64_t d[4];
+            uint32_t m[4];  // symbols of the piece to store: 16 (whole), 1..15 (a chunk's ragged end), 0
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t P = base + 64 * u + lane;
+                const uint32_t j = (P < total ? P : 0u) / pc;  // the chunk (its lane in the wave)
+                const uint32_t q = (P < total ? P : 0u) - j * pc;
+                const uint32_t nsj = __shfl(okns, (int)j, 64);
+                const uint64_t swj = ((uint64_t)__shfl((uint32_t)(src_w >> 32), (int)j, 64) << 32) |
+                                     __shfl((uint32_t)src_w, (int)j, 64);
+                d[u] = (((uint64_t)__shfl((uint32_t)(dst_a >> 32), (int)j, 64) << 32) |
+                        __shfl((uint32_t)dst_a, (int)j, 64)) + 16ull * q;
+                const uint32_t first = 16 * q;
+                m[u] = (P < total && first < nsj) ? (nsj - first < 16 ? nsj - first : 16u) : 0u;
+#pragma unroll
+                for (uint32_t t = 0; t < 4; ++t)
+                    v[u][t] = (4 * t < m[u]) ? in32[swj + 4 * q + t] : 0u;  // words holding the piece's symbols
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                if (m[u] == 16) {
+                    *(HC_G v4u *)d[u] = v4u{__builtin_bswap32(v[u][0]), __builtin_bswap32(v[u][1]),
+                                            __builtin_bswap32(v[u][2]), __builtin_bswap32(v[u][3])};
+                } else {
+                    for (uint32_t k = 0; k < m[u]; ++k)
+                        ((HC_G uint8_t *)d[u])[k] = (uint8_t)(v[u][k >> 2] >> (24 - 8 * (k & 3)));
+                }
+            }
+        }
         return;
     }
+    if (!ok) return;
 
     // ---- input ring.  Stream words are counted from the 128-byte line that
     // holds the stream's first word (virtual word = stream word + mis), and
@@ -971,7 +1039,6 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     // on, so a round never reads a word the ring does not hold.
     const uint64_t in_words = in_bytes >> 2;
     const uint32_t mis = (uint32_t)(((uint64_t)in32 >> 2) & 31u);  // a multiple of 4
-    const uint64_t pw0 = (o >> 2) + 1;                             // stream word of payload bit 0
     const uint64_t u0 = pw0 + (p0 >> 5) + mis;                     // virtual word of the chunk's first bit
     const uint64_t ubase = u0 & ~(uint64_t)31;                     // virtual word of local word 0
     const int64_t qbase = (int64_t)(ubase >> 2) - (int64_t)(mis >> 2);  // stream quad of local quad 0
@@ -1076,35 +1143,22 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             bad8 |= (uint32_t)(cd >= ncode);
             return cd;
         };
-        // All 256 bytes coded (a complete code: 2^8 codes of 8 bits): canonical
-        // order is then value order, so every symbol is its own code and a
-        // payload word holds four symbols, first in its top byte.
-        const bool identity = ncode == kNumSym;  // uniform over the group: one job per group
-        auto lines = [&](auto identity_tag) {
-            constexpr bool kIdentity = decltype(identity_tag)::value;
-            for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
+        for (uint32_t lb = v_first - v_first % kLineRounds; lb < v_end; lb += kLineRounds) {
 #pragma unroll
-                for (uint32_t r = 0; r < kLineRounds; ++r) {
-                    if (r % 8 == 2) sync_lines();  // 8 rounds take 32 words: one sync per line of output
-                    const uint32_t v = lb + r;
-                    if (v >= v_first && v < v_end) {
+            for (uint32_t r = 0; r < kLineRounds; ++r) {
+                if (r % 8 == 2) sync_lines();  // 8 rounds take 32 words: one sync per line of output
+                const uint32_t v = lb + r;
+                if (v >= v_first && v < v_end) {
 #pragma unroll
-                        for (uint32_t q = 0; q < kRoundWords; ++q)
-                            ow[kRoundWords * r + q] =
-                                kIdentity ? __builtin_bswap32(ring[(nxt + q) & 63u])
-                                          : s_sorted[code_at(4 * q)] | (s_sorted[code_at(4 * q + 1)] << 8) |
-                                                (s_sorted[code_at(4 * q + 2)] << 16) |
-                                                (s_sorted[code_at(4 * q + 3)] << 24);
-                        nxt += R / 4;
-                    }
+                    for (uint32_t q = 0; q < kRoundWords; ++q)
+                        ow[kRoundWords * r + q] = s_sorted[code_at(4 * q)] | (s_sorted[code_at(4 * q + 1)] << 8) |
+                                                  (s_sorted[code_at(4 * q + 2)] << 16) |
+                                                  (s_sorted[code_at(4 * q + 3)] << 24);
+                    nxt += R / 4;
                 }
-                store_line(lb);
             }
-        };
-        if (identity)
-            lines(std::integral_constant<bool, true>());
-        else
-            lines(std::integral_constant<bool, false>());
+            store_line(lb);
+        }
         k = nsym - nsym % R;
         if (k < nsym) {  // fewer than R symbols: at most R/4 words from nxt
             sync_lines();

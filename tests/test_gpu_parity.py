@@ -466,6 +466,41 @@ def test_fixed_length_codes(hc, oracle):
     assert _decode_status(hc, s, enc, sub=False) == hc.HC_ERR_CORRUPT
 
 
+def test_complete_8bit_code(hc, oracle):
+    """Every byte coded with 8 bits (a complete code): the decoder's copy path.
+    Any payload byte is a valid code, so a flipped payload byte decodes as
+    the oracle decodes it; header, index and pad corruptions are rejected."""
+    x = synth.uniform_bytes(70_003, 32)  # n % 4 != 0: pad bits in the last block
+    for B, S in ((4096, 0), (16384, 1024), (65536, 4096)):
+        enc = check_full(hc, oracle, x, B, S, "complete 8-bit code")
+        L = enc.codebook.host.lengths
+        assert np.all(L == 8)
+        s = enc.stream.cpu().numpy().copy()
+        for pos in (4 + 100, 4 + 4 * 1000 + 2, s.size - 5):
+            t = s.copy()
+            t[pos] ^= 0x5A
+            st, ref = oracle.decode_status(t, x.size, B, L)
+            assert st == oracle.OK, pos
+            y = hc.decompress(hc.Encoded(dev(t), enc.block_off, enc.sub_idx, enc.n, B, S, enc.codebook))
+            assert np.array_equal(y.cpu().numpy(), ref[: x.size]), (B, S, pos)
+            assert int((y.cpu().numpy() != x).sum()) == 1, (B, S, pos)
+        t = s.copy()
+        t[0] ^= 1  # a header no longer 8 bits per symbol
+        assert oracle.decode_status(t, x.size, B, L)[0] == oracle.ERR_CORRUPT
+        assert _decode_status(hc, t, enc, sub=False) == hc.HC_ERR_CORRUPT
+        t = s.copy()
+        t[s.size - 4] |= 1  # a pad bit of the last word
+        assert oracle.decode_status(t, x.size, B, L)[0] == oracle.ERR_CORRUPT
+        assert _decode_status(hc, t, enc, sub=False) == hc.HC_ERR_CORRUPT
+        if S:
+            bad = enc.sub_idx.clone()
+            bad[1] += 8  # an index entry off by one symbol
+            err = hc.new_error_word("cuda")
+            out = torch.empty(x.size + 16, dtype=torch.uint8, device="cuda")
+            hc.hc_decode_blocks(enc.stream, enc.nbytes, enc.n, B, enc.codebook, enc.block_off, bad, S, out, err)
+            assert hc.read_error(err) == hc.HC_ERR_CORRUPT
+
+
 def test_codebook_set(hc, oracle):
     """A set of resident tables rebuilt from histograms in one call gives the
     same codes and streams as separate codebooks, rebuild after rebuild."""
