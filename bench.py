@@ -614,9 +614,13 @@ def main():
         gb = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
         # algorithmic bytes per launch: what each step must move (scratch of the
         # implementation, such as per-tile counts, is not counted)
+        # the length pass need not read a stream whose code is a complete
+        # 8-bit code (every symbol costs 8 bits): only the other streams count
+        complete8 = [bool(np.all(np.asarray(d.host.lengths) == 8)) for d in w.dcb]
+        count_bytes = w.seg * sum(1 for c in complete8 if not c)
         alg = {
             "k_hist": n + 8 * 256 * w.nseg,
-            "k_count": n,
+            "k_count": count_bytes,
             "k_offsets": off_bytes,
             "k_encode": n + C + off_bytes + sub_bytes,
             "k_decode": C + n + off_bytes + sub_bytes,

@@ -318,6 +318,14 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
     const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
     const uint32_t s = tl.ts + kSyms * tid;
+    if (tb->fixed_len == 8 && tb->count[8] == (uint32_t)kNumSym) {
+        // A complete 8-bit code (uniform over the group: one job per tile):
+        // every symbol has a code of 8 bits, so the input need not be read.
+        const uint32_t mt = s < tl.te ? (tl.te - s < kSyms ? tl.te - s : kSyms) : 0u;
+        if (thread_bits) thread_bits[t * kTileThreads + tid] = (uint16_t)(8 * mt);
+        if (tid == 0) tile_bits[t] = tl.ts < tl.te ? 8 * (tl.te - tl.ts) : 0u;
+        return;
+    }
     uint32_t w[4 * QPT];
     const uint32_t m = load_syms<QPT>(in, tl, s, w);  // 0 past the end of the tile
     {
@@ -471,6 +479,37 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
 
     const bool last_tile = tl.te == tl.cnt;
+    if (tb->fixed_len == 8 && tb->count[8] == (uint32_t)kNumSym) {
+        // A complete 8-bit code (uniform over the group): every symbol is its
+        // own code, a tile starts on a whole word (P is 8 times a multiple of
+        // 4096) and shares no word with the next tile, so the tile's payload
+        // is its input words byte-swapped (the first symbol into a word's top
+        // byte), copied with thread k on word k (coalesced both ways).  A
+        // last partial word is assembled from bytes; its missing bytes are
+        // the zero pad.
+        const uint64_t P = tile_pos[t], O = ((const HC_G uint64_t *)s_job.block_off)[tl.blk];
+        HC_G uint32_t *payload = out32 + (O >> 2) + 1 + (P >> 5);
+        const HC_G uint8_t *src8 = in + tl.blk_start + tl.ts;  // 16-byte aligned: B and the tile are multiples of 16
+        const HC_G uint32_t *src = (const HC_G uint32_t *)src8;
+        const uint32_t nsym = tl.te - tl.ts, nfull = nsym / 4;
+#pragma unroll 4
+        for (uint32_t k = tid; k < nfull; k += kTileThreads) payload[k] = __builtin_bswap32(src[k]);
+        if ((nsym & 3) && tid == 0) {
+            uint32_t part = 0;
+            for (uint32_t b = 0; b < (nsym & 3); ++b) part |= (uint32_t)src8[4 * nfull + b] << (8 * b);
+            payload[nfull] = __builtin_bswap32(part);
+        }
+        const uint32_t blk_bits = (uint32_t)P + 8 * nsym;
+        if (last_tile && tid == 0) out32[O >> 2] = blk_bits;
+        if (sub_idx) {
+            // entries at the multiples of S in the tile, 8 bits per symbol
+            for (uint32_t sj = tl.ts + (S - tl.ts % S) % S + tid * S; sj < tl.te; sj += kTileThreads * S)
+                sub_idx[tl.blk * cpb + sj / S] = (uint32_t)P + 8 * (sj - tl.ts);
+            if (last_tile && tid == 0)
+                for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = blk_bits;
+        }
+        return;
+    }
     const uint32_t avail = last_tile ? 0u : (tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32u);
     if (tid < 32) s_next[tid] = tid < avail ? in[tl.blk_start + tl.te + tid] : 0u;
     if (tid == 32) {  // where the tile's bits go: from the offset pass
