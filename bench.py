@@ -7,8 +7,8 @@ One step = the whole coding path over the 4 GiB mixed workload (64 segments of
   2. read-back of the 64 histograms (16 KiB)
   3. Huffman code + canonical codes of every segment and one refresh of the
      resident device tables                     (hc_cbset_build, host + async copy)
-  4. block encode of every segment: length pass, offset scan by look-back,
-     bit packing                                (hc_encode_batch, one launch)
+  4. block encode of every segment: length pass, offset scan, bit packing
+                                                (hc_encode_batch, one launch each)
   5. block decode of every segment from the encoder's offsets and sub-block
      index                                      (hc_decode_batch, one launch)
 
@@ -21,6 +21,8 @@ oracle timed on a bounded sample of the same workload.
   python bench.py [--steps K] [--warmup W] [--block B] [--sub-block S]
   python bench.py --sweep          # block size / sub-block sweep, one line each
   python bench.py --copy-probe     # plain device copy: achievable HBM GB/s
+  python bench.py --batched N      # + N independent buffers, batched / graph / plain
+  python bench.py --serve N        # + the serving loop against one request per launch
 """
 from __future__ import annotations
 
