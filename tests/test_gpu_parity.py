@@ -580,7 +580,7 @@ def test_batch_graph_replays(hc, oracle, B, S):
              for k in range(cnt)]
     for k in range(cnt):
         assert torch.equal(ys[k][: sizes[k]], xd[k]), k
-    for k in (1, 2, 3, 10, cnt - 1):  # sampled buffers against the oracle's own code and encoder
+    for k in range(1, cnt):  # every buffer against the oracle's own code and encoder
         L, Cw = oracle.codebook(oracle.histogram(xs[k]))
         s_o, off_o, _ = oracle.encode(xs[k], B, L, Cw)
         assert np.array_equal(eager[k][1].cpu().numpy(), s_o), k
