@@ -12,6 +12,9 @@ One step = the whole coding path over the 4 GiB mixed workload (64 segments of
   5. block decode of every segment from the encoder's offsets and sub-block
      index                                      (hc_decode_batch, one launch)
 
+Steps are pipelined: step k+1's counts are launched before step k's decode,
+so the host builds step k+1's codes while the device decodes step k.
+
 Inputs are resident in HBM before timing starts.  The JSON line reports the
 whole-step throughput in uncompressed GB/s, the per-phase rates, the roofline
 of the dominant kernel (its algorithmic bytes per launch over its average
@@ -56,6 +59,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--per-kind", action="store_true",
+                    help="the same step on segments of one data kind at a time (uniform, skewed, fp32): "
+                         "per-kernel time and GB/s of each kind, one JSON line each")
     ap.add_argument("--batched", type=int, default=0, metavar="N",
                     help="also measure N independent buffers (log-uniform 1 KiB-64 MiB, Zipf s in [0.8,1.6]): "
                          "one launch per phase vs one buffer per launch")
@@ -66,6 +72,9 @@ def parse():
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="turn rocprofv3 --pmc runs in DIR/{fetch,write,copy_fetch,copy_write} into "
                          "profiles/traffic_*.json (HBM bytes per launch of each codec kernel)")
+    ap.add_argument("--sq-table", metavar="DIR",
+                    help="turn rocprofv3 --pmc runs of --per-kind under DIR (any number of counter sets) into "
+                         "a per-kind table of SQ counters per symbol and per wave cycle of each codec kernel")
     return ap.parse_args()
 
 
@@ -84,7 +93,7 @@ class Workload:
     hc_encode_batch, hc_decode_batch); the segment table lives in hc_item
     arrays built once."""
 
-    def __init__(self, hc, synth, torch, nseg, B, S):
+    def __init__(self, hc, synth, torch, nseg, B, S, kind=None):
         self.hc, self.torch = hc, torch
         self.seg = synth.WORKLOADS[WORKLOAD]["segment"]
         self.nseg = nseg
@@ -93,7 +102,7 @@ class Workload:
         dev = "cuda"
         self.x = torch.empty(self.n, dtype=torch.uint8, device=dev)
         for t in range(nseg):
-            synth.segment_bytes_torch(synth.mixed_kind(t), self.seg, synth.derive_seed(3, t),
+            synth.segment_bytes_torch(kind or synth.mixed_kind(t), self.seg, synth.derive_seed(3, t),
                                       out=self.x[t * self.seg:(t + 1) * self.seg])
         self.hist = torch.zeros((nseg, 256), dtype=torch.int64, device=dev)
         self.hist_host = torch.zeros((nseg, 256), dtype=torch.int64).pin_memory()
@@ -142,30 +151,47 @@ class Workload:
     def subs(self, t):
         return self.sub[t] if self.S else None
 
-    def step(self, ev=None):
-        """One pass of the whole path.  ev: optional dict of (start, end) events per phase."""
+    def run(self, steps, evs=None):
+        """'steps' passes of the whole path (one pass: counts, their read-back,
+        host code build and one table copy, encode, decode), pipelined across
+        passes: the counts of pass k+1 and their read-back are enqueued between
+        the encode and the decode of pass k, so the host builds pass k+1's
+        codes while the device decodes pass k.  Every pass runs every kernel
+        over the whole batch; pass k+1's code tables are copied in after pass
+        k's decode (stream order).  evs: optional list of per-pass dicts of
+        (start, end) events for "hist", "copy" (end only), "enc" and "dec";
+        the host build time of each pass is stored under "host"."""
         hc, torch = self.hc, self.torch
 
-        def mark(k, i):
-            if ev is not None and k in ev:
-                ev[k][i].record()
+        def mark(k, name, i):
+            if evs is not None and name in evs[k]:
+                evs[k][name][i].record()
 
-        mark("hist", 0)
-        hc.hc_histogram_batch(self.hist_items, self.hist_ws)
-        mark("hist", 1)
-        self.hist_host.copy_(self.hist, non_blocking=True)
-        mark("copy", 1)
-        torch.cuda.current_stream().synchronize()
-        t1 = time.perf_counter()
-        self.cbset.build(self.hist_host.numpy().view("uint64"))  # all codes, one table copy
-        if ev is not None and "copy" in ev:
-            ev["host"] = time.perf_counter() - t1
-        mark("enc", 0)
-        hc.hc_encode_batch(self.enc_items, self.B, self.S, self.ws, self.err)
-        mark("enc", 1)
-        mark("dec", 0)
-        hc.hc_decode_batch(self.dec_items, self.B, self.S, self.ws, self.err)
-        mark("dec", 1)
+        def count(k):
+            mark(k, "hist", 0)
+            hc.hc_histogram_batch(self.hist_items, self.hist_ws)
+            mark(k, "hist", 1)
+            self.hist_host.copy_(self.hist, non_blocking=True)
+            mark(k, "copy", 1)
+            ready = torch.cuda.Event()
+            ready.record()
+            return ready
+
+        ready = count(0)
+        for k in range(steps):
+            ready.synchronize()  # pass k's counts are on the host
+            t1 = time.perf_counter()
+            self.cbset.build(self.hist_host.numpy().view("uint64"))
+            if evs is not None and "copy" in evs[k]:
+                evs[k]["host"] = time.perf_counter() - t1
+            mark(k, "enc", 0)
+            hc.hc_encode_batch(self.enc_items, self.B, self.S, self.ws, self.err)
+            mark(k, "enc", 1)
+            if k + 1 < steps:
+                ready = count(k + 1)
+            mark(k, "dec", 0)
+            hc.hc_decode_batch(self.dec_items, self.B, self.S, self.ws, self.err)
+            mark(k, "dec", 1)
 
     def step_by_kernel(self, ev):
         """The same pass with the encoder's three steps issued as separate calls
@@ -521,6 +547,78 @@ def traffic_summary(root: str, B: int, S: int):
     print(json.dumps(out, indent=1))
 
 
+def sq_table(root: str, synth, args):
+    """Per-kind SQ counter table from rocprofv3 --pmc runs of --per-kind.
+
+    Each kind runs the workload set-up, then warm-up + timed passes, each
+    ending with one decode launch; the last launch of each kernel before a
+    kind's final decode is that kind's timed launch.  VALU and LDS are wave
+    instructions x 64 lanes per input symbol; conflict is
+    SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS; wait, wait-issue and active are
+    SQ_WAIT_ANY, SQ_WAIT_INST_ANY and SQ_ACTIVE_INST_ANY over SQ_WAVE_CYCLES."""
+    import csv
+    import glob
+
+    per_kind = args.warmup + args.steps
+    symbols = args.segments * synth.WORKLOADS[WORKLOAD]["segment"]
+    vals = {}  # (kind index, kernel) -> counter -> value
+    for f in sorted(glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True)):
+        disp = {}
+        for r in csv.DictReader(open(f)):
+            d = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"].split("(")[0].replace("void ", "")})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        kind, decodes, last = 0, 0, {}
+        for i in sorted(disp):
+            name = disp[i]["name"]
+            short = name.split("::")[-1].split("<")[0]
+            if short in ("k_count", "k_encode", "k_decode_ring"):
+                last[name] = disp[i]
+            if short == "k_decode_ring":
+                decodes += 1
+                if decodes == per_kind:
+                    for k, c in last.items():
+                        vals.setdefault((kind, k), {}).update({n: v for n, v in c.items() if n != "name"})
+                    kind, decodes, last = kind + 1, 0, {}
+    rows = ["| kind | kernel | VALU / symbol | LDS / symbol | conflict / LDS active | wait | wait issue | active |",
+            "|---|---|---|---|---|---|---|---|"]
+    order = {"k_count": 0, "k_encode": 1, "k_decode_ring": 2}
+    for (kind, k) in sorted(vals, key=lambda t: (t[0], order[t[1].split("::")[-1].split("<")[0]])):
+        c = vals[(kind, k)]
+        g = lambda n: c.get(n, float("nan"))
+        cyc = g("SQ_WAVE_CYCLES")
+        rows.append(f"| {synth.SEGMENT_KINDS[kind]} | `{k.split('::')[-1]}` | {64 * g('SQ_INSTS_VALU') / symbols:.2f} | "
+                    f"{64 * g('SQ_INSTS_LDS') / symbols:.2f} | {g('SQ_LDS_BANK_CONFLICT') / g('SQ_ACTIVE_INST_LDS'):.2f} | "
+                    f"{g('SQ_WAIT_ANY') / cyc:.2f} | {g('SQ_WAIT_INST_ANY') / cyc:.2f} | {g('SQ_ACTIVE_INST_ANY') / cyc:.2f} |")
+    print("\n".join(rows))
+
+
+def per_kind_bench(hc, synth, torch, np, args):
+    """The step on args.segments segments of one kind at a time: each
+    kernel's average time over args.steps passes (HIP events around every
+    launch) and its rate in algorithmic bytes, one JSON line per kind."""
+    for kind in synth.SEGMENT_KINDS:
+        print(f"[bench] {kind}: {args.segments} x 64 MiB", file=sys.stderr, flush=True)
+        w = Workload(hc, synth, torch, args.segments, args.block, args.sub_block, kind=kind)
+        kt = kernel_times(w, torch, np, reps=args.steps, warmup=args.warmup)
+        if hc.read_error(w.err):
+            raise hc.HcError(hc.read_error(w.err), kind)
+        assert torch.equal(w.y, w.x), f"round trip failed ({kind})"
+        n, C = w.n, sum(w.C)
+        side = 8 * (w.nb + 1) * w.nseg + 4 * w.nsub * w.nseg
+        complete8 = all(bool(np.all(np.asarray(d.host.lengths) == 8)) for d in w.dcb)
+        alg = {"k_hist": n + 8 * 256 * w.nseg, "k_count": 0 if complete8 else n, "k_offsets": 8 * (w.nb + 1) * w.nseg,
+               "k_encode": n + C + side, "k_decode": C + n + side}
+        kernels = {}
+        for k in KERNELS:
+            ms = float(np.mean(kt[k]))
+            kernels[k] = {"avg_ms": round(ms, 4), "GBps_alg": round(alg[k] / (ms * 1e-3) / 1e9, 1)}
+        print(json.dumps({"kind": kind, "bytes": n, "ratio": round(C / n, 5),
+                          "max_len": [min(d.max_len for d in w.dcb), max(d.max_len for d in w.dcb)],
+                          "block_size": args.block, "sub_block": args.sub_block, "kernels": kernels}), flush=True)
+        del w
+        torch.cuda.empty_cache()
+
+
 def copy_probe(torch, quiet=False):
     """A plain 1 GiB device-to-device copy: the read + write rate this box
     reaches on a streaming kernel (the achievable side of the roofline)."""
@@ -564,9 +662,15 @@ def main():
     if args.traffic_summary:
         traffic_summary(args.traffic_summary, args.block, args.sub_block)
         return
+    if args.sq_table:
+        sq_table(args.sq_table, synth, args)
+        return
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.per_kind:
+        per_kind_bench(hc, synth, torch, np, args)
         return
 
     configs = [(args.block, args.sub_block)]
@@ -576,8 +680,7 @@ def main():
     for B, S in configs:
         print(f"[bench] setting up {args.segments} x 64 MiB, B={B} S={S}", file=sys.stderr, flush=True)
         w = Workload(hc, synth, torch, args.segments, B, S)
-        for _ in range(args.warmup):
-            w.step()
+        w.run(args.warmup)
         torch.cuda.synchronize()
         if hc.read_error(w.err):
             raise hc.HcError(hc.read_error(w.err), "warmup")
@@ -591,8 +694,7 @@ def main():
                for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(args.steps):
-            w.step(evs[k])
+        w.run(args.steps, evs)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         if hc.read_error(w.err):

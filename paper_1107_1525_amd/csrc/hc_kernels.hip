@@ -320,9 +320,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const uint32_t s = tl.ts + kSyms * tid;
     if (tb->fixed_len == 8 && tb->count[8] == (uint32_t)kNumSym) {
         // A complete 8-bit code (uniform over the group: one job per tile):
-        // every symbol has a code of 8 bits, so the input need not be read.
-        const uint32_t mt = s < tl.te ? (tl.te - s < kSyms ? tl.te - s : kSyms) : 0u;
-        if (thread_bits) thread_bits[t * kTileThreads + tid] = (uint16_t)(8 * mt);
+        // every symbol has a code of 8 bits, so the input need not be read;
+        // the packing pass copies such tiles without per-thread counts.
         if (tid == 0) tile_bits[t] = tl.ts < tl.te ? 8 * (tl.te - tl.ts) : 0u;
         return;
     }
@@ -462,7 +461,6 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const uint32_t k = wave_job_of_unit(jl, t);
         if (tid == 0) s_job = job_at(jl, k);
     }
-    for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
     if (kPacked) {
@@ -510,6 +508,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         }
         return;
     }
+    // the tile's words start at zero (ordered before the packing's ors by the
+    // barrier below)
+    for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
     const uint32_t avail = last_tile ? 0u : (tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32u);
     if (tid < 32) s_next[tid] = tid < avail ? in[tl.blk_start + tl.te + tid] : 0u;
     if (tid == 32) {  // where the tile's bits go: from the offset pass
