@@ -23,9 +23,10 @@ oracle timed on a bounded sample of the same workload.
 
   python bench.py [--steps K] [--warmup W] [--block B] [--sub-block S]
   python bench.py --sweep          # block size / sub-block sweep, one line each
-  python bench.py --copy-probe     # plain device copy: achievable HBM GB/s
+  python bench.py --copy-probe     # streaming copy / read probes: achievable HBM GB/s
   python bench.py --batched N      # + N independent buffers, batched / graph / plain
   python bench.py --serve N        # + the serving loop against one request per launch
+  python bench.py --host-pipeline  # + the workload from pinned host memory, PCIe included
 """
 from __future__ import annotations
 
@@ -69,6 +70,10 @@ def parse():
                     help="also run the serving loop on N requests (50/50 compress/decompress, log-uniform "
                          "4 KiB-256 MiB, mixed data) against one request per launch: saturation GB/s of both, "
                          "and p50/p99 latency of both under the same Poisson arrivals")
+    ap.add_argument("--host-pipeline", action="store_true",
+                    help="also run the workload from pinned host memory through the chunked pipeline "
+                         "(copy-in, coding, copy-out overlapped; 64 MiB chunks, one code each): "
+                         "PCIe-inclusive compress / decompress GB/s beside plain pinned copy rates")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="turn rocprofv3 --pmc runs in DIR/{fetch,write,copy_fetch,copy_write} into "
                          "profiles/traffic_*.json (HBM bytes per launch of each codec kernel)")
@@ -510,7 +515,8 @@ def traffic_summary(root: str, B: int, S: int):
         _pmc_per_kernel(os.path.join(root, "write"), "WRITE_SIZE")
     cf = _pmc_per_kernel(os.path.join(root, "copy_fetch"), "FETCH_SIZE")
     cw = _pmc_per_kernel(os.path.join(root, "copy_write"), "WRITE_SIZE")
-    copy_name = max(cf, key=cf.get)  # the 1 GiB copy dominates the probe
+    # the probe's 1 GiB copy (its read probe fetches as much but writes nothing)
+    copy_name = next((k for k in cf if "k_probe_copy" in k), None) or max(cf, key=cf.get)
     f_scale = copy_bytes / (cf[copy_name] * 1024.0)
     w_scale = copy_bytes / (cw[copy_name] * 1024.0)
     out = {}
@@ -619,31 +625,88 @@ def per_kind_bench(hc, synth, torch, np, args):
         torch.cuda.empty_cache()
 
 
-def copy_probe(torch, quiet=False):
-    """A plain 1 GiB device-to-device copy: the read + write rate this box
-    reaches on a streaming kernel (the achievable side of the roofline)."""
+def host_pipeline_bench(hc, synth, torch, np, nseg: int, B: int, S: int, reps: int = 3):
+    """The mixed workload held in pinned host memory, through the chunked
+    host pipeline (paper_1107_1525_amd.hostpipe): wall-clock compress and
+    decompress rates including every host<->device copy, the round trip
+    checked, and plain pinned copies of 1 GiB each way (the PCIe bound)."""
+    from paper_1107_1525_amd.hostpipe import HostPipeline
+
+    seg = synth.WORKLOADS[WORKLOAD]["segment"]
+    n = seg * nseg
+    xh = torch.empty(n, dtype=torch.uint8).pin_memory()
+    for t in range(nseg):
+        xh[t * seg:(t + 1) * seg].copy_(synth.segment_bytes_torch(synth.mixed_kind(t), seg, synth.derive_seed(3, t)))
+    pipe = HostPipeline(B, S, chunk_bytes=seg, slots=3)
+    enc = pipe.compress(xh)  # warm-up, and the output buffers
+    y = pipe.decompress(enc)
+    assert torch.equal(y, xh), "host pipeline round trip failed"
+    tc, td = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        enc = pipe.compress(xh, out=enc.data)
+        tc.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        pipe.decompress(enc, y)
+        td.append(time.perf_counter() - t0)
+    assert torch.equal(y, xh), "host pipeline round trip failed (timed)"
+    # plain pinned copies, 1 GiB each way, on a side stream
+    g = 1 << 30
+    hbuf = torch.empty(g, dtype=torch.uint8).pin_memory()
+    dbuf = torch.empty(g, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.Stream()
+    rates = {}
+    for name, fn in (("h2d", lambda: dbuf.copy_(hbuf, non_blocking=True)),
+                     ("d2h", lambda: hbuf.copy_(dbuf, non_blocking=True))):
+        with torch.cuda.stream(st):
+            fn()
+            st.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            st.synchronize()
+        rates[name] = reps * g / (time.perf_counter() - t0) / 1e9
+    del hbuf, dbuf
+    return {
+        "bytes": n, "chunk_bytes": seg, "chunks": nseg, "compressed_bytes": enc.total, "ratio": round(enc.total / n, 5),
+        "compress_GBps": round(n / min(tc) / 1e9, 2), "decompress_GBps": round(n / min(td) / 1e9, 2),
+        "compress_ms": round(1e3 * min(tc), 2), "decompress_ms": round(1e3 * min(td), 2),
+        "pinned_h2d_GBps": round(rates["h2d"], 2), "pinned_d2h_GBps": round(rates["d2h"], 2),
+        "note": "wall clock, inputs and outputs in pinned host memory, every host<->device copy included; best of "
+                f"{reps}",
+    }
+
+
+def copy_probe(hc, torch, quiet=False):
+    """The library's roofline probes over 1 GiB: a streaming device copy
+    (read + write) and a streaming read.  Returns both rates in GB/s; the
+    copy is the achievable side of the codec kernels' roofline."""
     n = 1 << 30
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
     a.fill_(1)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
     E = torch.cuda.Event
-    s, e = E(enable_timing=True), E(enable_timing=True)
     reps = 20
-    s.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / reps
+    ms = {}
+    for name, fn in (("copy", lambda: hc.hc_probe_copy(a, b)), ("read", lambda: hc.hc_probe_read(a, sink))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        s, e = E(enable_timing=True), E(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        ms[name] = s.elapsed_time(e) / reps
     del a, b
-    rate = 2 * n / ms / 1e6
+    copy_rate, read_rate = 2 * n / ms["copy"] / 1e6, n / ms["read"] / 1e6
     if not quiet:
-        print(json.dumps({"probe": "device copy", "bytes_read": n, "bytes_written": n, "ms": round(ms, 4),
-                          "GBps_read_plus_write": round(rate, 1)}), flush=True)
-    return rate
+        print(json.dumps({"probe": "hc_probe_copy / hc_probe_read", "bytes": n, "copy_ms": round(ms["copy"], 4),
+                          "copy_GBps_read_plus_write": round(copy_rate, 1), "read_ms": round(ms["read"], 4),
+                          "read_GBps": round(read_rate, 1)}), flush=True)
+    return copy_rate, read_rate
 
 
 def main():
@@ -667,7 +730,7 @@ def main():
         return
     torch.cuda.set_device(0)
     if args.copy_probe:
-        copy_probe(torch)
+        copy_probe(hc, torch)
         return
     if args.per_kind:
         per_kind_bench(hc, synth, torch, np, args)
@@ -706,7 +769,7 @@ def main():
         # host code build (host clock), each alone
         readback_ms = float(np.mean([e["hist"][1].elapsed_time(e["copy"][1]) for e in evs]))
         build_ms = 1e3 * float(np.mean([e["host"] for e in evs]))
-        copy_rate = copy_probe(torch, quiet=True)
+        copy_rate, read_rate = copy_probe(hc, torch, quiet=True)
         kt = kernel_times(w, torch, np)
         if hc.read_error(w.err):
             raise hc.HcError(hc.read_error(w.err), "kernel timing")
@@ -755,8 +818,10 @@ def main():
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": load_traffic(KERNEL_SYMBOL[dominant], B, S),
             "bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4),
-            # what a plain 1 GiB device copy reaches on this machine (read + write)
+            # what the library's streaming copy probe reaches on this device
+            # (1 GiB, read + write), and its streaming read alone
             "achievable": round(copy_rate, 1), "frac_of_achievable": round(achieved / copy_rate, 4),
+            "achievable_read": round(read_rate, 1),
         }
         line = {
             "metric": METRIC, "value": round(gb(n, ms_step), 2), "unit": "GB/s", "n_gpus": 1,
@@ -774,6 +839,10 @@ def main():
         if args.batched:
             print(f"[bench] batched: {args.batched} buffers", file=sys.stderr, flush=True)
             line["batched"] = batched_bench(hc, synth, torch, np, args.batched, B, S)
+            torch.cuda.empty_cache()
+        if args.host_pipeline:
+            print("[bench] host-resident pipeline", file=sys.stderr, flush=True)
+            line["host_pipeline"] = host_pipeline_bench(hc, synth, torch, np, args.segments, B, S)
             torch.cuda.empty_cache()
         if args.serve:
             print(f"[bench] serving: {args.serve} requests", file=sys.stderr, flush=True)

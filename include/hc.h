@@ -311,6 +311,23 @@ hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, uint32_t bl
 hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* Roofline probes (measurement helpers, not part of the coding path):     */
+/* the HBM rate plain streaming kernels reach on the device, against       */
+/* which the codec kernels' rates are read.                                */
+/* hc_probe_copy: d_dst[0 .. n-1] = d_src[0 .. n-1]; reads n bytes and     */
+/*   writes n bytes.  Both 16-byte aligned, the ranges must not overlap.   */
+/* hc_probe_read: reads d_src[0 .. n-1] (16-byte aligned) and xors its     */
+/*   32-bit words into *d_sink (one u32, 4-byte aligned, caller-owned;     */
+/*   the value only keeps the reads from being removed).                   */
+/* n must be a multiple of 16 (n == 0: nothing is launched).  One launch   */
+/* on the stream, no allocation.                                          */
+/* Errors returned: INVALID_ARG (null, misaligned or overlapping           */
+/* pointers, n % 16 != 0), HIP.                                            */
+/* ---------------------------------------------------------------------- */
+hc_status hc_probe_copy(const void *d_src, void *d_dst, uint64_t n, void *stream);
+hc_status hc_probe_read(const void *d_src, uint64_t n, uint32_t *d_sink, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

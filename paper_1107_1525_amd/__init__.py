@@ -115,6 +115,8 @@ _sigs = {
     "hc_encode_offsets_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_encode_pack_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_decode_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
+    "hc_probe_copy": ([_vp, _vp, _u64, _vp], _st),
+    "hc_probe_read": ([_vp, _u64, _vp, _vp], _st),
 }
 for _name, (_args, _res) in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -435,3 +437,17 @@ def hc_decode_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, er
                     stream=None) -> None:
     _check(_lib.hc_decode_batch(items, len(items), block_size, sub_block, _ptr(ws), ws.numel(), _ptr(err),
                                 _stream(stream)), "hc_decode_batch")
+
+
+def hc_probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """dst[:] = src[:] with the library's streaming copy probe (byte sizes equal, a multiple of 16)."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("hc_probe_copy: src and dst differ in size")
+    _check(_lib.hc_probe_copy(_ptr(src), _ptr(dst), n, _stream(stream)), "hc_probe_copy")
+
+
+def hc_probe_read(src: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """Reads all of src (a multiple of 16 bytes) and xors its 32-bit words into sink[0] (int32)."""
+    n = src.numel() * src.element_size()
+    _check(_lib.hc_probe_read(_ptr(src), n, _ptr(sink), _stream(stream)), "hc_probe_read")

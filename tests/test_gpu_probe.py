@@ -1,0 +1,44 @@
+"""Roofline probes through the C ABI: the copy reproduces its source byte for
+byte and the read folds exactly the source's 32-bit words (xor, checked on
+the host), at sizes below one wave, with a ragged grid-stride tail, and over
+many work-groups."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1107_1525_amd as hc_mod
+
+    return hc_mod
+
+
+@pytest.mark.parametrize("n", [0, 16, 4096 + 48, (1 << 20) + 16 * 37, 64 << 20])
+def test_probe_copy_and_read(hc, n):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1107 + n)
+    x = torch.randint(0, 256, (max(n, 16),), dtype=torch.uint8, device="cuda", generator=g)[:n]
+    y = torch.full((max(n, 16),), 0xA5, dtype=torch.uint8, device="cuda")[:n]
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    hc.hc_probe_copy(x, y)
+    hc.hc_probe_read(x, sink)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    want = np.bitwise_xor.reduce(x.cpu().numpy().view(np.uint32)) if n else np.uint32(0)
+    assert int(sink.cpu().numpy().view(np.uint32)[0]) == int(want)
+
+
+def test_probe_rejects_bad_arguments(hc):
+    x = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(hc.HcError):
+        hc.hc_probe_copy(x[:40], torch.empty(40, dtype=torch.uint8, device="cuda"))  # not a multiple of 16
+    with pytest.raises(hc.HcError):
+        hc.hc_probe_copy(x[:48], x[16:])  # overlapping
+    with pytest.raises(hc.HcError):
+        hc.hc_probe_read(x[4:36], sink)  # misaligned

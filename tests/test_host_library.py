@@ -133,6 +133,16 @@ def test_host_argument_errors(hc):
     assert lib.hc_histogram(vp(16), 10, vp(12), None) == hc.HC_ERR_INVALID_ARG  # misaligned d_hist
     assert lib.hc_histogram(vp(8), 10, vp(16), None) == hc.HC_ERR_INVALID_ARG   # misaligned d_in
     u64, u32 = ctypes.c_uint64, ctypes.c_uint32
+    lib.hc_probe_copy.argtypes = [vp, vp, u64, vp]
+    lib.hc_probe_read.argtypes = [vp, u64, vp, vp]
+    assert lib.hc_probe_copy(vp(16), vp(4096), 24, None) == hc.HC_ERR_INVALID_ARG      # n % 16
+    assert lib.hc_probe_copy(vp(8), vp(4096), 32, None) == hc.HC_ERR_INVALID_ARG       # misaligned src
+    assert lib.hc_probe_copy(vp(4096), vp(4112), 32, None) == hc.HC_ERR_INVALID_ARG    # overlap
+    assert lib.hc_probe_copy(None, vp(4096), 32, None) == hc.HC_ERR_INVALID_ARG
+    assert lib.hc_probe_copy(None, None, 0, None) == hc.HC_OK                          # nothing to do
+    assert lib.hc_probe_read(vp(16), 32, None, None) == hc.HC_ERR_INVALID_ARG          # no sink
+    assert lib.hc_probe_read(vp(16), 32, vp(4098), None) == hc.HC_ERR_INVALID_ARG      # misaligned sink
+    assert lib.hc_probe_read(vp(24), 32, vp(4096), None) == hc.HC_ERR_INVALID_ARG      # misaligned src
     lib.hc_encode_blocks.argtypes = [vp, u64, u32, vp, vp, u64, vp, vp, u32, vp, u64, vp, vp]
     for B in (0, 8, 24, (1 << 26) + 16):
         assert lib.hc_encode_blocks(vp(16), 100, B, vp(16), vp(16), 1 << 20, vp(16), None, 0, vp(16),
