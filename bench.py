@@ -492,6 +492,12 @@ def serve_bench(hc, synth, torch, np, count: int, B: int, S: int):
     }
 
 
+def kernel_name(full: str) -> str:
+    """A rocprofv3 kernel name without its parameter list, return type and
+    anonymous-namespace prefix (the probes live in one)."""
+    return full.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+
+
 def _pmc_per_kernel(root: str, counter: str):
     """Mean counter value (KiB) per dispatch, by kernel, from rocprofv3 CSVs."""
     import csv
@@ -502,7 +508,7 @@ def _pmc_per_kernel(root: str, counter: str):
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] != counter:
                 continue
-            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            name = kernel_name(r["Kernel_Name"])
             vals.setdefault(name, []).append(float(r["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in vals.items()}
 
@@ -522,7 +528,7 @@ def traffic_summary(root: str, B: int, S: int):
     out = {}
     for k in fetch:
         short = k.split("::")[-1].split("<")[0]
-        if not short.startswith("k_"):
+        if not short.startswith("k_") or short.startswith("k_probe"):  # codec kernels only
             continue
         rec = {
             "kernel": k, "fetch_kib_per_dispatch": round(fetch[k], 1), "write_kib_per_dispatch": round(write.get(k, 0.0), 1),
@@ -571,7 +577,7 @@ def sq_table(root: str, synth, args):
     for f in sorted(glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True)):
         disp = {}
         for r in csv.DictReader(open(f)):
-            d = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"].split("(")[0].replace("void ", "")})
+            d = disp.setdefault(int(r["Dispatch_Id"]), {"name": kernel_name(r["Kernel_Name"])})
             d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
         kind, decodes, last = 0, 0, {}
         for i in sorted(disp):
