@@ -27,6 +27,7 @@ oracle timed on a bounded sample of the same workload.
   python bench.py --batched N      # + N independent buffers, batched / graph / plain
   python bench.py --serve N        # + the serving loop against one request per launch
   python bench.py --host-pipeline  # + the workload from pinned host memory, PCIe included
+  python bench.py --selfsync       # + decode without the sub-block index
 """
 from __future__ import annotations
 
@@ -74,6 +75,9 @@ def parse():
                     help="also run the workload from pinned host memory through the chunked pipeline "
                          "(copy-in, coding, copy-out overlapped; 64 MiB chunks, one code each): "
                          "PCIe-inclusive compress / decompress GB/s beside plain pinned copy rates")
+    ap.add_argument("--selfsync", action="store_true",
+                    help="also decode the workload's streams without their sub-block index "
+                         "(hc_decode_blocks_selfsync, one call per stream) against the indexed decode")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="turn rocprofv3 --pmc runs in DIR/{fetch,write,copy_fetch,copy_write} into "
                          "profiles/traffic_*.json (HBM bytes per launch of each codec kernel)")
@@ -683,6 +687,34 @@ def host_pipeline_bench(hc, synth, torch, np, nseg: int, B: int, S: int, reps: i
     }
 
 
+def selfsync_bench(w, hc, torch, np, indexed_ms: float, reps: int = 5):
+    """The workload's streams decoded without their sub-block index
+    (hc_decode_blocks_selfsync: each block's pieces resynchronised on the code
+    boundaries), one call per stream, against the indexed batched decode; the
+    output is checked against the input."""
+    def run():
+        for t in range(w.nseg):
+            hc.hc_decode_blocks_selfsync(w.outs(t), w.C[t], w.seg, w.B, w.dcb[t], w.off[t], w.ys(t), w.err)
+
+    w.y.zero_()
+    run()
+    torch.cuda.synchronize()
+    if hc.read_error(w.err):
+        raise hc.HcError(hc.read_error(w.err), "selfsync decode")
+    assert torch.equal(w.y, w.x), "selfsync decode round trip failed"
+    E = torch.cuda.Event
+    s, e = E(enable_timing=True), E(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        run()
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    return {"ms": round(ms, 3), "GBps": round(w.n / ms / 1e6, 1), "indexed_decode_ms": round(indexed_ms, 3),
+            "block_size": w.B, "streams": w.nseg,
+            "note": "decode without the sub-block index, one call per stream, HIP events over all calls"}
+
+
 def copy_probe(hc, torch, quiet=False):
     """The library's roofline probes over 1 GiB: a streaming device copy
     (read + write) and a streaming read.  Returns both rates in GB/s; the
@@ -837,6 +869,9 @@ def main():
                        "parallelism": "single-gpu"},
             "phases": phases, "kernels": kernels, "roofline": roofline,
         }
+        if args.selfsync:
+            print("[bench] decode without the sub-block index", file=sys.stderr, flush=True)
+            line["selfsync_decode"] = selfsync_bench(w, hc, torch, np, kavg["k_decode"])
         if not args.no_cpu_baseline and not args.sweep:
             print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
             line["cpu_baseline"] = cpu_baseline(w, __import__("oracle"), np)

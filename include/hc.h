@@ -312,6 +312,29 @@ hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_s
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Block decoding without the sub-block index (section 2.1: a code stream  */
+/* cut at fixed bit positions decodes wrongly from the cut, and Huffman    */
+/* codes tend to resynchronise).  One work-group per block cuts the        */
+/* block's payload into up to 256 equal pieces, decodes them all from      */
+/* their first bit, then re-decodes each piece from where its left         */
+/* neighbour's codes end until no start moves (at most one round per       */
+/* piece), places the pieces' symbols by a scan of their counts and        */
+/* decodes them into d_out.  For blocks too large for one lane each when   */
+/* the encoder wrote no index (any paper-format stream).                   */
+/* Arguments and layout as hc_decode_blocks with d_sub_idx = NULL: d_in    */
+/* (16-byte aligned, in_bytes % 4 == 0), n, block_size, cb, d_block_off    */
+/* (nb + 1 u64), d_out (n bytes, 16-byte aligned, caller-owned), d_err.    */
+/* Decoding is as strict as hc_decode_blocks: CORRUPT in *d_err for an     */
+/* invalid code, codes not ending exactly at the header's bit count, a     */
+/* symbol count other than the block's, non-zero pad, or headers that      */
+/* disagree with the offsets.  No workspace, no allocation; one launch.    */
+/* Errors returned: INVALID_ARG, HIP.                                      */
+/* ---------------------------------------------------------------------- */
+hc_status hc_decode_blocks_selfsync(const uint8_t *d_in, uint64_t in_bytes, uint64_t n, uint32_t block_size,
+                                    hc_cb_handle cb, const uint64_t *d_block_off, uint8_t *d_out, uint32_t *d_err,
+                                    void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Roofline probes (measurement helpers, not part of the coding path):     */
 /* the HBM rate plain streaming kernels reach on the device, against       */
 /* which the codec kernels' rates are read.                                */

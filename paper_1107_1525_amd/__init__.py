@@ -115,6 +115,7 @@ _sigs = {
     "hc_encode_offsets_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_encode_pack_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_decode_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
+    "hc_decode_blocks_selfsync": ([_vp, _u64, _u64, _u32, _vp, _vp, _vp, _vp, _vp], _st),
     "hc_probe_copy": ([_vp, _vp, _u64, _vp], _st),
     "hc_probe_read": ([_vp, _u64, _vp, _vp], _st),
 }
@@ -298,6 +299,15 @@ def hc_decode_blocks(stream_bytes: torch.Tensor, in_bytes: int, n: int, block_si
     rc = _lib.hc_decode_blocks(_ptr(stream_bytes), in_bytes, n, block_size, dcb.handle, _ptr(block_off),
                                _ptr(sub_idx), sub_block, _ptr(out), _ptr(err), _stream(stream))
     _check(rc, "hc_decode_blocks")
+
+
+def hc_decode_blocks_selfsync(stream_bytes: torch.Tensor, in_bytes: int, n: int, block_size: int,
+                              dcb: DeviceCodebook, block_off: torch.Tensor, out: torch.Tensor, err: torch.Tensor,
+                              stream=None) -> None:
+    """Block decode without the sub-block index (pieces resynchronised per block)."""
+    rc = _lib.hc_decode_blocks_selfsync(_ptr(stream_bytes), in_bytes, n, block_size, dcb.handle, _ptr(block_off),
+                                        _ptr(out), _ptr(err), _stream(stream))
+    _check(rc, "hc_decode_blocks_selfsync")
 
 
 # ------------------------------------------------------------------ conveniences

@@ -470,6 +470,18 @@ extern "C" hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, ui
                                     d_err, static_cast<hipStream_t>(stream)));
 }
 
+extern "C" hc_status hc_decode_blocks_selfsync(const uint8_t *d_in, uint64_t in_bytes, uint64_t n,
+                                               uint32_t block_size, hc_cb_handle cb, const uint64_t *d_block_off,
+                                               uint8_t *d_out, uint32_t *d_err, void *stream)
+{
+    if (!valid_block_size(block_size)) return HC_ERR_INVALID_ARG;
+    hc_status st = check_decode(d_in, in_bytes, n, cb, d_block_off, nullptr, 0, d_out);
+    if (st != HC_OK || n == 0) return st;
+    if (num_blocks(n, block_size) > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    return hip_status(launch_decode_sync(d_in, in_bytes, n, block_size, cb->d_tables, d_block_off, d_out, d_err,
+                                         static_cast<hipStream_t>(stream)));
+}
+
 // ---------------------------------------------------------------------- batches
 extern "C" uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size)
 {

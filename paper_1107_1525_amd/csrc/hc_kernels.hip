@@ -883,6 +883,149 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
     }
 }
 
+// ---------------------------------------------------------------- decode without the sub-block index
+// One work-group per block; its lanes cut the block's payload bits into equal
+// pieces and decode them in parallel without knowing where a code starts in
+// a piece.  Section 2.1 recalls that a code stream cut at a fixed bit decodes
+// wrongly from the cut, and that Huffman codes tend to fall back onto the
+// true code boundaries soon after such a wrong start.  So each lane first
+// decodes its piece from the piece's first bit: the codes that start before
+// the piece's end, recording where the last of them ends (at or after the
+// piece's end) and how many there were.  Then, round after round, a lane
+// whose start differs from where its left neighbour's codes end decodes
+// again from there.  Lane 0 starts on a true boundary, so after at most one
+// round per lane every start is a true code boundary; usually one round
+// settles all, since a re-decoded path meets the first one before the
+// piece's end and the end no longer moves.  A scan of the counts places each
+// piece's symbols, and each lane decodes its piece once more into the
+// output.  The strict decoder's checks hold: every code valid, the codes end
+// exactly at the header's bit count, their number is the block's symbol
+// count, and the pad bits are zero.
+constexpr uint32_t kSyncThreads = 256;
+constexpr uint64_t kSyncMinPieceBits = 256;  // shorter pieces would spend most of their codes resynchronising
+
+__global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in32_, uint64_t in_bytes, uint64_t n,
+                                                               uint32_t B, const DevTables *tb_, const uint64_t *off_,
+                                                               uint8_t *out_, uint32_t *err)
+{
+    __shared__ uint16_t s_lut[1 << kLutBits];
+    __shared__ uint64_t s_first[kMaxLen + 1];
+    __shared__ uint32_t s_count[kMaxLen + 1];
+    __shared__ uint32_t s_base[kMaxLen + 1];
+    __shared__ uint32_t s_sorted[kNumSym];
+    __shared__ uint64_t s_end[kSyncThreads];  // where lane j's codes end
+    __shared__ uint32_t s_scan[kSyncThreads / 64];
+
+    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)tb_;
+    const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)in32_;
+    const HC_G uint64_t *__restrict__ off = (const HC_G uint64_t *)off_;
+    HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)out_;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t K = tb->lut_bits;
+    const uint32_t max_len = tb->max_len;
+    for (uint32_t k = tid; k < (1u << K); k += kSyncThreads) s_lut[k] = tb->lut[k];
+    for (uint32_t k = tid; k <= (uint32_t)kMaxLen; k += kSyncThreads) {
+        s_first[k] = tb->first[k];
+        s_count[k] = tb->count[k];
+        s_base[k] = tb->base[k];
+    }
+    s_sorted[tid] = tb->sorted[tid];
+    __syncthreads();
+
+    // the block and its checks (the same values in every lane: the group
+    // leaves together or not at all)
+    const uint64_t nb = num_blocks_dev(n, B);
+    const uint64_t i = blockIdx.x;
+    const uint64_t blk_start = i * (uint64_t)B;
+    const uint32_t cnt = (uint32_t)(n - blk_start < B ? n - blk_start : B);
+    const uint64_t o = off[i], o1 = off[i + 1];
+    if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
+        if (tid == 0) report(err, HC_ERR_CORRUPT);
+        return;
+    }
+    if (tid == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
+    const uint32_t hdr = in32[o >> 2];
+    if (o + 4 + 4 * (((uint64_t)hdr + 31) / 32) != o1) {
+        if (tid == 0) report(err, HC_ERR_CORRUPT);
+        return;
+    }
+    const HC_G uint32_t *payload = in32 + (o >> 2) + 1;
+    const uint32_t nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
+    const uint64_t bits = hdr;
+
+    // pieces of L bits (a multiple of 32), at most one per lane
+    uint64_t L = (bits + kSyncThreads - 1) / kSyncThreads;
+    L = L < kSyncMinPieceBits ? kSyncMinPieceBits : (L + 31) & ~(uint64_t)31;
+    const uint32_t np = (uint32_t)((bits + L - 1) / L);
+    const bool mine = tid < np;
+    const uint64_t lo = (uint64_t)tid * L;
+    const uint64_t hi = lo + L < bits ? lo + L : bits;
+
+    // the codes that start in [from, hi): their number and where they end;
+    // every code read takes at least one bit, and an invalid prefix stops it
+    auto run = [&](uint64_t from, uint32_t &c, bool &bad) -> uint64_t {
+        BitReader br;
+        br.seek(payload, nwords, from);
+        c = 0;
+        bad = false;
+        while (br.pos() < hi && !bad) {
+            (void)decode_one(br, payload, nwords, s_lut, K, max_len, s_first, s_count, s_base, s_sorted, bad);
+            c += bad ? 0u : 1u;
+        }
+        return br.pos();
+    };
+
+    uint64_t start = lo;
+    uint32_t c = 0;
+    bool bad = false;
+    if (mine) s_end[tid] = run(start, c, bad);
+    __syncthreads();
+    for (;;) {  // at most np + 1 rounds: lane j's start is final after j rounds
+        const uint64_t t = (mine && tid > 0) ? s_end[tid - 1] : start;
+        __syncthreads();  // every read of this round before any write
+        bool moved = false;
+        if (mine && tid > 0 && t != start) {
+            start = t;
+            s_end[tid] = run(start, c, bad);
+            moved = true;
+        }
+        if (!__syncthreads_or(moved)) break;
+    }
+
+    uint32_t total = 0;
+    const uint32_t first = group_exclusive_scan<uint32_t, kSyncThreads>(mine ? c : 0u, s_scan, &total);
+    const bool any_bad = __syncthreads_or(mine && bad);
+    const uint64_t last_end = np ? s_end[np - 1] : 0;
+    if (any_bad || total != cnt || last_end != bits) {
+        if (tid == 0) report(err, HC_ERR_CORRUPT);
+        return;
+    }
+    if (tid == 0 && (hdr & 31u)) {
+        const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
+        if (payload[nwords - 1] & mask) report(err, HC_ERR_CORRUPT);
+    }
+    if (!mine || c == 0) return;
+
+    // the piece's symbols into out[blk_start + first, +c): whole words where aligned
+    BitReader br;
+    br.seek(payload, nwords, start);
+    HC_G uint8_t *dst = out + blk_start + first;
+    bool unused = false;
+    auto next = [&]() {
+        return decode_one(br, payload, nwords, s_lut, K, max_len, s_first, s_count, s_base, s_sorted, unused);
+    };
+    uint32_t k = 0;
+    for (; k < c && ((uint64_t)(dst + k) & 3u); ++k) dst[k] = (uint8_t)next();
+    for (; k + 4 <= c; k += 4) {
+        uint32_t w = next();
+        w |= next() << 8;
+        w |= next() << 16;
+        w |= next() << 24;
+        *(HC_G uint32_t *)(dst + k) = w;
+    }
+    for (; k < c; ++k) dst[k] = (uint8_t)next();
+}
+
 // ---------------------------------------------------------------- decode, codes of <= 24 bits
 // Same lane mapping and checks as k_decode; what differs is how a lane meets
 // HBM.  Thousands of lanes each stream their own chunk, so a lane that read or
@@ -1385,6 +1528,16 @@ hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64
 hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s)
 {
     k_fill_u64<<<1, 64, 0, s>>>(block_off, 1, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode_sync(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
+                              const uint64_t *block_off, uint8_t *out, uint32_t *err, hipStream_t s)
+{
+    const uint64_t nb = num_blocks(n, B);
+    if (nb == 0) return hipSuccess;
+    k_decode_sync<<<dim3((uint32_t)nb), kSyncThreads, 0, s>>>((const uint32_t *)in, in_bytes, n, B, tb, block_off,
+                                                               out, err);
     return hipGetLastError();
 }
 

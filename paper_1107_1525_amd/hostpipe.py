@@ -1,6 +1,6 @@
 """Host-resident data through the device coder, with the transfers overlapped.
 
-The paper's conclusion (section 5) finds the GPU coder weighed down by
+The paper's conclusion (section 4) finds the GPU coder weighed down by
 moving data between host and device, and proposes overlapping the transfers
 with the coding.  Here a pinned host buffer is cut into chunks of M bytes (M a
 multiple of the block size B; the last chunk may be short).  Each chunk is
