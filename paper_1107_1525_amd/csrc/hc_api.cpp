@@ -478,8 +478,8 @@ extern "C" hc_status hc_decode_blocks_selfsync(const uint8_t *d_in, uint64_t in_
     hc_status st = check_decode(d_in, in_bytes, n, cb, d_block_off, nullptr, 0, d_out);
     if (st != HC_OK || n == 0) return st;
     if (num_blocks(n, block_size) > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
-    return hip_status(launch_decode_sync(d_in, in_bytes, n, block_size, cb->d_tables, d_block_off, d_out, d_err,
-                                         static_cast<hipStream_t>(stream)));
+    return hip_status(launch_decode_sync(d_in, in_bytes, n, block_size, cb->d_tables, cb->host.max_len, d_block_off,
+                                         d_out, d_err, static_cast<hipStream_t>(stream)));
 }
 
 // ---------------------------------------------------------------------- batches

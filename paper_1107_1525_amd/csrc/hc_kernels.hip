@@ -713,15 +713,17 @@ __global__ void k_walk(const uint32_t *__restrict__ in32, uint64_t in_bytes, uin
 }
 
 // ---------------------------------------------------------------- decode
-__device__ __forceinline__ uint32_t ld_word(const HC_G uint32_t *__restrict__ payload, uint32_t nwords,
-                                            uint32_t w)
+// The bit-reading helpers take the payload as global memory or as a copy in
+// LDS (Ptr: a pointer to const u32 in either).
+template <typename Ptr>
+__device__ __forceinline__ uint32_t ld_word(Ptr payload, uint32_t nwords, uint32_t w)
 {
     return w < nwords ? payload[w] : 0u;
 }
 
 // 64 payload bits starting at bit p (bits past the payload read as 0).
-__device__ __forceinline__ uint64_t window64(const HC_G uint32_t *__restrict__ payload, uint32_t nwords,
-                                             uint64_t p)
+template <typename Ptr>
+__device__ __forceinline__ uint64_t window64(Ptr payload, uint32_t nwords, uint64_t p)
 {
     const uint32_t w = (uint32_t)(p >> 5), r = (uint32_t)(p & 31);
     uint64_t v = ((uint64_t)ld_word(payload, nwords, w) << 32) | ld_word(payload, nwords, w + 1);
@@ -737,7 +739,8 @@ struct BitReader {
     uint32_t nbits;
     uint32_t wi;
 
-    __device__ __forceinline__ void seek(const HC_G uint32_t *payload, uint32_t nwords, uint64_t p)
+    template <typename Ptr>
+    __device__ __forceinline__ void seek(Ptr payload, uint32_t nwords, uint64_t p)
     {
         wi = (uint32_t)(p >> 5);
         const uint32_t r = (uint32_t)(p & 31);
@@ -751,9 +754,9 @@ struct BitReader {
 // Decodes one symbol.  Fast path: the next lut_bits bits index the LDS table.
 // Codes longer than lut_bits are resolved by comparing the next 64 bits with
 // the canonical code range of every longer length.
-__device__ __forceinline__ uint32_t decode_one(BitReader &br, const HC_G uint32_t *__restrict__ payload,
-                                               uint32_t nwords, const uint16_t *lut, uint32_t K,
-                                               uint32_t max_len, const uint64_t *first,
+template <typename Ptr>
+__device__ __forceinline__ uint32_t decode_one(BitReader &br, Ptr payload, uint32_t nwords, const uint16_t *lut,
+                                               uint32_t K, uint32_t max_len, const uint64_t *first,
                                                const uint32_t *count, const uint32_t *base,
                                                const uint32_t *sorted, bool &bad)
 {
@@ -903,56 +906,19 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(JobList jl, uint32_t B, 
 // count, and the pad bits are zero.
 constexpr uint32_t kSyncThreads = 256;
 constexpr uint64_t kSyncMinPieceBits = 256;  // shorter pieces would spend most of their codes resynchronising
+constexpr uint32_t kSyncStageWords = 16384;  // a block payload of up to 64 KiB is read from an LDS copy
 
-__global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in32_, uint64_t in_bytes, uint64_t n,
-                                                               uint32_t B, const DevTables *tb_, const uint64_t *off_,
-                                                               uint8_t *out_, uint32_t *err)
+// The pieces of one block, from its payload 'src' (global memory or its LDS
+// copy); every lane of the group calls it (it holds barriers).
+template <typename Ptr>
+__device__ __forceinline__ void sync_block(Ptr src, uint32_t nwords, uint32_t hdr, uint32_t cnt,
+                                           HC_G uint8_t *blk_out, uint32_t *err, const uint16_t *s_lut, uint32_t K,
+                                           uint32_t max_len, const uint64_t *s_first, const uint32_t *s_count,
+                                           const uint32_t *s_base, const uint32_t *s_sorted, uint64_t *s_end,
+                                           uint32_t *s_scan)
 {
-    __shared__ uint16_t s_lut[1 << kLutBits];
-    __shared__ uint64_t s_first[kMaxLen + 1];
-    __shared__ uint32_t s_count[kMaxLen + 1];
-    __shared__ uint32_t s_base[kMaxLen + 1];
-    __shared__ uint32_t s_sorted[kNumSym];
-    __shared__ uint64_t s_end[kSyncThreads];  // where lane j's codes end
-    __shared__ uint32_t s_scan[kSyncThreads / 64];
-
-    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)tb_;
-    const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)in32_;
-    const HC_G uint64_t *__restrict__ off = (const HC_G uint64_t *)off_;
-    HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)out_;
     const uint32_t tid = threadIdx.x;
-    const uint32_t K = tb->lut_bits;
-    const uint32_t max_len = tb->max_len;
-    for (uint32_t k = tid; k < (1u << K); k += kSyncThreads) s_lut[k] = tb->lut[k];
-    for (uint32_t k = tid; k <= (uint32_t)kMaxLen; k += kSyncThreads) {
-        s_first[k] = tb->first[k];
-        s_count[k] = tb->count[k];
-        s_base[k] = tb->base[k];
-    }
-    s_sorted[tid] = tb->sorted[tid];
-    __syncthreads();
-
-    // the block and its checks (the same values in every lane: the group
-    // leaves together or not at all)
-    const uint64_t nb = num_blocks_dev(n, B);
-    const uint64_t i = blockIdx.x;
-    const uint64_t blk_start = i * (uint64_t)B;
-    const uint32_t cnt = (uint32_t)(n - blk_start < B ? n - blk_start : B);
-    const uint64_t o = off[i], o1 = off[i + 1];
-    if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
-        if (tid == 0) report(err, HC_ERR_CORRUPT);
-        return;
-    }
-    if (tid == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
-    const uint32_t hdr = in32[o >> 2];
-    if (o + 4 + 4 * (((uint64_t)hdr + 31) / 32) != o1) {
-        if (tid == 0) report(err, HC_ERR_CORRUPT);
-        return;
-    }
-    const HC_G uint32_t *payload = in32 + (o >> 2) + 1;
-    const uint32_t nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
     const uint64_t bits = hdr;
-
     // pieces of L bits (a multiple of 32), at most one per lane
     uint64_t L = (bits + kSyncThreads - 1) / kSyncThreads;
     L = L < kSyncMinPieceBits ? kSyncMinPieceBits : (L + 31) & ~(uint64_t)31;
@@ -965,11 +931,11 @@ __global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in
     // every code read takes at least one bit, and an invalid prefix stops it
     auto run = [&](uint64_t from, uint32_t &c, bool &bad) -> uint64_t {
         BitReader br;
-        br.seek(payload, nwords, from);
+        br.seek(src, nwords, from);
         c = 0;
         bad = false;
         while (br.pos() < hi && !bad) {
-            (void)decode_one(br, payload, nwords, s_lut, K, max_len, s_first, s_count, s_base, s_sorted, bad);
+            (void)decode_one(br, src, nwords, s_lut, K, max_len, s_first, s_count, s_base, s_sorted, bad);
             c += bad ? 0u : 1u;
         }
         return br.pos();
@@ -1002,17 +968,17 @@ __global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in
     }
     if (tid == 0 && (hdr & 31u)) {
         const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
-        if (payload[nwords - 1] & mask) report(err, HC_ERR_CORRUPT);
+        if (src[nwords - 1] & mask) report(err, HC_ERR_CORRUPT);
     }
     if (!mine || c == 0) return;
 
-    // the piece's symbols into out[blk_start + first, +c): whole words where aligned
+    // the piece's symbols into blk_out[first, first + c): whole words where aligned
     BitReader br;
-    br.seek(payload, nwords, start);
-    HC_G uint8_t *dst = out + blk_start + first;
+    br.seek(src, nwords, start);
+    HC_G uint8_t *dst = blk_out + first;
     bool unused = false;
     auto next = [&]() {
-        return decode_one(br, payload, nwords, s_lut, K, max_len, s_first, s_count, s_base, s_sorted, unused);
+        return decode_one(br, src, nwords, s_lut, K, max_len, s_first, s_count, s_base, s_sorted, unused);
     };
     uint32_t k = 0;
     for (; k < c && ((uint64_t)(dst + k) & 3u); ++k) dst[k] = (uint8_t)next();
@@ -1024,6 +990,67 @@ __global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in
         *(HC_G uint32_t *)(dst + k) = w;
     }
     for (; k < c; ++k) dst[k] = (uint8_t)next();
+}
+
+// stage_words: the LDS words the launch gives the payload copy (a block whose
+// payload is longer is read from global memory)
+__global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in32_, uint64_t in_bytes, uint64_t n,
+                                                               uint32_t B, const DevTables *tb_, const uint64_t *off_,
+                                                               uint8_t *out_, uint32_t stage_words, uint32_t *err)
+{
+    extern __shared__ uint32_t s_pay[];
+    __shared__ uint16_t s_lut[1 << kLutBits];
+    __shared__ uint64_t s_first[kMaxLen + 1];
+    __shared__ uint32_t s_count[kMaxLen + 1];
+    __shared__ uint32_t s_base[kMaxLen + 1];
+    __shared__ uint32_t s_sorted[kNumSym];
+    __shared__ uint64_t s_end[kSyncThreads];  // where lane j's codes end
+    __shared__ uint32_t s_scan[kSyncThreads / 64];
+
+    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)tb_;
+    const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)in32_;
+    const HC_G uint64_t *__restrict__ off = (const HC_G uint64_t *)off_;
+    HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)out_;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t K = tb->lut_bits;
+    const uint32_t max_len = tb->max_len;
+    for (uint32_t k = tid; k < (1u << K); k += kSyncThreads) s_lut[k] = tb->lut[k];
+    for (uint32_t k = tid; k <= (uint32_t)kMaxLen; k += kSyncThreads) {
+        s_first[k] = tb->first[k];
+        s_count[k] = tb->count[k];
+        s_base[k] = tb->base[k];
+    }
+    s_sorted[tid] = tb->sorted[tid];
+
+    // the block and its checks (the same values in every lane: the group
+    // leaves together or not at all)
+    const uint64_t nb = num_blocks_dev(n, B);
+    const uint64_t i = blockIdx.x;
+    const uint64_t blk_start = i * (uint64_t)B;
+    const uint32_t cnt = (uint32_t)(n - blk_start < B ? n - blk_start : B);
+    const uint64_t o = off[i], o1 = off[i + 1];
+    if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
+        if (tid == 0) report(err, HC_ERR_CORRUPT);
+        return;
+    }
+    if (tid == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
+    const uint32_t hdr = in32[o >> 2];
+    if (o + 4 + 4 * (((uint64_t)hdr + 31) / 32) != o1) {
+        if (tid == 0) report(err, HC_ERR_CORRUPT);
+        return;
+    }
+    const HC_G uint32_t *payload = in32 + (o >> 2) + 1;
+    const uint32_t nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
+    const bool staged = nwords <= stage_words;  // the same in every lane
+    if (staged)
+        for (uint32_t w = tid; w < nwords; w += kSyncThreads) s_pay[w] = payload[w];
+    __syncthreads();  // tables and the payload copy in LDS
+    if (staged)
+        sync_block((const uint32_t *)s_pay, nwords, hdr, cnt, out + blk_start, err, s_lut, K, max_len, s_first,
+                   s_count, s_base, s_sorted, s_end, s_scan);
+    else
+        sync_block(payload, nwords, hdr, cnt, out + blk_start, err, s_lut, K, max_len, s_first, s_count, s_base,
+                   s_sorted, s_end, s_scan);
 }
 
 // ---------------------------------------------------------------- decode, codes of <= 24 bits
@@ -1532,12 +1559,15 @@ hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s)
 }
 
 hipError_t launch_decode_sync(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
-                              const uint64_t *block_off, uint8_t *out, uint32_t *err, hipStream_t s)
+                              uint32_t max_len, const uint64_t *block_off, uint8_t *out, uint32_t *err, hipStream_t s)
 {
     const uint64_t nb = num_blocks(n, B);
     if (nb == 0) return hipSuccess;
-    k_decode_sync<<<dim3((uint32_t)nb), kSyncThreads, 0, s>>>((const uint32_t *)in, in_bytes, n, B, tb, block_off,
-                                                               out, err);
+    // the longest payload a block can have (B codes of max_len bits), up to the LDS copy's limit
+    const uint64_t need = ((uint64_t)B * max_len + 31) / 32;
+    const uint32_t stage = (uint32_t)(need < kSyncStageWords ? need : kSyncStageWords);
+    k_decode_sync<<<dim3((uint32_t)nb), kSyncThreads, (size_t)stage * 4, s>>>(
+        (const uint32_t *)in, in_bytes, n, B, tb, block_off, out, stage, err);
     return hipGetLastError();
 }
 
