@@ -908,6 +908,41 @@ constexpr uint32_t kSyncThreads = 256;
 constexpr uint64_t kSyncMinPieceBits = 256;  // shorter pieces would spend most of their codes resynchronising
 constexpr uint32_t kSyncStageWords = 16384;  // a block payload of up to 64 KiB is read from an LDS copy
 
+// Codes that all fit the table (max_len <= lut_bits), positions below 2^31:
+// one table read, a shift and a branch-free refill per code, 32-bit
+// positions.  An invalid prefix reads as a 1-bit entry with kLutBadFlag, so
+// every step advances; callers collect the flags.
+struct TableBits {
+    uint64_t buf;  // the next nb payload bits, most significant first
+    uint32_t nb, wi, pos;
+
+    template <typename Ptr>
+    __device__ __forceinline__ void seek(Ptr src, uint32_t nwords, uint32_t p)
+    {
+        pos = p;
+        wi = p >> 5;
+        const uint32_t r = p & 31;
+        buf = (((uint64_t)ld_word(src, nwords, wi) << 32) | ld_word(src, nwords, wi + 1)) << r;
+        nb = 64 - r;
+        wi += 2;
+    }
+    template <typename Ptr>
+    __device__ __forceinline__ uint32_t next(Ptr src, uint32_t nwords, const uint16_t *lut, uint32_t K)
+    {
+        const uint32_t e = lut[(uint32_t)(buf >> (64 - K))];
+        const uint32_t L = e & 0x7Fu;
+        buf <<= L;
+        nb -= L;
+        pos += L;
+        const bool need = nb < 32;  // nb >= 32 again after it: >= K bits for the next read
+        const uint32_t w = need ? ld_word(src, nwords, wi) : 0u;
+        buf |= (uint64_t)w << ((32 - nb) & 63);
+        nb += need ? 32u : 0u;
+        wi += need ? 1u : 0u;
+        return e;
+    }
+};
+
 // The pieces of one block, from its payload 'src' (global memory or its LDS
 // copy); every lane of the group calls it (it holds barriers).
 template <typename Ptr>
@@ -919,9 +954,13 @@ __device__ __forceinline__ void sync_block(Ptr src, uint32_t nwords, uint32_t hd
 {
     const uint32_t tid = threadIdx.x;
     const uint64_t bits = hdr;
-    // pieces of L bits (a multiple of 32), at most one per lane
-    uint64_t L = (bits + kSyncThreads - 1) / kSyncThreads;
-    L = L < kSyncMinPieceBits ? kSyncMinPieceBits : (L + 31) & ~(uint64_t)31;
+    // pieces of L bits, at most one per lane: an odd number of 32-bit words,
+    // so that the lanes' first reads of the LDS copy fall on distinct banks
+    // (an even stride such as 64 words put all 64 lanes of a wave on one bank)
+    uint64_t Lw = (bits + 32 * kSyncThreads - 1) / (32 * kSyncThreads);
+    Lw = Lw < kSyncMinPieceBits / 32 ? kSyncMinPieceBits / 32 : Lw;
+    Lw |= 1;
+    const uint64_t L = 32 * Lw;
     const uint32_t np = (uint32_t)((bits + L - 1) / L);
     const bool mine = tid < np;
     const uint64_t lo = (uint64_t)tid * L;
@@ -929,7 +968,25 @@ __device__ __forceinline__ void sync_block(Ptr src, uint32_t nwords, uint32_t hd
 
     // the codes that start in [from, hi): their number and where they end;
     // every code read takes at least one bit, and an invalid prefix stops it
+    // (the table loop reads it as a 1-bit code and flags it)
+    // the codes that start in [from, hi): their number and where they end;
+    // every code read takes at least one bit, and an invalid prefix stops it
+    // (the table loop reads it as a 1-bit code and flags it)
+    const bool table_only = max_len <= K && bits < (1ull << 31);  // the same in every lane
     auto run = [&](uint64_t from, uint32_t &c, bool &bad) -> uint64_t {
+        if (table_only) {
+            TableBits tbits;
+            tbits.seek(src, nwords, (uint32_t)from);
+            const uint32_t end = (uint32_t)hi;
+            uint32_t n = 0, flags = 0;
+            while (tbits.pos < end) {
+                flags |= tbits.next(src, nwords, s_lut, K);
+                ++n;
+            }
+            c = n;
+            bad = (flags & kLutBadFlag) != 0;
+            return tbits.pos;
+        }
         BitReader br;
         br.seek(src, nwords, from);
         c = 0;
@@ -974,10 +1031,15 @@ __device__ __forceinline__ void sync_block(Ptr src, uint32_t nwords, uint32_t hd
 
     // the piece's symbols into blk_out[first, first + c): whole words where aligned
     BitReader br;
-    br.seek(src, nwords, start);
+    TableBits tbits;
+    if (table_only)
+        tbits.seek(src, nwords, (uint32_t)start);
+    else
+        br.seek(src, nwords, start);
     HC_G uint8_t *dst = blk_out + first;
     bool unused = false;
-    auto next = [&]() {
+    auto next = [&]() -> uint32_t {
+        if (table_only) return tbits.next(src, nwords, s_lut, K) >> 8;
         return decode_one(br, src, nwords, s_lut, K, max_len, s_first, s_count, s_base, s_sorted, unused);
     };
     uint32_t k = 0;
@@ -1042,8 +1104,24 @@ __global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in
     const HC_G uint32_t *payload = in32 + (o >> 2) + 1;
     const uint32_t nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
     const bool staged = nwords <= stage_words;  // the same in every lane
-    if (staged)
-        for (uint32_t w = tid; w < nwords; w += kSyncThreads) s_pay[w] = payload[w];
+    if (staged) {
+        // 16 loads in flight per thread before their LDS stores: a copy
+        // that waited for each load in turn took most of the kernel's time
+        constexpr uint32_t kU = 16;
+        for (uint32_t base = 0; base < nwords; base += kU * kSyncThreads) {
+            uint32_t v[kU];
+#pragma unroll
+            for (uint32_t u = 0; u < kU; ++u) {
+                const uint32_t w = base + u * kSyncThreads + tid;
+                v[u] = w < nwords ? payload[w] : 0u;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kU; ++u) {
+                const uint32_t w = base + u * kSyncThreads + tid;
+                if (w < nwords) s_pay[w] = v[u];
+            }
+        }
+    }
     __syncthreads();  // tables and the payload copy in LDS
     if (staged)
         sync_block((const uint32_t *)s_pay, nwords, hdr, cnt, out + blk_start, err, s_lut, K, max_len, s_first,
