@@ -67,6 +67,30 @@ def test_two_queue_matches_heap_tie_break(hc, oracle, seed):
     assert cb.max_len == int(L_or.max()) and cb.nsym == int((h > 0).sum())
 
 
+def test_two_queue_matches_heap_1e5_histograms(hc, oracle):
+    """10^5 more histograms, random and adversarial (ties, wide and dyadic
+    weights, few symbols, one symbol): the library's two-queue build and the
+    oracle's heap give the same lengths every time."""
+    rng = np.random.default_rng(1107)
+    for k in range(100_000):
+        kind = k % 6
+        h = np.zeros(256, np.uint64)
+        m = int(rng.integers(1, 257)) if kind < 4 else int(rng.integers(1, 9))
+        syms = rng.choice(256, size=m, replace=False)
+        if kind == 0:
+            h[syms] = rng.integers(1, 3, size=m)
+        elif kind == 1:
+            h[syms] = rng.integers(1, 1 << 40, size=m)
+        elif kind == 2:
+            h[syms] = 2 ** rng.integers(0, 30, size=m)
+        elif kind == 3:
+            h[syms] = rng.integers(1, 1 << 16, size=m)
+        else:  # few symbols: every tie pattern of small alphabets comes up
+            h[syms] = rng.integers(1, 4, size=m)
+        L_or = oracle.code_lengths(h)
+        assert np.array_equal(hc.hc_build_codebook(h).lengths, L_or), k
+
+
 def test_codebook_fibonacci_depth(hc, oracle):
     fib = [1, 1]
     while len(fib) < 65:

@@ -302,8 +302,8 @@ def test_format_blocks_independent(oracle):
 
 
 def test_format_exhaustive_tiny(oracle):
-    # all inputs of length <= 6 over the alphabet {10, 20, 30}, four block sizes
-    for n in range(1, 7):
+    # all inputs of length <= 8 over the alphabet {10, 20, 30}, four block sizes
+    for n in range(1, 9):
         for tup in itertools.product((10, 20, 30), repeat=n):
             x = np.array(tup, dtype=np.uint8)
             L, C = oracle.codebook(oracle.histogram(x))
