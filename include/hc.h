@@ -335,6 +335,19 @@ hc_status hc_decode_blocks_selfsync(const uint8_t *d_in, uint64_t in_bytes, uint
                                     void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Streaming copy by a kernel of one work-group per CU, for moves between  */
+/* device memory and pinned host memory that should not wait on the        */
+/* runtime's copy engines (the host-resident pipeline's copy-out).         */
+/* d_dst[0 .. n-1] = d_src[0 .. n-1]; both 16-byte aligned, n % 16 == 0,    */
+/* no overlap.  Both ranges (first and last byte) must be device-accessible */
+/* at their own addresses: device memory or host memory pinned by the HIP  */
+/* runtime; the call checks this with the runtime and refuses otherwise    */
+/* (pageable host memory included).  One launch, no allocation.            */
+/* Errors returned: INVALID_ARG, HIP.                                      */
+/* ---------------------------------------------------------------------- */
+hc_status hc_copy(const void *d_src, void *d_dst, uint64_t n, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Roofline probes (measurement helpers, not part of the coding path):     */
 /* the HBM rate plain streaming kernels reach on the device, against       */
 /* which the codec kernels' rates are read.                                */

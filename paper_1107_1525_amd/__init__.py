@@ -116,6 +116,7 @@ _sigs = {
     "hc_encode_pack_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_decode_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_decode_blocks_selfsync": ([_vp, _u64, _u64, _u32, _vp, _vp, _vp, _vp, _vp], _st),
+    "hc_copy": ([_vp, _vp, _u64, _vp], _st),
     "hc_probe_copy": ([_vp, _vp, _u64, _vp], _st),
     "hc_probe_read": ([_vp, _u64, _vp, _vp], _st),
 }
@@ -461,3 +462,12 @@ def hc_probe_read(src: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
     """Reads all of src (a multiple of 16 bytes) and xors its 32-bit words into sink[0] (int32)."""
     n = src.numel() * src.element_size()
     _check(_lib.hc_probe_read(_ptr(src), n, _ptr(sink), _stream(stream)), "hc_probe_read")
+
+
+def hc_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """dst[:] = src[:] by the library's copy kernel (device memory or pinned
+    host memory on either side; byte sizes equal, a multiple of 16)."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("hc_copy: src and dst differ in size")
+    _check(_lib.hc_copy(_ptr(src), _ptr(dst), n, _stream(stream)), "hc_copy")

@@ -16,6 +16,13 @@ Device buffers form a ring of `slots` chunk slots; events order each slot's
 reuse (its copy-in waits until the coding of the chunk that last held it has
 read it, its coding waits until that chunk's copy-out has drained it).
 
+When decompressing, copies out go through the library's copy kernel
+(hc_copy: one work-group per CU, straight into the pinned buffer): the
+runtime sent some 64 MiB device-to-host copies to an SDMA engine at about a
+quarter of its blit kernel's rate.  When compressing, the runtime copies out
+(there the copy kernel's groups took CU slots from the encode kernels and
+the runtime did better); copies in stay with the runtime.
+
 Compressing needs two host waits per chunk: the chunk's 2 KiB of counts (the
 code is built on the host) and its compressed size (the copy-out moves
 exactly C_k bytes).  Decompressing has none: sizes and codes are known.
@@ -31,7 +38,7 @@ from typing import List, Optional
 import numpy as np
 import torch
 
-from . import (DeviceCodebook, HcError, HC_ERR_NO_SPACE, hc_build_codebook, hc_codebook_from_lengths,
+from . import (DeviceCodebook, HcError, HC_ERR_NO_SPACE, hc_build_codebook, hc_codebook_from_lengths, hc_copy,
                hc_decode_blocks, hc_encode_blocks, hc_encode_bound, hc_encode_workspace_bytes, hc_histogram,
                hc_sub_index_entries, num_blocks, read_error)
 
@@ -48,7 +55,7 @@ def plan_chunks(n: int, chunk_bytes: int, block_size: int) -> List[tuple]:
 @dataclass
 class HostChunk:
     """One chunk of a host-resident encoding: its stream occupies
-    data[pos : pos + nbytes]; lengths (256 u8) determine its canonical code;
+    data[pos : pos + nbytes] (pos a multiple of 16); lengths (256 u8) determine its canonical code;
     block_off (nb + 1 u64 as int64) and sub_idx (int32, or None) are pinned
     host tensors."""
     start: int
@@ -62,7 +69,7 @@ class HostChunk:
 
 @dataclass
 class HostEncoded:
-    data: torch.Tensor  # pinned uint8: the chunks' streams back to back (first `total` bytes used)
+    data: torch.Tensor  # pinned uint8: the chunks' streams in order, each from a 16-byte boundary
     total: int
     n: int
     block_size: int
@@ -105,6 +112,24 @@ class HostPipeline:
         # stream, so that the host-side wait of a refresh (for the handle's
         # previous table copy) is on a copy two rounds of slots back
         self.dcb = [DeviceCodebook(hc_codebook_from_lengths(L)) for _ in range(2 * slots)]
+        self.kernel_copy = True  # until the runtime says a buffer is not device-visible
+
+    def _copy_out(self, src: torch.Tensor, dst: torch.Tensor):
+        """src (device) into dst (pinned host) on the copy-out stream: the
+        library's copy kernel for the 16-byte-multiple head when both ends are
+        16-byte aligned, the runtime for the rest."""
+        n = src.numel()
+        head = n - n % 16
+        if not (self.kernel_copy and head and src.data_ptr() % 16 == 0 and dst.data_ptr() % 16 == 0):
+            head = 0
+        if head:
+            try:
+                hc_copy(src[:head], dst[:head], stream=self.s_out)
+            except HcError:
+                self.kernel_copy = False  # not device-visible at its own address: the runtime copies
+                head = 0
+        if head < n:
+            dst[head:].copy_(src[head:], non_blocking=True)
 
     def _drain(self):
         for st in (self.s_in, self.s_code, self.s_out):
@@ -127,7 +152,7 @@ class HostPipeline:
         n, B, S, K = x.numel(), self.B, self.S, self.slots
         plan = plan_chunks(n, self.M, B)
         if out is None:
-            out = torch.empty(max(sum(hc_encode_bound(m, B, 8) for _, m in plan), 16),
+            out = torch.empty(max(sum(hc_encode_bound(m, B, 8) + 16 for _, m in plan), 16),
                               dtype=torch.uint8).pin_memory()
         nbs = [num_blocks(m, B) for _, m in plan]
         off_h = torch.empty(sum(nb + 1 for nb in nbs) or 1, dtype=torch.int64).pin_memory()
@@ -169,6 +194,7 @@ class HostPipeline:
             ev_enc[j].synchronize()  # the chunk's offsets are on the host
             offs = off_h[obase[j]:obase[j + 1]]
             C = int(offs[nbs[j]])
+            pos = (pos + 15) // 16 * 16  # each chunk's stream from a 16-byte boundary
             if pos + C > out.numel():
                 self._drain()  # nothing left in flight on the caller's buffers
                 raise HcError(HC_ERR_NO_SPACE, "HostPipeline.compress: output buffer too small")
@@ -253,7 +279,7 @@ class HostPipeline:
                 ev_dec[k].record(self.s_code)
             with torch.cuda.stream(self.s_out):
                 self.s_out.wait_event(ev_dec[k])
-                y[c.start:c.start + c.n].copy_(self.d_x[slot][:c.n], non_blocking=True)
+                self._copy_out(self.d_x[slot][:c.n], y[c.start:c.start + c.n])
                 ev_out[k] = torch.cuda.Event()
                 ev_out[k].record(self.s_out)
         self._drain()

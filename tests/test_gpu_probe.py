@@ -1,7 +1,8 @@
 """Roofline probes through the C ABI: the copy reproduces its source byte for
 byte and the read folds exactly the source's 32-bit words (xor, checked on
 the host), at sizes below one wave, with a ragged grid-stride tail, and over
-many work-groups."""
+many work-groups.  Also the streaming copy hc_copy between device memory and
+pinned host memory, and its refusals."""
 import numpy as np
 import pytest
 import torch
@@ -42,3 +43,36 @@ def test_probe_rejects_bad_arguments(hc):
         hc.hc_probe_copy(x[:48], x[16:])  # overlapping
     with pytest.raises(hc.HcError):
         hc.hc_probe_read(x[4:36], sink)  # misaligned
+
+
+@pytest.mark.parametrize("n", [16, 4096 + 48, (1 << 20) + 16 * 37, 64 << 20])
+def test_copy_device_and_pinned_host(hc, n):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(n)
+    d = torch.randint(0, 256, (n + 64,), dtype=torch.uint8, device="cuda", generator=g)
+    h = torch.zeros(n + 64, dtype=torch.uint8).pin_memory()
+    # device -> pinned host, from an offset inside both allocations
+    hc.hc_copy(d[16:16 + n], h[32:32 + n])
+    torch.cuda.synchronize()
+    assert torch.equal(h[32:32 + n], d[16:16 + n].cpu())
+    assert int(h[:32].sum()) == 0 and int(h[32 + n:].sum()) == 0  # nothing outside the range
+    # pinned host -> device, and device -> device
+    d2 = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    hc.hc_copy(h[32:32 + n], d2)
+    d3 = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    hc.hc_copy(d2, d3)
+    torch.cuda.synchronize()
+    assert torch.equal(d2, d[16:16 + n]) and torch.equal(d3, d2)
+
+
+def test_copy_refusals(hc):
+    d = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    pageable = torch.zeros(4096, dtype=torch.uint8)  # not pinned: the device cannot reach it
+    with pytest.raises(hc.HcError):
+        hc.hc_copy(d, pageable)
+    with pytest.raises(hc.HcError):
+        hc.hc_copy(pageable, d)
+    with pytest.raises(hc.HcError):
+        hc.hc_copy(d[4:36], torch.zeros(32, dtype=torch.uint8, device="cuda"))  # misaligned
+    with pytest.raises(hc.HcError):
+        hc.hc_copy(d[:64], d[32:96])  # overlapping
