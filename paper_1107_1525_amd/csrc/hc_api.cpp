@@ -379,8 +379,14 @@ hc_status check_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, hc_cb_h
 // of every job and the total.
 uint64_t job_table_bytes(uint32_t count)
 {
-    return align256((uint64_t)count * sizeof(Job)) + align256(8 * ((uint64_t)count + 1));
+    // + room for the alignment of a second table: the decode splits its jobs
+    // into two launches, each with its own table
+    return align256((uint64_t)count * sizeof(Job)) + align256(8 * ((uint64_t)count + 1)) + 1024;
 }
+
+// A complete 8-bit code: all 256 bytes coded, none longer than 8 bits, so
+// (Kraft) every code has 8 bits and decoding is a byte-swapped copy.
+bool complete8(const hc_codebook &cb) { return cb.max_len == 8 && cb.nsym == 256; }
 
 // Writes a job list (and the table of job start units) into the head of the
 // caller's workspace, in stream order and without waiting for the stream (a
@@ -467,7 +473,7 @@ extern "C" hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, ui
     j.block_off = const_cast<uint64_t *>(d_block_off);
     j.sub_idx = const_cast<uint32_t *>(d_sub_idx);
     return hip_status(launch_decode(single(j), groups, block_size, cb->host.max_len, sub_block, d_sub_idx != nullptr,
-                                    d_err, static_cast<hipStream_t>(stream)));
+                                    d_err, static_cast<hipStream_t>(stream), complete8(cb->host)));
 }
 
 extern "C" hc_status hc_decode_blocks_selfsync(const uint8_t *d_in, uint64_t in_bytes, uint64_t n,
@@ -609,13 +615,16 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
     if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
     if (ws_bytes < job_table_bytes(count)) return HC_ERR_NO_SPACE;
-    std::vector<Job> jobs(count);
-    uint64_t groups = 0;
+    // two launches: streams with a complete 8-bit code take the copy form
+    // alone (no ring in LDS, more groups per CU); the rest the ring decoder
+    std::vector<Job> jobs[2];
+    uint64_t groups[2] = {0, 0};
     uint32_t max_len = 1;
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
         hc_status st = check_decode(it.in, it.in_bytes, it.n, it.cb, it.block_off, it.sub_idx, sub_block, it.out);
         if (st != HC_OK) return st;
+        const int w = (it.n > 0 && complete8(it.cb->host)) ? 0 : 1;
         Job j = empty_job();
         j.in = it.in;
         j.in_bytes = it.in_bytes;
@@ -624,15 +633,23 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
         j.out = it.out;
         j.block_off = it.block_off;
         j.sub_idx = it.sub_idx;
-        j.unit_begin = groups;
-        groups += it.n ? decode_groups(it.n, block_size, sub_block) : 0;
-        if (it.n > 0 && it.cb->host.max_len > max_len) max_len = it.cb->host.max_len;
-        jobs[k] = j;
+        j.unit_begin = groups[w];
+        groups[w] += it.n ? decode_groups(it.n, block_size, sub_block) : 0;
+        if (w == 1 && it.n > 0 && it.cb->host.max_len > max_len) max_len = it.cb->host.max_len;
+        jobs[w].push_back(j);
     }
-    if (groups > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    if (groups[0] > 0x7FFFFFFFull || groups[1] > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    JobList jl;
-    hc_status st = upload_jobs(jobs, groups, d_ws, s, &jl);
-    if (st != HC_OK) return st;
-    return hip_status(launch_decode(jl, groups, block_size, max_len, sub_block, sub_block != 0, d_err, s));
+    char *ws = static_cast<char *>(d_ws);
+    for (int w = 0; w < 2; ++w) {
+        if (jobs[w].empty()) continue;
+        JobList jl;
+        hc_status st = upload_jobs(jobs[w], groups[w], ws, s, &jl);
+        if (st != HC_OK) return st;
+        ws += align256(jobs[w].size() * sizeof(Job)) + align256(8 * (jobs[w].size() + 1));
+        const hipError_t e = launch_decode(jl, groups[w], block_size, w == 0 ? 8u : max_len, sub_block,
+                                           sub_block != 0, d_err, s, w == 0);
+        if (e != hipSuccess) return HC_ERR_HIP;
+    }
+    return HC_OK;
 }

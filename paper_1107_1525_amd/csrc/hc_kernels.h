@@ -102,7 +102,9 @@ hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64
 // Decode without the sub-block index: one work-group per block (grid = nb).
 hipError_t launch_decode_sync(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
                               uint32_t max_len, const uint64_t *block_off, uint8_t *out, uint32_t *err, hipStream_t s);
+// complete8: every job has a complete 8-bit code (all 256 bytes coded with 8
+// bits), decoded by the copy form alone.
 hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_t max_len, uint32_t S,
-                         bool with_index, uint32_t *err, hipStream_t s);
+                         bool with_index, uint32_t *err, hipStream_t s, bool complete8 = false);
 
 }  // namespace hc

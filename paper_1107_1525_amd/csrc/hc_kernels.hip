@@ -1159,15 +1159,17 @@ __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32,
 
 // R symbols per round (8 or 16); refills of the bit buffer follow symbols
 // SPR, 2*SPR, ... of a round and its last symbol (SPR * max_len <= 32);
-// kLong: codes may be longer than the table.
-template <uint32_t R, uint32_t SPR, bool kLong>
+// kLong: codes may be longer than the table.  kCopyOnly: every job of the
+// launch has a complete 8-bit code, so only the copy form below runs and the
+// ring is left out (its LDS would hold the copy to 2 groups per CU).
+template <uint32_t R, uint32_t SPR, bool kLong, bool kCopyOnly = false>
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
                                                              uint32_t *err)
 {
     constexpr uint32_t kRoundWords = R / 4;             // output words of a round
     constexpr uint32_t kLineRounds = 128 / R;           // rounds of one 128-byte output line
     extern __shared__ uint16_t s_lut[];  // 2^lut_bits entries (the launch sizes it for the largest)
-    __shared__ uint32_t s_ring[kDecThreads * kRingStride];
+    __shared__ uint32_t s_ring[kCopyOnly ? 1 : kDecThreads * kRingStride];
     __shared__ uint32_t s_first[kPackedMaxLen + 1];
     __shared__ uint32_t s_count[kPackedMaxLen + 1];
     __shared__ uint32_t s_base[kPackedMaxLen + 1];
@@ -1302,6 +1304,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
                 }
             }
         }
+        return;
+    }
+    if (kCopyOnly) {  // not reached: the host gives this launch complete 8-bit codes only
+        if (ok) report(err, HC_ERR_CORRUPT);
         return;
     }
     if (!ok) return;
@@ -1650,12 +1656,16 @@ hipError_t launch_decode_sync(const uint8_t *in, uint64_t in_bytes, uint64_t n, 
 }
 
 hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_t max_len, uint32_t S,
-                         bool with_index, uint32_t *err, hipStream_t s)
+                         bool with_index, uint32_t *err, hipStream_t s, bool complete8)
 {
     if (groups == 0) return hipSuccess;
     const uint32_t S_eff = with_index ? S : B;
     const uint32_t cpb = with_index ? (B + S - 1) / S : 1;
     const dim3 grid((uint32_t)groups);
+    if (complete8) {  // every job a complete 8-bit code: the copy form, no ring, no table
+        k_decode_ring<16, 4, false, true><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+        return hipGetLastError();
+    }
     // the table has 2^lut_bits entries, lut_bits = min(max_len, kLutBits) of the longest code
     const size_t lut = (size_t)2 << (max_len < (uint32_t)kLutBits ? max_len : (uint32_t)kLutBits);
     // a round of R symbols of <= 32 * 16 / R bits stays within one ring half (16 words)

@@ -609,3 +609,34 @@ def test_batch_graph_replays(hc, oracle, B, S):
             if S:
                 assert torch.equal(subs[k], eager[k][3]), (rep, k)
             assert torch.equal(ys[k][: sizes[k]], xd[k]), (rep, k)
+
+
+def test_batch_decode_mixed_complete_codes(hc, oracle):
+    """A batch mixing complete 8-bit codes (large uniform buffers: decoded by
+    the copy launch) with other codes (the ring launch): every buffer decodes
+    to its input, and its stream is the oracle's."""
+    B, S = 65536, 1024
+    sizes = [300_000, 1 << 20, 70_001, 2 << 20, 5, 4096 * 3 + 17, 1 << 20]
+    xs = [synth.uniform_bytes(n, 100 + k) if k % 2 == 0 else synth.zipf_bytes(n, 1.1, 100 + k)
+          for k, n in enumerate(sizes)]
+    encs = [hc.compress(dev(x), B, sub_block=S) for x in xs]
+    complete = [e.codebook.max_len == 8 and int(e.codebook.host.nsym) == 256 for e in encs]
+    assert any(complete) and not all(complete)
+    for x, e in zip(xs, encs):
+        L, C = oracle.codebook(oracle.histogram(x))
+        assert np.array_equal(e.stream.cpu().numpy(), oracle.encode(x, B, L, C)[0])
+    items = hc.make_items(len(xs))
+    outs = [torch.empty(max(x.size, 16), dtype=torch.uint8, device="cuda")[: x.size] for x in xs]
+    for k, (e, o) in enumerate(zip(encs, outs)):
+        hc.set_item(items, k, x=e.stream, n=e.n, in_bytes=e.nbytes, dcb=e.codebook, out=o,
+                    block_off=e.block_off, sub_idx=e.sub_idx)
+    ws = torch.empty(hc.hc_batch_workspace_bytes(items, B), dtype=torch.uint8, device="cuda")
+    err = hc.new_error_word("cuda")
+    for _ in range(2):  # the workspace's two job tables reused
+        for o in outs:
+            o.zero_()
+        hc.hc_decode_batch(items, B, S, ws, err)
+        torch.cuda.synchronize()
+        assert hc.read_error(err) == 0
+        for x, o in zip(xs, outs):
+            assert np.array_equal(o.cpu().numpy(), x)
