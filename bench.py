@@ -529,6 +529,9 @@ def traffic_summary(root: str, B: int, S: int):
     copy_name = next((k for k in cf if "k_probe_copy" in k), None) or max(cf, key=cf.get)
     f_scale = copy_bytes / (cf[copy_name] * 1024.0)
     w_scale = copy_bytes / (cw[copy_name] * 1024.0)
+    # a decode call runs two instances of k_decode_ring (the copy form for
+    # complete 8-bit codes, the ring decoder for the rest), each once per
+    # call: the instances of a kernel are summed, per call
     out = {}
     for k in fetch:
         short = k.split("::")[-1].split("<")[0]
@@ -554,9 +557,12 @@ def traffic_summary(root: str, B: int, S: int):
             "OUT": "the directory the four rocprofv3 runs wrote (any path)",
         }
         path = os.path.join(ROOT, "profiles", f"traffic_{short}_{WORKLOAD}_B{B}_S{S}.json")
-        if short in out:  # several instantiations: keep the busiest
-            if out[short]["bytes_per_launch"] >= rec["bytes_per_launch"]:
-                continue
+        if short in out:  # another instance of the same kernel in each call: add it
+            prev = out[short]
+            rec["kernel"] = prev["kernel"] + " + " + rec["kernel"]
+            rec["fetch_kib_per_dispatch"] = round(prev["fetch_kib_per_dispatch"] + rec["fetch_kib_per_dispatch"], 1)
+            rec["write_kib_per_dispatch"] = round(prev["write_kib_per_dispatch"] + rec["write_kib_per_dispatch"], 1)
+            rec["bytes_per_launch"] += prev["bytes_per_launch"]
         out[short] = rec
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)

@@ -263,14 +263,15 @@ typedef struct {
     uint64_t *hist;       /* histogram: 256 u64 written */
 } hc_item;
 
-/* Device workspace (256-byte aligned, caller-owned) any of the three batch */
-/* calls needs for these items and block size: the job table copied from  */
-/* the host, then the encoder's per-tile (and per-thread) bit counts and  */
-/* positions.                                                              */
+/* Device workspace (256-byte aligned, caller-owned) any of the batch      */
+/* calls needs for these items and block size: the job table (room for    */
+/* two: the decode launches complete 8-bit codes apart), then the         */
+/* encoder's per-tile (and per-thread) bit counts and positions.          */
 uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size);
 
 /* hc_histogram for every item (uses in, n, hist).  The item table is       */
-/* copied into d_ws with an asynchronous host-to-device copy on 'stream';  */
+/* written into d_ws on 'stream' by small kernels that carry the items as  */
+/* arguments (no host-to-device copy, nothing waits for the stream);       */
 /* 'items' may be reused when the call returns.                            */
 /* Errors returned: INVALID_ARG, NO_SPACE, HIP.                            */
 hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes, void *stream);
@@ -306,7 +307,9 @@ hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, uint32_t bl
                                void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
 /* hc_decode_blocks for every item (uses in, in_bytes, n, cb, block_off,   */
-/* sub_idx, out).  One launch.                                             */
+/* sub_idx, out).  At most two launches: items whose code is a complete    */
+/* 8-bit code (all 256 bytes, 8 bits each) decode as a byte-swapped copy   */
+/* in a launch of their own; the rest in one launch of the table decoder. */
 /* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: CORRUPT.         */
 hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
