@@ -10,7 +10,9 @@ One step = the whole coding path over the 4 GiB mixed workload (64 segments of
   4. block encode of every segment: length pass, offset scan, bit packing
                                                 (hc_encode_batch, one launch each)
   5. block decode of every segment from the encoder's offsets and sub-block
-     index                                      (hc_decode_batch, one launch)
+     index                                      (hc_decode_batch: one launch for
+                                                the complete 8-bit codes, one
+                                                for the rest)
 
 Steps are pipelined: step k+1's counts are launched before step k's decode,
 so the host builds step k+1's codes while the device decodes step k.
