@@ -388,36 +388,6 @@ uint64_t job_table_bytes(uint32_t count)
 // (Kraft) every code has 8 bits and decoding is a byte-swapped copy.
 bool complete8(const hc_codebook &cb) { return cb.max_len == 8 && cb.nsym == 256; }
 
-// A stream of the library's per device, for the decode's copy launch to run
-// beside its table-decoder launch: the copy is bound by memory bandwidth,
-// the table decoder by the latency of its per-symbol chain, and their
-// work-groups fit on a CU together.  The caller's stream forks to it and
-// joins back through two events, so the call still starts after and ends
-// before the caller's neighbouring work on its own stream.  Created once per
-// device (default priority); the mutex keeps concurrent calls from
-// interleaving their fork and join on the shared events.
-struct SideStream {
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-};
-std::mutex g_side_mu;
-SideStream g_side[64];
-
-hc_status side_stream(SideStream **out)  // with g_side_mu held
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HC_ERR_HIP;
-    SideStream &ss = g_side[dev];
-    if (!ss.s) {
-        if (hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess) return HC_ERR_HIP;
-        if (hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess)
-            return HC_ERR_HIP;
-    }
-    *out = &ss;
-    return HC_OK;
-}
-
 // Writes a job list (and the table of job start units) into the head of the
 // caller's workspace, in stream order and without waiting for the stream (a
 // copy from pageable host memory would wait for the stream's earlier work).
@@ -671,31 +641,15 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
     if (groups[0] > 0x7FFFFFFFull || groups[1] > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(d_ws);
-    const bool both = !jobs[0].empty() && !jobs[1].empty();
-    std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
-    SideStream *side = nullptr;
-    if (both) {  // the copy launch forks to the side stream
-        lock.lock();
-        hc_status st = side_stream(&side);
-        if (st != HC_OK) return st;
-        if (hipEventRecord(side->fork, s) != hipSuccess || hipStreamWaitEvent(side->s, side->fork, 0) != hipSuccess)
-            return HC_ERR_HIP;
-    }
-    // the table decoder first: its groups (2 per CU, bound by LDS) take their
-    // places before the copy's, which fill the CU slots they leave
-    char *ws_at[2] = {ws, ws + align256(jobs[1].size() * sizeof(Job)) + align256(8 * (jobs[1].size() + 1))};
-    for (int w : {1, 0}) {
+    for (int w = 0; w < 2; ++w) {
         if (jobs[w].empty()) continue;
-        ws = w == 1 ? ws_at[0] : ws_at[1];  // each launch's own job table
-        hipStream_t sw = (both && w == 0) ? side->s : s;
         JobList jl;
-        hc_status st = upload_jobs(jobs[w], groups[w], ws, sw, &jl);
+        hc_status st = upload_jobs(jobs[w], groups[w], ws, s, &jl);
         if (st != HC_OK) return st;
+        ws += align256(jobs[w].size() * sizeof(Job)) + align256(8 * (jobs[w].size() + 1));
         const hipError_t e = launch_decode(jl, groups[w], block_size, w == 0 ? 8u : max_len, sub_block,
-                                           sub_block != 0, d_err, sw, w == 0);
+                                           sub_block != 0, d_err, s, w == 0);
         if (e != hipSuccess) return HC_ERR_HIP;
-        if (both && w == 0 && hipEventRecord(side->join, side->s) != hipSuccess) return HC_ERR_HIP;
     }
-    if (both && hipStreamWaitEvent(s, side->join, 0) != hipSuccess) return HC_ERR_HIP;  // the join
     return HC_OK;
 }
