@@ -759,8 +759,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the codec has no multi-GPU path in this build "
-              "(segments shard with no exchange; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the codec has no multi-GPU path (its independent streams "
+              "would shard across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
