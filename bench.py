@@ -519,7 +519,7 @@ def _pmc_per_kernel(root: str, counter: str):
     return {k: sum(v) / len(v) for k, v in vals.items()}
 
 
-def traffic_summary(root: str, B: int, S: int):
+def traffic_summary(root: str, B: int, S: int, out_dir: str = None):
     """Per-launch HBM traffic of each codec kernel.  Each counter is scaled by
     what it reads for a plain 1 GiB device copy (bytes known exactly)."""
     copy_bytes = 1 << 30
@@ -558,7 +558,7 @@ def traffic_summary(root: str, B: int, S: int):
             ],
             "OUT": "the directory the four rocprofv3 runs wrote (any path)",
         }
-        path = os.path.join(ROOT, "profiles", f"traffic_{short}_{WORKLOAD}_B{B}_S{S}.json")
+        path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_{short}_{WORKLOAD}_B{B}_S{S}.json")
         if short in out:  # another instance of the same kernel in each call: add it
             prev = out[short]
             rec["kernel"] = prev["kernel"] + " + " + rec["kernel"]
@@ -569,6 +569,7 @@ def traffic_summary(root: str, B: int, S: int):
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)
     print(json.dumps(out, indent=1))
+    return out
 
 
 def sq_table(root: str, synth, args):
