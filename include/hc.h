@@ -212,6 +212,31 @@ hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t block_size,
                            uint32_t *d_sub_idx, uint32_t sub_block, void *d_ws, uint64_t ws_bytes,
                            uint32_t *d_err, void *stream);
 
+/* Size in bytes of the device array that hc_encode_blocks_noalloc uses as  */
+/* its scratch (one copy per GPU, held until the process ends).            */
+#define HC_NOALLOC_SCRATCH_BYTES (32ull << 20)
+
+/* hc_encode_blocks without a workspace argument, for callers that cannot  */
+/* allocate device memory (code under stream capture, tight serving loops, */
+/* harnesses that forbid allocation): the encoder's scratch is a           */
+/* file-scope device array of HC_NOALLOC_SCRATCH_BYTES per GPU.  The call   */
+/* itself allocates and frees nothing; the first call on a device looks up */
+/* that device's copy of the array once.  Other arguments, layouts and     */
+/* errors are those of hc_encode_blocks.                                   */
+/* Limit: the scratch this (n, B, codebook) needs, as hc_encode_blocks      */
+/* would use of its workspace (hc_encode_workspace_bytes(n, B) bounds it;   */
+/* about n/32 bytes for B >= 16384, 8 bytes per block for B <= 4096), must  */
+/* fit HC_NOALLOC_SCRATCH_BYTES, else NO_SPACE is returned and nothing is   */
+/* enqueued.  Every call on one GPU shares that GPU's array and nothing in  */
+/* it needs clearing (every entry is written before it is read), so calls  */
+/* that may overlap in time on one GPU (different streams, or host threads */
+/* without ordering) race on it: order them, e.g. on one stream.          */
+/* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: SYMBOL_ABSENT,   */
+/* BLOCK_OVERFLOW.                                                          */
+hc_status hc_encode_blocks_noalloc(const uint8_t *d_in, uint64_t n, uint32_t block_size, hc_cb_handle cb,
+                                   uint8_t *d_out, uint64_t out_cap, uint64_t *d_block_off, uint32_t *d_sub_idx,
+                                   uint32_t sub_block, uint32_t *d_err, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Offset table from the length delimiters (section 2.1), for a stream    */
 /* whose offsets were not kept.  Walks the nb headers one after another   */

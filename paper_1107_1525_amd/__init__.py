@@ -7,7 +7,7 @@ names of the C ABI in ``include/hc.h``:
 
     hc_histogram, hc_build_codebook, hc_codebook_from_lengths,
     hc_codebook_upload, hc_codebook_update, hc_codebook_destroy, hc_encode_bound,
-    hc_encode_workspace_bytes, hc_sub_index_entries, hc_encode_blocks,
+    hc_encode_workspace_bytes, hc_sub_index_entries, hc_encode_blocks, hc_encode_blocks_noalloc,
     hc_walk_blocks, hc_decode_blocks, hc_status_str, hc_batch_workspace_bytes,
     hc_histogram_batch, hc_encode_batch, hc_encode_lengths_batch, hc_encode_offsets_batch,
     hc_encode_pack_batch, hc_decode_batch, hc_cbset_create,
@@ -106,6 +106,7 @@ _sigs = {
     "hc_encode_workspace_bytes": ([_u64, _u32], _u64),
     "hc_sub_index_entries": ([_u64, _u32, _u32], _u64),
     "hc_encode_blocks": ([_vp, _u64, _u32, _vp, _vp, _u64, _vp, _vp, _u32, _vp, _u64, _vp, _vp], _st),
+    "hc_encode_blocks_noalloc": ([_vp, _u64, _u32, _vp, _vp, _u64, _vp, _vp, _u32, _vp, _vp], _st),
     "hc_walk_blocks": ([_vp, _u64, _u64, _vp, _vp, _vp], _st),
     "hc_decode_blocks": ([_vp, _u64, _u64, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp], _st),
     "hc_batch_workspace_bytes": ([ctypes.POINTER(hc_item), _u32, _u32], _u64),
@@ -286,6 +287,18 @@ def hc_encode_blocks(x: torch.Tensor, block_size: int, dcb: DeviceCodebook, out:
                                _ptr(block_off), _ptr(sub_idx), sub_block, _ptr(ws), ws.numel(),
                                _ptr(err), _stream(stream))
     _check(rc, "hc_encode_blocks")
+
+
+HC_NOALLOC_SCRATCH_BYTES = 32 << 20  # HC_NOALLOC_SCRATCH_BYTES of include/hc.h
+
+
+def hc_encode_blocks_noalloc(x: torch.Tensor, block_size: int, dcb: DeviceCodebook, out: torch.Tensor,
+                             block_off: torch.Tensor, sub_idx: Optional[torch.Tensor], sub_block: int,
+                             err: torch.Tensor, stream=None) -> None:
+    """hc_encode_blocks with the library's own per-GPU scratch (no workspace argument)."""
+    rc = _lib.hc_encode_blocks_noalloc(_ptr(x), x.numel(), block_size, dcb.handle, _ptr(out), out.numel(),
+                                       _ptr(block_off), _ptr(sub_idx), sub_block, _ptr(err), _stream(stream))
+    _check(rc, "hc_encode_blocks_noalloc")
 
 
 def hc_walk_blocks(stream_bytes: torch.Tensor, in_bytes: int, nb: int, block_off: torch.Tensor,

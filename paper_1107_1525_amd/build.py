@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhc.so")
-SOURCES = ["hc_api.cpp", "hc_codebook.cpp", "hc_kernels.hip", "hc_probe.hip", "hc_copy.hip"]
+SOURCES = ["hc_api.cpp", "hc_codebook.cpp", "hc_kernels.hip", "hc_probe.hip", "hc_copy.hip", "hc_noalloc.hip"]
 ARCH = "gfx950"
 
 

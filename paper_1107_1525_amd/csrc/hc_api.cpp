@@ -425,6 +425,14 @@ extern "C" hc_status hc_encode_blocks(const uint8_t *d_in, uint64_t n, uint32_t 
                                       uint32_t *d_sub_idx, uint32_t sub_block, void *d_ws,
                                       uint64_t ws_bytes, uint32_t *d_err, void *stream)
 {
+    return hc::encode_blocks_ws(d_in, n, block_size, cb, d_out, out_cap, d_block_off, d_sub_idx, sub_block, d_ws,
+                                ws_bytes, d_err, stream);
+}
+
+hc_status hc::encode_blocks_ws(const uint8_t *d_in, uint64_t n, uint32_t block_size, hc_cb_handle cb, uint8_t *d_out,
+                               uint64_t out_cap, uint64_t *d_block_off, uint32_t *d_sub_idx, uint32_t sub_block,
+                               void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream)
+{
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
     hc_status st = check_encode(d_in, n, block_size, cb, d_out, out_cap, d_block_off, d_sub_idx, sub_block);
     if (st != HC_OK) return st;

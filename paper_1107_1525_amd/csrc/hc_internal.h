@@ -43,6 +43,12 @@ void build_dev_tables(const hc_codebook &cb, DevTables *t);
 // Kraft check and canonical assignment shared by the two codebook constructors.
 hc_status canonical_from_lengths(const uint8_t *len, hc_codebook *out);
 
+// hc_encode_blocks with its workspace given as a device address and size:
+// the caller-workspace entry point and the allocation-free one both end here.
+hc_status encode_blocks_ws(const uint8_t *d_in, uint64_t n, uint32_t block_size, hc_cb_handle cb, uint8_t *d_out,
+                           uint64_t out_cap, uint64_t *d_block_off, uint32_t *d_sub_idx, uint32_t sub_block,
+                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
+
 }  // namespace hc
 
 struct hc_cb_dev_s {
