@@ -1558,6 +1558,281 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     }
 }
 
+// ---------------------------------------------------------------- decode, wave-staged chunks
+// Same lane mapping, checks and table decode as k_decode_ring, for chunks of
+// at most kStageMaxS symbols (the sub-block index with S <= 128); what
+// differs is how a wave meets HBM.  The 64 chunks of a wave are consecutive
+// in the stream (blocks are back to back and a block's chunks in order), so
+// the wave copies the stream words they span into an LDS area of its own
+// with coalesced 16-byte loads (each load instruction moves a contiguous
+// 1 KiB), and then every lane decodes its chunk from there into 32 registers
+// (one 128-byte line) stored once at the end.  No per-lane ring, no line in
+// flight in registers and no rounds of the wave waiting for each other's
+// lines: the state of a lane is its bit buffer and its output line, so more
+// waves fit a CU (the per-symbol chain of table reads is latency-bound, and
+// waves are what hides it).  If the words of the wave's chunks do not fit
+// the area at once (long codes, or a corrupt index), the wave takes them in
+// passes, each pass the pending lanes whose words fit after the lowest one.
+constexpr uint32_t kStageMaxS = 128;     // symbols of a chunk: one 128-byte output line
+constexpr uint32_t kStageSlackWords = 128;  // after the last wave's area: reads past a corrupt chunk's end stay in LDS
+// Words of each wave's area: the 64 chunks at 8 bits per symbol, and at least
+// the longest chunk the checks let through (kStageMaxS codes of 24 bits) with
+// the bit buffer's read-ahead.  Static: the areas are fixed-size arrays.
+constexpr uint32_t kStageWords = 64 * kStageMaxS / 4 + 16;
+static_assert(kStageWords % 4 == 0 && kStageWords >= (kStageMaxS * kPackedMaxLen) / 32 + 16, "area too small");
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint64_t o = __shfl_xor(v, d, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint64_t o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// LDS written by some lanes of a wave, then read by others: the writes are
+// complete before any lane reads.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// R symbols per round (16, or 8 for codes of 17..24 bits); refills of the
+// bit buffer follow symbols SPR, 2*SPR, ... of a round and its last symbol
+// (SPR * max_len <= 32); kLong: codes may be longer than the table; kLutB:
+// table entries of the launch (2^kLutB >= 2^lut_bits of every job).  All LDS
+// is static (the areas are about 33 KiB per group).
+template <uint32_t R, uint32_t SPR, bool kLong, uint32_t kLutB>
+__global__ __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(kLutB <= 10 ? 4 : 3))) void k_decode_stage(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
+                                                              uint32_t *err)
+{
+    constexpr uint32_t kRoundWords = R / 4;
+    constexpr uint32_t kRounds = kStageMaxS / R;  // rounds of a full chunk (one output line)
+    __shared__ __attribute__((aligned(16))) uint16_t s_lut[1u << kLutB];
+    __shared__ __attribute__((aligned(16))) uint32_t s_area[kDecThreads / 64 * kStageWords + kStageSlackWords];
+    __shared__ uint32_t s_first[kPackedMaxLen + 1];
+    __shared__ uint32_t s_count[kPackedMaxLen + 1];
+    __shared__ uint32_t s_base[kPackedMaxLen + 1];
+    __shared__ uint32_t s_sorted[kNumSym];
+    __shared__ Job s_job;
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    if (tid < 64) {
+        const uint32_t k = wave_job_of_unit(jl, blockIdx.x);
+        if (tid == 0) s_job = job_at(jl, k);
+    }
+    __syncthreads();
+    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
+    const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)s_job.in;
+    const uint64_t in_bytes = s_job.in_bytes, n = s_job.n;
+    const uint64_t nb = num_blocks_dev(n, B);
+    const HC_G uint64_t *__restrict__ off = (const HC_G uint64_t *)s_job.block_off;
+    const HC_G uint32_t *__restrict__ sub_idx = (const HC_G uint32_t *)s_job.sub_idx;
+    HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)s_job.out;
+    const uint32_t K = tb->lut_bits;
+    const uint32_t max_len = tb->max_len;
+    {
+        // the table, 8 entries (16 bytes) per load
+        const uint32_t nq = (1u << K) >= 8 ? (1u << K) / 8 : 1u;
+        for (uint32_t k = tid; k < nq; k += kDecThreads) ((v4u *)s_lut)[k] = ((const HC_G v4u *)tb->lut)[k];
+    }
+    if (tid <= (uint32_t)kPackedMaxLen) {
+        s_first[tid] = (uint32_t)tb->first[tid];
+        s_count[tid] = tb->count[tid];
+        s_base[tid] = tb->base[tid];
+    }
+    s_sorted[tid] = tb->sorted[tid];
+    __syncthreads();  // the last barrier of the group: waves go their own way from here
+
+    // ---- the lane's chunk and its checks (as k_decode_ring)
+    const uint64_t g = (uint64_t)(blockIdx.x - s_job.unit_begin) * kDecThreads + tid;
+    const uint64_t i = g / cpb;
+    const uint32_t c = (uint32_t)(g - i * cpb);
+    bool ok = i < nb;
+    uint64_t blk_start = 0, o = 0, o1 = 0, p0 = 0, p1 = 0;
+    uint32_t cnt = 0, s0 = 0, s1 = 0, hdr = 0, nwords = 0;
+    if (ok) {
+        blk_start = i * (uint64_t)B;
+        const uint64_t left = n - blk_start;
+        cnt = (uint32_t)(left < B ? left : B);
+        s0 = c * S_eff;
+        ok = s0 < cnt;
+    }
+    if (ok) {
+        s1 = (cnt - s0 < S_eff) ? cnt : s0 + S_eff;
+        o = off[i];
+        o1 = off[i + 1];
+        if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
+            report(err, HC_ERR_CORRUPT);
+            ok = false;
+        }
+    }
+    if (ok) {
+        if (c == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
+        hdr = in32[o >> 2];
+        if (o + 4 + 4 * (((uint64_t)hdr + 31) / 32) != o1) {
+            report(err, HC_ERR_CORRUPT);
+            ok = false;
+        }
+    }
+    if (ok) {
+        nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
+        p1 = hdr;
+        p0 = sub_idx[i * cpb + c];
+        if (s1 < cnt) p1 = sub_idx[i * cpb + c + 1];
+        // every code has 1 .. max_len bits
+        if (p0 > p1 || p1 > hdr || p1 - p0 < (uint64_t)(s1 - s0) || p1 - p0 > (uint64_t)(s1 - s0) * max_len) {
+            report(err, HC_ERR_CORRUPT);
+            ok = false;
+        }
+    }
+    const uint64_t pw0 = (o >> 2) + 1;            // stream word of payload bit 0
+    const uint64_t fw = pw0 + (p0 >> 5);           // stream word of the chunk's first bit
+    const uint64_t lw = pw0 + ((p1 - 1) >> 5);     // and of its last bit
+    const uint64_t in_words = in_bytes >> 2;
+    const int64_t q_last = (int64_t)((in_words ? in_words - 1 : 0) >> 2);  // the stream's last quad
+    uint32_t *const area = s_area + wave * kStageWords;
+    constexpr uint32_t area_quads = kStageWords / 4;
+
+    HC_G uint8_t *const dst = out + blk_start + s0;
+    const uint32_t nsym = s1 - s0;
+    uint32_t bad = 0;  // kLutBadFlag: an invalid prefix was met
+    bool pending = ok;
+    while (__any(pending)) {
+        // the pass: pending lanes whose words (and the three the bit buffer
+        // reads ahead) fit the area from the lowest pending quad on
+        const uint64_t bq = wave_min_u64(pending ? (fw >> 2) : ~0ull);
+        const bool take = pending && ((lw + 3) >> 2) < bq + area_quads;
+        const uint64_t eq = wave_max_u64(take ? ((lw + 3) >> 2) + 1 : 0ull);
+        if (!__any(take)) {
+            // not reached: the launch sizes the area for the longest chunk the
+            // checks above let through; kept so that no wave can loop forever
+            if (pending && (fw >> 2) == bq) {
+                report(err, HC_ERR_CORRUPT);
+                pending = false;
+            }
+            continue;
+        }
+        const uint32_t nq = (uint32_t)(eq - bq);  // <= area_quads
+        {
+            constexpr uint32_t kU = 8;  // loads in flight per lane: 8 KiB per wave
+            for (uint32_t q0 = 0; q0 < nq; q0 += 64 * kU) {
+                v4u v[kU];
+#pragma unroll
+                for (uint32_t u = 0; u < kU; ++u) {
+                    const uint32_t q = q0 + 64 * u + lane;
+                    v[u] = q < nq ? load_quad(in32, (int64_t)(bq + q), q_last) : v4u{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kU; ++u) {
+                    const uint32_t q = q0 + 64 * u + lane;
+                    if (q < nq) *(v4u *)(area + 4 * q) = v[u];
+                }
+            }
+        }
+        wave_lds_sync();
+        if (take) {
+            // ---- bit buffer: the next nbits chunk bits, most significant first;
+            // 'pre' is the area word at wi, read ahead of its refill
+            uint32_t wi = (uint32_t)(fw - 4 * bq);
+            const uint32_t r0 = (uint32_t)(p0 & 31);
+            uint64_t buf = (((uint64_t)area[wi] << 32) | area[wi + 1]) << r0;
+            uint32_t nbits = 64 - r0;
+            wi += 2;
+            uint32_t pre = area[wi];
+            const uint32_t lut_shift = 32 - K;
+            uint32_t esum = 0;
+            auto decode_entry = [&]() -> uint32_t {
+                uint32_t e = s_lut[(uint32_t)(buf >> 32) >> lut_shift];
+                if (kLong && (e & 255u) == 0) {
+                    uint32_t L = 0, sym = 0;
+                    for (uint32_t l = K + 1; l <= max_len; ++l) {
+                        const uint32_t cv = (uint32_t)(buf >> (64 - l));
+                        const uint32_t d = cv - s_first[l];
+                        if (d < s_count[l]) {
+                            L = l;
+                            sym = s_sorted[s_base[l] + d];
+                            break;
+                        }
+                    }
+                    e = L ? (sym << 8) | L : (kLutBadFlag | 1u);
+                }
+                bad |= e;
+                buf <<= (e & 63u);
+                esum += e;
+                return e;
+            };
+            auto refill = [&]() {
+                nbits -= esum & 255u;
+                esum = 0;
+                const bool need = nbits < 32;
+                const uint32_t w = need ? pre : 0u;
+                buf |= (uint64_t)w << ((32 - nbits) & 63u);
+                nbits += need ? 32u : 0u;
+                wi += need ? 1u : 0u;
+                pre = area[wi];
+            };
+            const uint32_t nfull = nsym / R;
+            uint32_t ow[kRounds * kRoundWords];
+#pragma unroll
+            for (uint32_t q = 0; q < kRounds * kRoundWords; ++q) ow[q] = 0;  // (nothing flows from an earlier pass)
+#pragma unroll
+            for (uint32_t r = 0; r < kRounds; ++r) {
+                if (r < nfull) {
+                    uint32_t o4[kRoundWords];
+#pragma unroll
+                    for (uint32_t q = 0; q < kRoundWords; ++q) o4[q] = 0;
+#pragma unroll
+                    for (uint32_t q = 0; q < R; ++q) {
+                        // the entry's byte 1 (the symbol) into byte q & 3 of the word, the other bytes kept
+                        constexpr uint32_t kSel[4] = {0x03020105u, 0x03020500u, 0x03050100u, 0x05020100u};
+                        o4[q >> 2] = __builtin_amdgcn_perm(decode_entry(), o4[q >> 2], kSel[q & 3]);
+                        if ((q + 1) % SPR == 0 || q + 1 == R) refill();
+                    }
+#pragma unroll
+                    for (uint32_t q = 0; q < kRoundWords; ++q) ow[kRoundWords * r + q] = o4[q];
+                }
+            }
+            const uint32_t k = nfull * R;
+            for (uint32_t q = 0; q < nsym - k; ++q) {  // the ragged end of a block's last chunk
+                dst[k + q] = (uint8_t)(decode_entry() >> 8);
+                refill();
+            }
+            // the chunk's output: whole 16-byte pieces from the registers, then
+            // (rounds of 8 symbols) a last 8-byte piece
+#pragma unroll
+            for (uint32_t r = 0; r < kStageMaxS / 16; ++r)
+                if (16 * r + 16 <= k) *(HC_G v4u *)(dst + 16 * r) = v4u{ow[4 * r], ow[4 * r + 1], ow[4 * r + 2], ow[4 * r + 3]};
+            if (R == 8 && (k & 8u)) {
+#pragma unroll
+                for (uint32_t r = 0; r < kStageMaxS / 16; ++r)
+                    if (16 * r + 8 == k) *(HC_G v2u *)(dst + 16 * r) = v2u{ow[4 * r], ow[4 * r + 1]};
+            }
+            const uint64_t pos = 32 * ((uint64_t)wi + 4 * bq) - 32 * pw0 - nbits;  // payload bits consumed
+            if ((bad & kLutBadFlag) || pos != p1) report(err, HC_ERR_CORRUPT);
+            if (s1 == cnt && (hdr & 31u)) {
+                const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
+                if (in32[pw0 + nwords - 1] & mask) report(err, HC_ERR_CORRUPT);
+            }
+        }
+        wave_lds_sync();  // every read of this pass before the next pass's copy
+        pending = pending && !take;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, hipStream_t s)
 {
@@ -1668,6 +1943,22 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     }
     // the table has 2^lut_bits entries, lut_bits = min(max_len, kLutBits) of the longest code
     const size_t lut = (size_t)2 << (max_len < (uint32_t)kLutBits ? max_len : (uint32_t)kLutBits);
+    if (with_index && S <= kStageMaxS && max_len <= (uint32_t)kPackedMaxLen) {
+        // wave-staged chunks; the table sized for the longest code's lut_bits
+#define HC_STG(R, P, L, T) k_decode_stage<R, P, L, T><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err)
+        if (max_len <= 8)
+            HC_STG(16, 4, false, 8);
+        else if (max_len <= 10)
+            HC_STG(16, 3, false, 10);
+        else if (max_len <= (uint32_t)kLutBits)
+            HC_STG(16, 2, false, 12);
+        else if (max_len <= 16)
+            HC_STG(16, 2, true, 12);
+        else
+            HC_STG(8, 1, true, 12);
+#undef HC_STG
+        return hipGetLastError();
+    }
     // a round of R symbols of <= 32 * 16 / R bits stays within one ring half (16 words)
     if (max_len <= 8)
         k_decode_ring<16, 4, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
