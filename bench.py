@@ -226,6 +226,8 @@ class Workload:
 
 
 KERNELS = ("k_hist", "k_count", "k_offsets", "k_encode", "k_decode")
+# the device functions a decode call may launch (one launch per call and kind)
+DECODE_KERNELS = ("k_decode_ring", "k_decode_stage", "k_decode")
 
 
 def kernel_times(w, torch, np, reps=20, warmup=3):
@@ -596,9 +598,9 @@ def sq_table(root: str, synth, args):
         for i in sorted(disp):
             name = disp[i]["name"]
             short = name.split("::")[-1].split("<")[0]
-            if short in ("k_count", "k_encode", "k_decode_ring"):
+            if short in ("k_count", "k_encode") + DECODE_KERNELS:
                 last[name] = disp[i]
-            if short == "k_decode_ring":
+            if short in DECODE_KERNELS:
                 decodes += 1
                 if decodes == per_kind:
                     for k, c in last.items():
@@ -606,7 +608,7 @@ def sq_table(root: str, synth, args):
                     kind, decodes, last = kind + 1, 0, {}
     rows = ["| kind | kernel | VALU / symbol | LDS / symbol | conflict / LDS active | wait | wait issue | active |",
             "|---|---|---|---|---|---|---|---|"]
-    order = {"k_count": 0, "k_encode": 1, "k_decode_ring": 2}
+    order = {"k_count": 0, "k_encode": 1, **{k: 2 for k in DECODE_KERNELS}}
     for (kind, k) in sorted(vals, key=lambda t: (t[0], order[t[1].split("::")[-1].split("<")[0]])):
         c = vals[(kind, k)]
         g = lambda n: c.get(n, float("nan"))

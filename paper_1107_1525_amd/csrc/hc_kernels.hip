@@ -1610,19 +1610,85 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// R symbols per round (16, or 8 for codes of 17..24 bits); refills of the
-// bit buffer follow symbols SPR, 2*SPR, ... of a round and its last symbol
-// (SPR * max_len <= 32); kLong: codes may be longer than the table; kLutB:
-// table entries of the launch (2^kLutB >= 2^lut_bits of every job).  All LDS
-// is static (the areas are about 33 KiB per group).
-template <uint32_t R, uint32_t SPR, bool kLong, uint32_t kLutB>
-__global__ __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(kLutB <= 10 ? 4 : 3))) void k_decode_stage(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
-                                                              uint32_t *err)
+// The bit reader of one chunk in its wave's area: 'buf' holds the 64 area
+// bits from bit position p on (at least 33 of them the chunk's: two words
+// shifted by p mod 32); the table entries decoded since the last refill are
+// summed in esum, whose low byte is then their total length (refills come
+// after at most SPR codes, SPR * max_len <= 33).
+struct StageBits {
+    uint64_t buf;
+    uint32_t p, esum;
+
+    __device__ __forceinline__ void window(const uint32_t *area)
+    {
+        const uint32_t w = p >> 5;
+        buf = (((uint64_t)area[w] << 32) | area[w + 1]) << (p & 31u);
+    }
+    __device__ __forceinline__ void refill(const uint32_t *area)
+    {
+        p += esum & 255u;
+        esum = 0;
+        window(area);
+    }
+};
+
+// One code from the reader, as its table entry (symbol << 8) | length; an
+// invalid prefix reads as a 1-bit code flagged kLutBadFlag (or-ed into bad).
+// kLong: codes longer than the table take the canonical-range search on the
+// buffered bits (which hold >= max_len bits whenever a code starts).
+template <bool kLong>
+__device__ __forceinline__ uint32_t stage_entry(StageBits &b, const uint16_t *lut, uint32_t lut_shift, uint32_t K,
+                                                uint32_t max_len, const uint32_t *s_first, const uint32_t *s_count,
+                                                const uint32_t *s_base, const uint32_t *s_sorted, uint32_t &bad)
 {
+    uint32_t e = lut[(uint32_t)(b.buf >> 32) >> lut_shift];
+    if (kLong && (e & 255u) == 0) {
+        uint32_t L = 0, sym = 0;
+        for (uint32_t l = K + 1; l <= max_len; ++l) {
+            const uint32_t cv = (uint32_t)(b.buf >> (64 - l));
+            const uint32_t d = cv - s_first[l];
+            if (d < s_count[l]) {
+                L = l;
+                sym = s_sorted[s_base[l] + d];
+                break;
+            }
+        }
+        e = L ? (sym << 8) | L : (kLutBadFlag | 1u);
+    }
+    bad |= e;
+    b.buf <<= (e & 63u);
+    b.esum += e;
+    return e;
+}
+
+// The entry's byte 1 (the symbol) into byte q & 3 of a word, the other bytes kept.
+__device__ __forceinline__ uint32_t put_sym(uint32_t e, uint32_t word, uint32_t q)
+{
+    constexpr uint32_t kSel[4] = {0x03020105u, 0x03020500u, 0x03050100u, 0x05020100u};
+    return __builtin_amdgcn_perm(e, word, kSel[q & 3]);
+}
+
+// R symbols per round (16, or 8 for codes of 17..24 bits); refills follow
+// symbols SPR, 2*SPR, ... of a round and its last symbol; kLong: codes may be
+// longer than the table; kLutB: table entries of the launch (2^kLutB >=
+// 2^lut_bits of every job).  kChains: consecutive chunks per lane (2 for
+// chunks of <= 64 symbols: two independent decode chains interleaved, so
+// each lane has two table reads in flight; 1 for chunks of 65..128).  A
+// group always covers 256 chunks (256 / kChains lanes).  All LDS is static
+// (about 8 KiB of area per wave).
+template <uint32_t R, uint32_t SPR, bool kLong, uint32_t kLutB, uint32_t kChains>
+__global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_per_eu(kLutB <= 10 ? 4 : 3))) void k_decode_stage(
+    JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb, uint32_t *err)
+{
+    constexpr uint32_t kThreads = kDecThreads / kChains;
+    constexpr uint32_t kWaves = kThreads / 64;
+    constexpr uint32_t kChainSyms = kStageMaxS / kChains;  // the longest chunk of the launch
+    constexpr uint32_t kChainWords = kChainSyms / 4;       // its output words
     constexpr uint32_t kRoundWords = R / 4;
-    constexpr uint32_t kRounds = kStageMaxS / R;  // rounds of a full chunk (one output line)
+    constexpr uint32_t kChainRounds = kChainSyms / R;
+    static_assert(kChainSyms % 16 == 0 && kChainSyms % R == 0, "whole 16-byte pieces per chunk");
     __shared__ __attribute__((aligned(16))) uint16_t s_lut[1u << kLutB];
-    __shared__ __attribute__((aligned(16))) uint32_t s_area[kDecThreads / 64 * kStageWords + kStageSlackWords];
+    __shared__ __attribute__((aligned(16))) uint32_t s_area[kWaves * kStageWords + kStageSlackWords];
     __shared__ uint32_t s_first[kPackedMaxLen + 1];
     __shared__ uint32_t s_count[kPackedMaxLen + 1];
     __shared__ uint32_t s_base[kPackedMaxLen + 1];
@@ -1647,80 +1713,99 @@ __global__ __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(kLu
     {
         // the table, 8 entries (16 bytes) per load
         const uint32_t nq = (1u << K) >= 8 ? (1u << K) / 8 : 1u;
-        for (uint32_t k = tid; k < nq; k += kDecThreads) ((v4u *)s_lut)[k] = ((const HC_G v4u *)tb->lut)[k];
+        for (uint32_t k = tid; k < nq; k += kThreads) ((v4u *)s_lut)[k] = ((const HC_G v4u *)tb->lut)[k];
     }
     if (tid <= (uint32_t)kPackedMaxLen) {
         s_first[tid] = (uint32_t)tb->first[tid];
         s_count[tid] = tb->count[tid];
         s_base[tid] = tb->base[tid];
     }
-    s_sorted[tid] = tb->sorted[tid];
+    for (uint32_t k = tid; k < (uint32_t)kNumSym; k += kThreads) s_sorted[k] = tb->sorted[k];
     __syncthreads();  // the last barrier of the group: waves go their own way from here
 
-    // ---- the lane's chunk and its checks (as k_decode_ring)
-    const uint64_t g = (uint64_t)(blockIdx.x - s_job.unit_begin) * kDecThreads + tid;
-    const uint64_t i = g / cpb;
-    const uint32_t c = (uint32_t)(g - i * cpb);
-    bool ok = i < nb;
-    uint64_t blk_start = 0, o = 0, o1 = 0, p0 = 0, p1 = 0;
-    uint32_t cnt = 0, s0 = 0, s1 = 0, hdr = 0, nwords = 0;
-    if (ok) {
-        blk_start = i * (uint64_t)B;
-        const uint64_t left = n - blk_start;
-        cnt = (uint32_t)(left < B ? left : B);
-        s0 = c * S_eff;
-        ok = s0 < cnt;
+    // ---- the lane's chunks and their checks (as k_decode_ring, per chunk)
+    const bool small_job = nb * cpb < (1ull << 32);  // chunk numbers fit 32 bits (the same in every lane)
+    bool ok[kChains];
+    uint64_t blk_start[kChains], pw0[kChains], fw[kChains], lw[kChains], p0[kChains], p1[kChains];
+    uint32_t cnt[kChains], s0[kChains], s1[kChains], hdr[kChains], nwords[kChains];
+#pragma unroll
+    for (uint32_t h = 0; h < kChains; ++h) {
+        const uint64_t g = ((uint64_t)(blockIdx.x - s_job.unit_begin) * kThreads + tid) * kChains + h;
+        const uint64_t i = small_job ? (uint64_t)((uint32_t)g / cpb) : g / cpb;
+        const uint32_t c = (uint32_t)(g - i * cpb);
+        bool k_ok = i < nb;
+        uint64_t o = 0, o1 = 0;
+        blk_start[h] = 0; p0[h] = 0; p1[h] = 0;
+        cnt[h] = 0; s0[h] = 0; s1[h] = 0; hdr[h] = 0; nwords[h] = 0;
+        if (k_ok) {
+            blk_start[h] = i * (uint64_t)B;
+            const uint64_t left = n - blk_start[h];
+            cnt[h] = (uint32_t)(left < B ? left : B);
+            s0[h] = c * S_eff;
+            k_ok = s0[h] < cnt[h];
+        }
+        if (k_ok) {
+            s1[h] = (cnt[h] - s0[h] < S_eff) ? cnt[h] : s0[h] + S_eff;
+            o = off[i];
+            o1 = off[i + 1];
+            if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
+                report(err, HC_ERR_CORRUPT);
+                k_ok = false;
+            }
+        }
+        if (k_ok) {
+            if (c == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
+            hdr[h] = in32[o >> 2];
+            if (o + 4 + 4 * (((uint64_t)hdr[h] + 31) / 32) != o1) {
+                report(err, HC_ERR_CORRUPT);
+                k_ok = false;
+            }
+        }
+        if (k_ok) {
+            nwords[h] = (uint32_t)(((uint64_t)hdr[h] + 31) >> 5);
+            p1[h] = hdr[h];
+            p0[h] = sub_idx[i * cpb + c];
+            if (s1[h] < cnt[h]) p1[h] = sub_idx[i * cpb + c + 1];
+            // every code has 1 .. max_len bits
+            const uint64_t ns = s1[h] - s0[h];
+            if (p0[h] > p1[h] || p1[h] > hdr[h] || p1[h] - p0[h] < ns || p1[h] - p0[h] > ns * max_len) {
+                report(err, HC_ERR_CORRUPT);
+                k_ok = false;
+            }
+        }
+        ok[h] = k_ok;
+        pw0[h] = (o >> 2) + 1;                  // stream word of payload bit 0
+        fw[h] = pw0[h] + (p0[h] >> 5);          // stream word of the chunk's first bit
+        lw[h] = pw0[h] + ((p1[h] - 1) >> 5);    // and of its last bit
     }
-    if (ok) {
-        s1 = (cnt - s0 < S_eff) ? cnt : s0 + S_eff;
-        o = off[i];
-        o1 = off[i + 1];
-        if ((o & 3) || o + 4 > in_bytes || o1 > in_bytes || o1 < o + 4) {
-            report(err, HC_ERR_CORRUPT);
-            ok = false;
+    // the stream words the lane's chunks span
+    uint64_t lo = ~0ull, hi = 0;
+    bool pending = false;
+#pragma unroll
+    for (uint32_t h = 0; h < kChains; ++h) {
+        if (ok[h]) {
+            lo = fw[h] < lo ? fw[h] : lo;
+            hi = lw[h] > hi ? lw[h] : hi;
+            pending = true;
         }
     }
-    if (ok) {
-        if (c == 0 && ((i == 0 && o != 0) || (i + 1 == nb && o1 != in_bytes))) report(err, HC_ERR_CORRUPT);
-        hdr = in32[o >> 2];
-        if (o + 4 + 4 * (((uint64_t)hdr + 31) / 32) != o1) {
-            report(err, HC_ERR_CORRUPT);
-            ok = false;
-        }
-    }
-    if (ok) {
-        nwords = (uint32_t)(((uint64_t)hdr + 31) >> 5);
-        p1 = hdr;
-        p0 = sub_idx[i * cpb + c];
-        if (s1 < cnt) p1 = sub_idx[i * cpb + c + 1];
-        // every code has 1 .. max_len bits
-        if (p0 > p1 || p1 > hdr || p1 - p0 < (uint64_t)(s1 - s0) || p1 - p0 > (uint64_t)(s1 - s0) * max_len) {
-            report(err, HC_ERR_CORRUPT);
-            ok = false;
-        }
-    }
-    const uint64_t pw0 = (o >> 2) + 1;            // stream word of payload bit 0
-    const uint64_t fw = pw0 + (p0 >> 5);           // stream word of the chunk's first bit
-    const uint64_t lw = pw0 + ((p1 - 1) >> 5);     // and of its last bit
     const uint64_t in_words = in_bytes >> 2;
     const int64_t q_last = (int64_t)((in_words ? in_words - 1 : 0) >> 2);  // the stream's last quad
     uint32_t *const area = s_area + wave * kStageWords;
     constexpr uint32_t area_quads = kStageWords / 4;
-
-    HC_G uint8_t *const dst = out + blk_start + s0;
-    const uint32_t nsym = s1 - s0;
+    const uint32_t lut_shift = 32 - K;
     uint32_t bad = 0;  // kLutBadFlag: an invalid prefix was met
-    bool pending = ok;
+
     while (__any(pending)) {
         // the pass: pending lanes whose words (and the three the bit buffer
         // reads ahead) fit the area from the lowest pending quad on
-        const uint64_t bq = wave_min_u64(pending ? (fw >> 2) : ~0ull);
-        const bool take = pending && ((lw + 3) >> 2) < bq + area_quads;
-        const uint64_t eq = wave_max_u64(take ? ((lw + 3) >> 2) + 1 : 0ull);
+        const uint64_t bq = wave_min_u64(pending ? (lo >> 2) : ~0ull);
+        const bool take = pending && ((hi + 3) >> 2) < bq + area_quads;
+        const uint64_t eq = wave_max_u64(take ? ((hi + 3) >> 2) + 1 : 0ull);
         if (!__any(take)) {
-            // not reached: the launch sizes the area for the longest chunk the
-            // checks above let through; kept so that no wave can loop forever
-            if (pending && (fw >> 2) == bq) {
+            // not reached with a valid stream (a lane's chunks span far less
+            // than an area); a corrupt one may, and no wave may loop forever
+            if (pending && (lo >> 2) == bq) {
                 report(err, HC_ERR_CORRUPT);
                 pending = false;
             }
@@ -1745,88 +1830,110 @@ __global__ __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(kLu
         }
         wave_lds_sync();
         if (take) {
-            // ---- bit buffer: the next nbits chunk bits, most significant first;
-            // 'pre' is the area word at wi, read ahead of its refill
-            uint32_t wi = (uint32_t)(fw - 4 * bq);
-            const uint32_t r0 = (uint32_t)(p0 & 31);
-            uint64_t buf = (((uint64_t)area[wi] << 32) | area[wi + 1]) << r0;
-            uint32_t nbits = 64 - r0;
-            wi += 2;
-            uint32_t pre = area[wi];
-            const uint32_t lut_shift = 32 - K;
-            uint32_t esum = 0;
-            auto decode_entry = [&]() -> uint32_t {
-                uint32_t e = s_lut[(uint32_t)(buf >> 32) >> lut_shift];
-                if (kLong && (e & 255u) == 0) {
-                    uint32_t L = 0, sym = 0;
-                    for (uint32_t l = K + 1; l <= max_len; ++l) {
-                        const uint32_t cv = (uint32_t)(buf >> (64 - l));
-                        const uint32_t d = cv - s_first[l];
-                        if (d < s_count[l]) {
-                            L = l;
-                            sym = s_sorted[s_base[l] + d];
-                            break;
+            StageBits rd[kChains];
+#pragma unroll
+            for (uint32_t h = 0; h < kChains; ++h) {
+                rd[h].p = 32 * (uint32_t)(fw[h] - 4 * bq) + (uint32_t)(p0[h] & 31);
+                rd[h].esum = 0;
+                if (ok[h]) rd[h].window(area);
+            }
+            auto entry = [&](uint32_t h) -> uint32_t {
+                return stage_entry<kLong>(rd[h], s_lut, lut_shift, K, max_len, s_first, s_count, s_base, s_sorted,
+                                          bad);
+            };
+            uint32_t ow[kChains * kChainWords];
+#pragma unroll
+            for (uint32_t q = 0; q < kChains * kChainWords; ++q) ow[q] = 0;  // (nothing flows from an earlier pass)
+            uint32_t done[kChains];  // symbols of each chunk decoded into ow (whole rounds)
+            bool all_full = true;
+#pragma unroll
+            for (uint32_t h = 0; h < kChains; ++h) all_full = all_full && ok[h] && s1[h] - s0[h] == S_eff;
+            if (kChains > 1 && all_full && S_eff % R == 0) {
+                // the usual case: both chunks whole, their codes decoded in turn
+                const uint32_t nr = S_eff / R;
+#pragma unroll
+                for (uint32_t r = 0; r < kChainRounds; ++r) {
+                    if (r < nr) {
+                        uint32_t o4[kChains][kRoundWords];
+#pragma unroll
+                        for (uint32_t h = 0; h < kChains; ++h)
+#pragma unroll
+                            for (uint32_t q = 0; q < kRoundWords; ++q) o4[h][q] = 0;
+#pragma unroll
+                        for (uint32_t q = 0; q < R; ++q) {
+#pragma unroll
+                            for (uint32_t h = 0; h < kChains; ++h) o4[h][q >> 2] = put_sym(entry(h), o4[h][q >> 2], q);
+                            if ((q + 1) % SPR == 0 || q + 1 == R)
+#pragma unroll
+                                for (uint32_t h = 0; h < kChains; ++h) rd[h].refill(area);
+                        }
+#pragma unroll
+                        for (uint32_t h = 0; h < kChains; ++h)
+#pragma unroll
+                            for (uint32_t q = 0; q < kRoundWords; ++q) ow[h * kChainWords + kRoundWords * r + q] = o4[h][q];
+                    }
+                }
+#pragma unroll
+                for (uint32_t h = 0; h < kChains; ++h) done[h] = nr * R;
+            } else {
+                // one chunk after the other: a block's short last chunk, a
+                // chunk that failed its checks, or one chunk per lane
+#pragma unroll
+                for (uint32_t h = 0; h < kChains; ++h) {
+                    done[h] = 0;
+                    if (ok[h]) {
+                        const uint32_t nfull = (s1[h] - s0[h]) / R;
+#pragma unroll
+                        for (uint32_t r = 0; r < kChainRounds; ++r) {
+                            if (r < nfull) {
+                                uint32_t o4[kRoundWords];
+#pragma unroll
+                                for (uint32_t q = 0; q < kRoundWords; ++q) o4[q] = 0;
+#pragma unroll
+                                for (uint32_t q = 0; q < R; ++q) {
+                                    o4[q >> 2] = put_sym(entry(h), o4[q >> 2], q);
+                                    if ((q + 1) % SPR == 0 || q + 1 == R) rd[h].refill(area);
+                                }
+#pragma unroll
+                                for (uint32_t q = 0; q < kRoundWords; ++q) ow[h * kChainWords + kRoundWords * r + q] = o4[q];
+                            }
+                        }
+                        done[h] = nfull * R;
+                        HC_G uint8_t *const dst = out + blk_start[h] + s0[h];
+                        for (uint32_t q = done[h]; q < s1[h] - s0[h]; ++q) {  // the ragged end of a block's last chunk
+                            dst[q] = (uint8_t)(entry(h) >> 8);
+                            rd[h].refill(area);
                         }
                     }
-                    e = L ? (sym << 8) | L : (kLutBadFlag | 1u);
                 }
-                bad |= e;
-                buf <<= (e & 63u);
-                esum += e;
-                return e;
-            };
-            auto refill = [&]() {
-                nbits -= esum & 255u;
-                esum = 0;
-                const bool need = nbits < 32;
-                const uint32_t w = need ? pre : 0u;
-                buf |= (uint64_t)w << ((32 - nbits) & 63u);
-                nbits += need ? 32u : 0u;
-                wi += need ? 1u : 0u;
-                pre = area[wi];
-            };
-            const uint32_t nfull = nsym / R;
-            uint32_t ow[kRounds * kRoundWords];
+            }
+            // each chunk's output: whole 16-byte pieces from the registers, then
+            // (rounds of 8 symbols) a last 8-byte piece; then its checks
 #pragma unroll
-            for (uint32_t q = 0; q < kRounds * kRoundWords; ++q) ow[q] = 0;  // (nothing flows from an earlier pass)
+            for (uint32_t h = 0; h < kChains; ++h) {
+                if (ok[h]) {
+                    HC_G uint8_t *const dst = out + blk_start[h] + s0[h];
+                    const uint32_t k = done[h];
 #pragma unroll
-            for (uint32_t r = 0; r < kRounds; ++r) {
-                if (r < nfull) {
-                    uint32_t o4[kRoundWords];
+                    for (uint32_t r = 0; r < kChainSyms / 16; ++r)
+                        if (16 * r + 16 <= k)
+                            *(HC_G v4u *)(dst + 16 * r) = v4u{ow[h * kChainWords + 4 * r], ow[h * kChainWords + 4 * r + 1],
+                                                              ow[h * kChainWords + 4 * r + 2], ow[h * kChainWords + 4 * r + 3]};
+                    if (R == 8 && (k & 8u)) {
 #pragma unroll
-                    for (uint32_t q = 0; q < kRoundWords; ++q) o4[q] = 0;
-#pragma unroll
-                    for (uint32_t q = 0; q < R; ++q) {
-                        // the entry's byte 1 (the symbol) into byte q & 3 of the word, the other bytes kept
-                        constexpr uint32_t kSel[4] = {0x03020105u, 0x03020500u, 0x03050100u, 0x05020100u};
-                        o4[q >> 2] = __builtin_amdgcn_perm(decode_entry(), o4[q >> 2], kSel[q & 3]);
-                        if ((q + 1) % SPR == 0 || q + 1 == R) refill();
+                        for (uint32_t r = 0; r < kChainSyms / 16; ++r)
+                            if (16 * r + 8 == k)
+                                *(HC_G v2u *)(dst + 16 * r) = v2u{ow[h * kChainWords + 4 * r], ow[h * kChainWords + 4 * r + 1]};
                     }
-#pragma unroll
-                    for (uint32_t q = 0; q < kRoundWords; ++q) ow[kRoundWords * r + q] = o4[q];
+                    const uint64_t pos = 128 * bq + rd[h].p - 32 * pw0[h];  // payload bits consumed
+                    if (pos != p1[h]) report(err, HC_ERR_CORRUPT);
+                    if (s1[h] == cnt[h] && (hdr[h] & 31u)) {
+                        const uint32_t mask = (1u << (32 - (hdr[h] & 31u))) - 1u;
+                        if (in32[pw0[h] + nwords[h] - 1] & mask) report(err, HC_ERR_CORRUPT);
+                    }
                 }
             }
-            const uint32_t k = nfull * R;
-            for (uint32_t q = 0; q < nsym - k; ++q) {  // the ragged end of a block's last chunk
-                dst[k + q] = (uint8_t)(decode_entry() >> 8);
-                refill();
-            }
-            // the chunk's output: whole 16-byte pieces from the registers, then
-            // (rounds of 8 symbols) a last 8-byte piece
-#pragma unroll
-            for (uint32_t r = 0; r < kStageMaxS / 16; ++r)
-                if (16 * r + 16 <= k) *(HC_G v4u *)(dst + 16 * r) = v4u{ow[4 * r], ow[4 * r + 1], ow[4 * r + 2], ow[4 * r + 3]};
-            if (R == 8 && (k & 8u)) {
-#pragma unroll
-                for (uint32_t r = 0; r < kStageMaxS / 16; ++r)
-                    if (16 * r + 8 == k) *(HC_G v2u *)(dst + 16 * r) = v2u{ow[4 * r], ow[4 * r + 1]};
-            }
-            const uint64_t pos = 32 * ((uint64_t)wi + 4 * bq) - 32 * pw0 - nbits;  // payload bits consumed
-            if ((bad & kLutBadFlag) || pos != p1) report(err, HC_ERR_CORRUPT);
-            if (s1 == cnt && (hdr & 31u)) {
-                const uint32_t mask = (1u << (32 - (hdr & 31u))) - 1u;
-                if (in32[pw0 + nwords - 1] & mask) report(err, HC_ERR_CORRUPT);
-            }
+            if (bad & kLutBadFlag) report(err, HC_ERR_CORRUPT);
         }
         wave_lds_sync();  // every read of this pass before the next pass's copy
         pending = pending && !take;
@@ -1944,8 +2051,15 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     // the table has 2^lut_bits entries, lut_bits = min(max_len, kLutBits) of the longest code
     const size_t lut = (size_t)2 << (max_len < (uint32_t)kLutBits ? max_len : (uint32_t)kLutBits);
     if (with_index && S <= kStageMaxS && max_len <= (uint32_t)kPackedMaxLen) {
-        // wave-staged chunks; the table sized for the longest code's lut_bits
-#define HC_STG(R, P, L, T) k_decode_stage<R, P, L, T><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err)
+        // wave-staged chunks; the table sized for the longest code's lut_bits;
+        // two chunks per lane up to 64 symbols (groups of 128 lanes)
+#define HC_STG(R, P, L, T)                                                                                       \
+    do {                                                                                                          \
+        if (S <= kStageMaxS / 2)                                                                                  \
+            k_decode_stage<R, P, L, T, 2><<<grid, kDecThreads / 2, 0, s>>>(jl, B, S_eff, cpb, err);               \
+        else                                                                                                      \
+            k_decode_stage<R, P, L, T, 1><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);                   \
+    } while (0)
         if (max_len <= 8)
             HC_STG(16, 4, false, 8);
         else if (max_len <= 10)
