@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--block", type=int, default=64 * 1024)
-    ap.add_argument("--sub-block", type=int, default=1024)
+    ap.add_argument("--sub-block", type=int, default=128)
     ap.add_argument("--segments", type=int, default=64, help="number of 64 MiB segments (64 = 4 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true")

@@ -36,7 +36,9 @@ namespace hc {
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ void report(uint32_t *err, uint32_t code)
 {
-    if (err) atomicCAS(err, 0u, code);
+    // the plain read first: once the word holds an error, the many lanes of a
+    // corrupt stream do not all queue on one atomic
+    if (err && *(volatile uint32_t *)err == 0u) atomicCAS(err, 0u, code);
 }
 
 template <typename T>
@@ -1579,6 +1581,7 @@ constexpr uint32_t kStageSlackWords = 128;  // after the last wave's area: reads
 // the longest chunk the checks let through (kStageMaxS codes of 24 bits) with
 // the bit buffer's read-ahead.  Static: the areas are fixed-size arrays.
 constexpr uint32_t kStageWords = 64 * kStageMaxS / 4 + 16;
+static_assert(kStageWords >= 32 * 36, "half a wave's output lines fit the area");
 static_assert(kStageWords % 4 == 0 && kStageWords >= (kStageMaxS * kPackedMaxLen) / 32 + 16, "area too small");
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
@@ -1829,6 +1832,13 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
             }
         }
         wave_lds_sync();
+        // every chunk of the wave whole and taken in this pass: the wave's
+        // output is one contiguous range (a lane's chunks are consecutive, and
+        // so are the lanes'), stored through the area afterwards
+        bool whole = take;
+#pragma unroll
+        for (uint32_t h = 0; h < kChains; ++h) whole = whole && ok[h] && s1[h] - s0[h] == S_eff;
+        const bool coalesce = __all(whole) && S_eff * kChains == kStageMaxS;
         if (take) {
             StageBits rd[kChains];
 #pragma unroll
@@ -1907,11 +1917,38 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
                     }
                 }
             }
-            // each chunk's output: whole 16-byte pieces from the registers, then
-            // (rounds of 8 symbols) a last 8-byte piece; then its checks
+            if (coalesce) {
+                // all 64 lanes are here.  Each half of the wave in turn puts its
+                // 128-byte lines into the area (lane stride 36 words: a 16-byte
+                // write instruction covers all 64 banks), then the wave stores
+                // them with lane l on 16 bytes 64u + l: every store instruction
+                // writes a contiguous 1 KiB instead of touching 64 lines
+                const uint64_t a0 = (uint64_t)(out + blk_start[0] + s0[0]);
+                HC_G uint8_t *const base =
+                    (HC_G uint8_t *)((((uint64_t)__shfl((uint32_t)(a0 >> 32), 0, 64)) << 32) | __shfl((uint32_t)a0, 0, 64));
+                wave_lds_sync();  // the decode's reads of the area are done
+#pragma unroll
+                for (uint32_t half = 0; half < 2; ++half) {
+                    if ((lane >> 5) == half) {
+#pragma unroll
+                        for (uint32_t r = 0; r < 8; ++r)
+                            *(v4u *)(area + 36 * (lane & 31u) + 4 * r) = v4u{ow[4 * r], ow[4 * r + 1], ow[4 * r + 2], ow[4 * r + 3]};
+                    }
+                    wave_lds_sync();
+#pragma unroll
+                    for (uint32_t u = 0; u < 4; ++u) {
+                        const uint32_t Q = 64 * u + lane;
+                        *(HC_G v4u *)(base + 4096 * half + 16 * Q) = *(const v4u *)(area + 36 * (Q >> 3) + 4 * (Q & 7u));
+                    }
+                    wave_lds_sync();
+                }
+            }
+            // each chunk's output (unless stored above): whole 16-byte pieces
+            // from the registers, then (rounds of 8 symbols) a last 8-byte
+            // piece; then its checks
 #pragma unroll
             for (uint32_t h = 0; h < kChains; ++h) {
-                if (ok[h]) {
+                if (ok[h] && !coalesce) {
                     HC_G uint8_t *const dst = out + blk_start[h] + s0[h];
                     const uint32_t k = done[h];
 #pragma unroll
@@ -1925,6 +1962,8 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
                             if (16 * r + 8 == k)
                                 *(HC_G v2u *)(dst + 16 * r) = v2u{ow[h * kChainWords + 4 * r], ow[h * kChainWords + 4 * r + 1]};
                     }
+                }
+                if (ok[h]) {
                     const uint64_t pos = 128 * bq + rd[h].p - 32 * pw0[h];  // payload bits consumed
                     if (pos != p1[h]) report(err, HC_ERR_CORRUPT);
                     if (s1[h] == cnt[h] && (hdr[h] & 31u)) {
