@@ -26,9 +26,12 @@
  * Conventions shared by all entry points:
  *   - Pointers named d_* are device memory owned by the caller; h_* are host
  *     memory owned by the caller.  The library allocates memory only in
- *     hc_codebook_upload (freed by hc_codebook_destroy); no other call
- *     allocates or frees, and only hc_codebook_upload, hc_codebook_update
- *     (see there) and hc_codebook_destroy wait on the device.
+ *     hc_codebook_upload and hc_cbset_create (freed by hc_codebook_destroy and
+ *     hc_cbset_destroy); no other call allocates or frees.  Calls that wait
+ *     on the host: hc_codebook_upload (its copy), hc_codebook_update and
+ *     hc_cbset_build (the handle's or set's own previous table copy, normally
+ *     long finished), hc_codebook_destroy and hc_cbset_destroy (the same, and
+ *     the runtime's free).  The coding calls never wait.
  *   - 'stream' is a hipStream_t passed as void* (NULL = the null stream).
  *     Device work is enqueued on it and the call returns without waiting.
  *   - Errors that the host can see (bad sizes, null or misaligned pointers,
@@ -67,7 +70,10 @@ typedef enum {
     HC_ERR_SYMBOL_ABSENT = 4,  /* the input holds a symbol the codebook has no code for */
     HC_ERR_BLOCK_OVERFLOW = 5, /* a block's bit count does not fit the 4-byte header */
     HC_ERR_CORRUPT = 6,        /* the compressed stream is not a valid encoding */
-    HC_ERR_CODE_TOO_LONG = 7   /* a Huffman code would be longer than 64 bits */
+    HC_ERR_CODE_TOO_LONG = 7,  /* a Huffman code would be longer than 64 bits */
+    HC_ERR_TABLE_CHANGED = 8   /* (in d_err) a launch met code tables other than those it
+                                  was shaped for: a replayed graph whose codes got longer
+                                  or stopped being complete 8-bit codes */
 } hc_status;
 
 /* Host description of a code: lengths and canonical code values.
@@ -162,11 +168,15 @@ hc_cb_handle hc_cbset_handle(hc_cbset set, uint32_t k);
 /* calling one included.  Errors: INVALID_ARG, CODE_TOO_LONG, HIP.         */
 hc_status hc_cbset_build(hc_cbset set, const uint64_t *h_hists, hc_codebook *h_out, void *stream);
 
-/* Frees a set (NULL is accepted).  Waits for the device to finish.       */
+/* Frees a set (NULL is accepted).  Waits for the set's own last table    */
+/* copy, not for the device; the caller must have ordered every launch     */
+/* that reads the set's tables before the call (a stream or event          */
+/* synchronisation), as for any freed buffer.                              */
 hc_status hc_cbset_destroy(hc_cbset set);
 
 /* Frees a handle from hc_codebook_upload (NULL is accepted).  Waits for  */
-/* the device to finish work that may still read it.                      */
+/* the handle's own last table copy only; launches that read the handle   */
+/* must be finished (ordered by the caller) before the call.              */
 hc_status hc_codebook_destroy(hc_cb_handle cb);
 
 /* ---------------------------------------------------------------------- */
@@ -249,11 +259,19 @@ hc_status hc_walk_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t nb, ui
 
 /* ---------------------------------------------------------------------- */
 /* Parallel block decoding (section 2.1, section 3.2).                    */
-/*   d_in, in_bytes  the stream (16-byte aligned, in_bytes % 4 == 0).      */
+/*   d_in, in_bytes  the stream (16-byte aligned, in_bytes % 4 == 0).  The */
+/*                   decoder reads whole 16-byte pieces, so the last one   */
+/*                   may reach up to 12 bytes past in_bytes (within the    */
+/*                   16-byte piece that holds the stream's last word; the  */
+/*                   values read there never reach the output).            */
 /*   n, block_size   symbol count and B used to encode.                    */
 /*   cb              the encoding's codebook.                              */
 /*   d_block_off     nb + 1 u64 offsets (from hc_encode_blocks or          */
-/*                   hc_walk_blocks).                                      */
+/*                   hc_walk_blocks).  Required: a NULL table is refused   */
+/*                   (INVALID_ARG) rather than walked here, because the    */
+/*                   walk needs nb + 1 u64 of memory that this call does   */
+/*                   not take and would not allocate; walk first with      */
+/*                   hc_walk_blocks into a buffer of the caller's.         */
 /*   d_sub_idx, sub_block  the sub-block index written by hc_encode_blocks */
 /*                   with the same S, or NULL and 0: then each block is    */
 /*                   decoded as one piece.                                 */
@@ -272,9 +290,9 @@ hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t n, u
 /* ---------------------------------------------------------------------- */
 /* Batches: many independent buffers, each with its own codebook, in one  */
 /* launch per step (the blocks of all buffers are independent units of    */
-/* work, section 2.1: "concurrent compression and decompression on        */
-/* multiple processors").  Every buffer follows the contract of the       */
-/* single-buffer call; B and S are common to the batch.                   */
+/* work that many processors may code at once: abstract, section 2.1).    */
+/* Every buffer follows the contract of the single-buffer call; B and S    */
+/* are common to the batch.                                                */
 /* ---------------------------------------------------------------------- */
 typedef struct {
     const uint8_t *in;    /* histogram / encode: the n bytes (16-byte aligned); decode: the stream */
@@ -311,7 +329,7 @@ hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_s
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
 /* The three steps of hc_encode_batch as separate calls (section 2.1: the  */
-/* block lengths, the offsets "where the block starts and ends", then the  */
+/* block lengths, the table of where each block begins, then the          */
 /* packing), for callers that time or schedule them one by one.  Same      */
 /* arguments as hc_encode_batch; issue them in this order on one stream    */
 /* with the same items and workspace (the workspace carries each tile's    */
@@ -335,7 +353,15 @@ hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, uint32_t bl
 /* sub_idx, out).  At most two launches: items whose code is a complete    */
 /* 8-bit code (all 256 bytes, 8 bits each) decode as a byte-swapped copy   */
 /* in a launch of their own; the rest in one launch of the table decoder. */
-/* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: CORRUPT.         */
+/* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: CORRUPT,         */
+/* TABLE_CHANGED.                                                           */
+/* Graph capture: the batch calls choose kernel variants and shapes from   */
+/* every item's code (longest code, complete 8-bit code or not) when they  */
+/* are called.  A captured graph therefore stays valid only while no       */
+/* item's longest code grows and no complete 8-bit code of a decode stops  */
+/* being one; the kernels of a replay that meet such tables leave at once  */
+/* and report TABLE_CHANGED in *d_err (outputs unspecified, as after any   */
+/* error); shorter codes are fine.                                         */
 hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
@@ -367,10 +393,11 @@ hc_status hc_decode_blocks_selfsync(const uint8_t *d_in, uint64_t in_bytes, uint
 /* device memory and pinned host memory that should not wait on the        */
 /* runtime's copy engines (the host-resident pipeline's copy-out).         */
 /* d_dst[0 .. n-1] = d_src[0 .. n-1]; both 16-byte aligned, n % 16 == 0,    */
-/* no overlap.  Both ranges (first and last byte) must be device-accessible */
-/* at their own addresses: device memory or host memory pinned by the HIP  */
-/* runtime; the call checks this with the runtime and refuses otherwise    */
-/* (pageable host memory included).  One launch, no allocation.            */
+/* no overlap.  Each range must lie inside one allocation that the device */
+/* reaches at its own addresses: device memory or host memory pinned by   */
+/* the HIP runtime; the call checks this with the runtime and refuses      */
+/* otherwise (pageable host memory, a range running past its allocation).  */
+/* One launch, no allocation.                                              */
 /* Errors returned: INVALID_ARG, HIP.                                      */
 /* ---------------------------------------------------------------------- */
 hc_status hc_copy(const void *d_src, void *d_dst, uint64_t n, void *stream);

@@ -38,6 +38,7 @@ HC_ERR_SYMBOL_ABSENT = 4
 HC_ERR_BLOCK_OVERFLOW = 5
 HC_ERR_CORRUPT = 6
 HC_ERR_CODE_TOO_LONG = 7
+HC_ERR_TABLE_CHANGED = 8
 
 
 class HcError(RuntimeError):

@@ -121,6 +121,7 @@ extern "C" const char *hc_status_str(int status)
     case HC_ERR_BLOCK_OVERFLOW: return "HC_ERR_BLOCK_OVERFLOW";
     case HC_ERR_CORRUPT: return "HC_ERR_CORRUPT";
     case HC_ERR_CODE_TOO_LONG: return "HC_ERR_CODE_TOO_LONG";
+    case HC_ERR_TABLE_CHANGED: return "HC_ERR_TABLE_CHANGED";
     default: return "HC_ERR_UNKNOWN";
     }
 }
@@ -280,7 +281,9 @@ extern "C" hc_status hc_cbset_build(hc_cbset set, const uint64_t *h_hists, hc_co
 extern "C" hc_status hc_cbset_destroy(hc_cbset set)
 {
     if (!set) return HC_OK;
-    hipError_t e = hipDeviceSynchronize();
+    // the set's own last copy out of its staging area; launches reading the
+    // tables are the caller's to have ordered before this call
+    hipError_t e = hipEventSynchronize(static_cast<hipEvent_t>(set->copy_done));
     (void)hipFree(set->d_tables);
     (void)hipHostFree(set->staging);
     (void)hipEventDestroy(static_cast<hipEvent_t>(set->copy_done));
@@ -292,7 +295,9 @@ extern "C" hc_status hc_cbset_destroy(hc_cbset set)
 extern "C" hc_status hc_codebook_destroy(hc_cb_handle cb)
 {
     if (!cb || cb->in_set) return HC_OK;
-    hipError_t e = hipDeviceSynchronize();
+    // the handle's own last table copy; launches reading it are the caller's
+    // to have ordered before this call
+    hipError_t e = hipEventSynchronize(static_cast<hipEvent_t>(cb->copy_done));
     release(cb);
     return hip_status(e);
 }

@@ -4,9 +4,9 @@
 // and writing straight into the destination (pinned host memory is reached
 // over PCIe).  The small grid leaves the CUs to coding kernels running beside
 // it.  Both ranges must be device-accessible at their own addresses (device
-// memory, or host memory pinned by the HIP runtime); the call asks the
-// runtime before launching and refuses anything else, pageable host memory
-// included.
+// memory, or host memory pinned by the HIP runtime), each inside one
+// allocation; the call asks the runtime before launching and refuses
+// anything else, pageable host memory included.
 #include <hip/hip_runtime.h>
 
 #include "hc.h"
@@ -34,9 +34,11 @@ __global__ __launch_bounds__(kCopyThreads) void k_copy(const cv4 *__restrict__ s
     for (; i < end; i += kCopyThreads) dst[i] = src[i];
 }
 
-// The runtime knows p (device memory or its own pinned host memory) and the
-// device reaches it at the same address.
-bool device_visible(const void *p)
+// The runtime knows [p, p + n) as part of one allocation (device memory or
+// its own pinned host memory), and the device reaches it at the same
+// address.  Asking about the two ends alone would accept a range whose ends
+// lie in two allocations with unmapped memory between them.
+bool device_visible(const void *p, uint64_t n)
 {
     hipPointerAttribute_t a;
     if (hipPointerGetAttributes(&a, p) != hipSuccess) {
@@ -44,7 +46,15 @@ bool device_visible(const void *p)
         return false;
     }
     if (a.type != hipMemoryTypeHost && a.type != hipMemoryTypeDevice) return false;
-    return a.devicePointer == p;
+    if (a.devicePointer != p) return false;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess || !base) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uintptr_t b = (uintptr_t)base, q = (uintptr_t)p;
+    return q >= b && q - b <= size && n <= size - (q - b);
 }
 
 }  // namespace
@@ -58,8 +68,7 @@ extern "C" hc_status hc_copy(const void *d_src, void *d_dst, uint64_t n, void *s
     if (a < b + n && b < a + n) return HC_ERR_INVALID_ARG;  // overlapping ranges
     const uint8_t *s8 = static_cast<const uint8_t *>(d_src);
     uint8_t *d8 = static_cast<uint8_t *>(d_dst);
-    if (!device_visible(s8) || !device_visible(s8 + n - 1) || !device_visible(d8) || !device_visible(d8 + n - 1))
-        return HC_ERR_INVALID_ARG;
+    if (!device_visible(s8, n) || !device_visible(d8, n)) return HC_ERR_INVALID_ARG;
     const uint64_t nvec = n / 16;
     const uint64_t per_unroll = (uint64_t)kCopyThreads * kCopyUnroll;
     uint64_t groups = (nvec + per_unroll - 1) / per_unroll;

@@ -4,9 +4,10 @@
 //                  sub-histograms, one replica per lane of a wavefront
 //   k_count        length pass (section 2.1): bits of every tile of 4096 * QPT
 //                  symbols (a tile never crosses a block boundary)
-//   k_offsets      offset pass (section 2.1: "where the block starts and
-//                  ends"): each tile's bit position inside its block and each
-//                  block's byte offset in the stream, one work-group per stream
+//   k_offsets      offset pass (section 2.1: the table of where each block
+//                  begins): each tile's bit position inside its block and
+//                  each block's byte offset in the stream, one work-group per
+//                  stream
 //   k_encode       bit packing (section 2.1, Fig. 3-4): a tile's code words
 //                  OR-ed into LDS words, stored coalesced at the block's offset
 //                  in the stream with the header and zero pad
@@ -302,7 +303,7 @@ __device__ __forceinline__ void put_bits(uint64_t &acc, uint32_t &nacc, uint32_t
 // SIMD, as the packing pass.
 template <uint32_t QPT>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_count(JobList jl, uint32_t B, uint32_t tpb, uint32_t *tile_bits,
-                                                        uint16_t *thread_bits, uint32_t *err)
+                                                        uint16_t *thread_bits, uint32_t shape_len, uint32_t *err)
 {
     constexpr uint32_t kSyms = kQuadSyms * QPT;
     constexpr uint32_t kWords = kNumSym / 4;  // length words per replica
@@ -317,6 +318,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     }
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
+    if (tb->max_len > shape_len) {  // the same in every lane: the group leaves together
+        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+        return;
+    }
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
     const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
     const uint32_t s = tl.ts + kSyms * tid;
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(JobList jl, uint32_t B,
 template <bool kPacked, uint32_t FPS, uint32_t QPT>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_encode(
     JobList jl, uint32_t B, uint32_t tpb, const uint32_t *tile_pos, const uint16_t *thread_bits, uint32_t S,
-    uint32_t cpb, uint32_t lds_words, uint32_t *err)
+    uint32_t cpb, uint32_t lds_words, uint32_t shape_len, uint32_t *err)
 {
     constexpr uint32_t kSyms = kQuadSyms * QPT;  // symbols per thread
     constexpr bool kHanded = QPT >= 2;           // bit counts from the length pass
@@ -465,6 +470,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     }
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
+    if (tb->max_len > shape_len) {  // the same in every lane: the group leaves together
+        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+        return;
+    }
     if (kPacked) {
         s_packed[tid] = tb->enc_packed[tid];
     } else {
@@ -1166,7 +1175,7 @@ __device__ __forceinline__ v4u load_quad(const HC_G uint32_t *__restrict__ in32,
 // ring is left out (its LDS would hold the copy to 2 groups per CU).
 template <uint32_t R, uint32_t SPR, bool kLong, bool kCopyOnly = false>
 __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb,
-                                                             uint32_t *err)
+                                                             uint32_t shape_len, uint32_t *err)
 {
     constexpr uint32_t kRoundWords = R / 4;             // output words of a round
     constexpr uint32_t kLineRounds = 128 / R;           // rounds of one 128-byte output line
@@ -1194,6 +1203,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
     const bool fixed8 = tb->fixed_len == 8;  // uniform over the group: one job per group
+    // the tables must still be those the launch was shaped for (the same in every lane)
+    if (max_len > shape_len || (kCopyOnly && !(fixed8 && tb->count[8] == (uint32_t)kNumSym))) {
+        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+        return;
+    }
     if (!fixed8)
         for (uint32_t k = tid; k < (1u << K); k += kDecThreads) s_lut[k] = tb->lut[k];
     if (tid <= (uint32_t)kPackedMaxLen) {
@@ -1308,10 +1322,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         }
         return;
     }
-    if (kCopyOnly) {  // not reached: the host gives this launch complete 8-bit codes only
-        if (ok) report(err, HC_ERR_CORRUPT);
-        return;
-    }
+    if (kCopyOnly) return;  // not reached: the launch holds complete 8-bit codes only (checked above)
     if (!ok) return;
 
     // ---- input ring.  Stream words are counted from the 128-byte line that
@@ -1681,7 +1692,7 @@ __device__ __forceinline__ uint32_t put_sym(uint32_t e, uint32_t word, uint32_t 
 // (about 8 KiB of area per wave).
 template <uint32_t R, uint32_t SPR, bool kLong, uint32_t kLutB, uint32_t kChains>
 __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_per_eu(kLutB <= 10 ? 4 : 3))) void k_decode_stage(
-    JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb, uint32_t *err)
+    JobList jl, uint32_t B, uint32_t S_eff, uint32_t cpb, uint32_t shape_len, uint32_t *err)
 {
     constexpr uint32_t kThreads = kDecThreads / kChains;
     constexpr uint32_t kWaves = kThreads / 64;
@@ -1713,6 +1724,10 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
     HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)s_job.out;
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
+    if (max_len > shape_len) {  // the tables changed since the launch was shaped (the same in every lane)
+        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+        return;
+    }
     {
         // the table, 8 entries (16 bytes) per load
         const uint32_t nq = (1u << K) >= 8 ? (1u << K) / 8 : 1u;
@@ -2019,15 +2034,15 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t
     if (!(steps & kStepLengths))
         ;
     else if (qpt == 4)
-        k_count<4><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, err);
+        k_count<4><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, max_len, err);
     else if (qpt == 2)
-        k_count<2><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, err);
+        k_count<2><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, max_len, err);
     else
-        k_count<1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, err);
+        k_count<1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, max_len, err);
     // 2. offsets
     if (steps & kStepOffsets) k_offsets<<<dim3(jl.count), kOffThreads, 0, s>>>(jl, B, tpb, tile_bits, tile_pos, err);
     // 3. packing
-#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tile_pos, thread_bits, S, cpb, lds_words, err)
+#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tile_pos, thread_bits, S, cpb, lds_words, max_len, err)
     if (!(steps & kStepPack)) {
     } else if (!packed) {
         HC_ENC(false, 1, 1);
@@ -2084,7 +2099,7 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     const uint32_t cpb = with_index ? (B + S - 1) / S : 1;
     const dim3 grid((uint32_t)groups);
     if (complete8) {  // every job a complete 8-bit code: the copy form, no ring, no table
-        k_decode_ring<16, 4, false, true><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 4, false, true><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, max_len, err);
         return hipGetLastError();
     }
     // the table has 2^lut_bits entries, lut_bits = min(max_len, kLutBits) of the longest code
@@ -2095,9 +2110,9 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
 #define HC_STG(R, P, L, T)                                                                                       \
     do {                                                                                                          \
         if (S <= kStageMaxS / 2)                                                                                  \
-            k_decode_stage<R, P, L, T, 2><<<grid, kDecThreads / 2, 0, s>>>(jl, B, S_eff, cpb, err);               \
+            k_decode_stage<R, P, L, T, 2><<<grid, kDecThreads / 2, 0, s>>>(jl, B, S_eff, cpb, max_len, err);               \
         else                                                                                                      \
-            k_decode_stage<R, P, L, T, 1><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);                   \
+            k_decode_stage<R, P, L, T, 1><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, max_len, err);                   \
     } while (0)
         if (max_len <= 8)
             HC_STG(16, 4, false, 8);
@@ -2114,15 +2129,15 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
     }
     // a round of R symbols of <= 32 * 16 / R bits stays within one ring half (16 words)
     if (max_len <= 8)
-        k_decode_ring<16, 4, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 4, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, max_len, err);
     else if (max_len <= 10)
-        k_decode_ring<16, 3, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 3, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, max_len, err);
     else if (max_len <= (uint32_t)kLutBits)
-        k_decode_ring<16, 2, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 2, false><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, max_len, err);
     else if (max_len <= 16)
-        k_decode_ring<16, 2, true><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<16, 2, true><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, max_len, err);
     else if (max_len <= (uint32_t)kPackedMaxLen)  // 8 symbols of <= 24 bits: 6 words
-        k_decode_ring<8, 1, true><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, err);
+        k_decode_ring<8, 1, true><<<grid, kDecThreads, lut, s>>>(jl, B, S_eff, cpb, max_len, err);
     else
         k_decode<<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, err);
     return hipGetLastError();

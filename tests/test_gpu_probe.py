@@ -76,3 +76,25 @@ def test_copy_refusals(hc):
         hc.hc_copy(d[4:36], torch.zeros(32, dtype=torch.uint8, device="cuda"))  # misaligned
     with pytest.raises(hc.HcError):
         hc.hc_copy(d[:64], d[32:96])  # overlapping
+
+
+def test_copy_refuses_range_past_its_allocation(hc):
+    """A range that starts in an allocation and runs past its end is refused
+    on the host (nothing is launched), device or pinned host memory alike."""
+    import ctypes
+
+    d = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda")
+    d2 = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda")
+    h = torch.zeros(1 << 20, dtype=torch.uint8).pin_memory()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    big = 1 << 30  # far past any of these allocations
+    for src, dst in ((d, d2), (h, d2), (d, h)):
+        rc = hc._lib.hc_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), big, stream)
+        assert rc == hc.HC_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert int(d2.count_nonzero()) == 0
+    # the same buffers within their sizes copy
+    d[:4096] = 7
+    hc.hc_copy(d[:4096], h[:4096])
+    torch.cuda.synchronize()
+    assert bool((h[:4096] == 7).all())
