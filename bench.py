@@ -49,7 +49,7 @@ METRIC = "compress/decompress GB/s (uncompressed) and % HBM peak; batched p50/p9
 WORKLOAD = "mixed-4GiB-64x64MiB"
 # the device function each timed launch runs (rocprofv3 names)
 KERNEL_SYMBOL = {"k_hist": "k_hist", "k_count": "k_count", "k_offsets": "k_offsets", "k_encode": "k_encode",
-                 "k_decode": "k_decode_ring"}
+                 "k_decode": "k_decode_stage", "k_decode_copy": "k_decode_ring", "k_decode_table": "k_decode_stage"}
 
 
 def parse():
@@ -246,6 +246,130 @@ def kernel_times(w, torch, np, reps=20, warmup=3):
     return out
 
 
+def kind_kernel_times(w, synth, torch, np, reps=10, warmup=2):
+    """The same workload's segments of one kind at a time, through the
+    batched calls on that subset (same buffers): the encoder's three launches
+    and the decode launch of each kind, HIP events around every launch.  The
+    decode of the uniform segments (complete 8-bit codes) is the decoder's
+    copy launch, that of the others its table-decode launch, so this also
+    times the two launches of the whole workload's decode call apart."""
+    hc = w.hc
+    E = torch.cuda.Event
+    out = {}
+    for kind in synth.SEGMENT_KINDS:
+        segs = [t for t in range(w.nseg) if synth.mixed_kind(t) == kind]
+        if not segs:
+            continue
+        e_it, d_it = hc.make_items(len(segs)), hc.make_items(len(segs))
+        for j, t in enumerate(segs):
+            hc.set_item(e_it, j, x=w.xs(t), dcb=w.dcb[t], out=w.outs(t), block_off=w.off[t], sub_idx=w.subs(t))
+            hc.set_item(d_it, j, x=w.outs(t), n=w.seg, in_bytes=w.C[t], dcb=w.dcb[t], out=w.ys(t),
+                        block_off=w.off[t], sub_idx=w.subs(t))
+        steps = (("k_count", lambda: hc.hc_encode_lengths_batch(e_it, w.B, w.S, w.ws, w.err)),
+                 ("k_offsets", lambda: hc.hc_encode_offsets_batch(e_it, w.B, w.S, w.ws, w.err)),
+                 ("k_encode", lambda: hc.hc_encode_pack_batch(e_it, w.B, w.S, w.ws, w.err)),
+                 ("k_decode", lambda: hc.hc_decode_batch(d_it, w.B, w.S, w.ws, w.err)))
+        t = {k: [] for k, _ in steps}
+        for r in range(warmup + reps):
+            ev = {k: (E(enable_timing=True), E(enable_timing=True)) for k, _ in steps}
+            for k, fn in steps:
+                ev[k][0].record()
+                fn()
+                ev[k][1].record()
+            torch.cuda.synchronize()
+            if r >= warmup:
+                for k, _ in steps:
+                    t[k].append(ev[k][0].elapsed_time(ev[k][1]))
+        n = w.seg * len(segs)
+        C = sum(w.C[j] for j in segs)
+        side = (8 * (w.nb + 1) + 4 * w.nsub) * len(segs)
+        complete8 = all(bool(np.all(np.asarray(w.dcb[j].host.lengths) == 8)) for j in segs)
+        alg = {"k_count": 0 if complete8 else n, "k_offsets": 8 * (w.nb + 1) * len(segs),
+               "k_encode": n + C + side, "k_decode": C + n + side}
+        ms = {k: float(np.mean(v)) for k, v in t.items()}
+        out[kind] = {
+            "segments": len(segs), "bytes": n, "ratio": round(C / n, 5),
+            "max_len": max(int(w.dcb[j].max_len) for j in segs),
+            "decode_kernel": "k_decode_ring (copy form)" if complete8 else "k_decode_stage",
+            **{k: {"avg_ms": round(v, 4), "ms_per_GiB": round(v * (1 << 30) / n, 4),
+                   "GBps_alg": round(alg[k] / (v * 1e-3) / 1e9, 1) if alg[k] else None,
+                   "pct_hbm": round(100 * alg[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBPS, 1) if alg[k] else None}
+               for k, v in ms.items()},
+        }
+    return out
+
+
+def single_stream_bench(hc, synth, torch, np, name: str, S: int, reps: int = 20, warmup: int = 3):
+    """One buffer, one codebook: compress (counts, their read-back, the host
+    code build and table refresh, the three encode launches) and decompress
+    (the decode), timed per call; plus the header walk that rebuilds the
+    offset table of a stream kept without it.  Median and p10/p90 of 'reps'
+    calls after 'warmup'; the round trip is checked."""
+    spec = synth.WORKLOADS[name]
+    n, B = spec["n"], spec["block"]
+    seed = synth.derive_seed(spec["config_id"], 0)
+    x = synth.zipf_bytes_torch(n, spec["s"], seed) if n >= (64 << 20) else \
+        torch.from_numpy(synth.zipf_bytes(n, spec["s"], seed)).cuda()
+    nb = hc.num_blocks(n, B)
+    hist = torch.zeros(256, dtype=torch.int64, device="cuda")
+    hist_host = torch.zeros(256, dtype=torch.int64).pin_memory()
+    hc.hc_histogram(x, out=hist)
+    cb = hc.hc_build_codebook(hist.cpu().numpy().view(np.uint64))
+    dcb = hc.DeviceCodebook(cb)
+    cap = (hc.hc_encode_bound(n, B, cb.max_len) + 255) // 256 * 256
+    out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    off = torch.empty(nb + 1, dtype=torch.int64, device="cuda")
+    off2 = torch.empty(nb + 1, dtype=torch.int64, device="cuda")
+    sub = torch.empty(max(hc.hc_sub_index_entries(n, B, S), 1), dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(hc.hc_encode_workspace_bytes(n, B), 16), dtype=torch.uint8, device="cuda")
+    y = torch.empty(n, dtype=torch.uint8, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    E = torch.cuda.Event
+    tc, td, tw = [], [], []
+    for r in range(warmup + reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hc.hc_histogram(x, out=hist)
+        hist_host.copy_(hist, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        c = hc.hc_build_codebook(hist_host.numpy().view(np.uint64))
+        dcb.update(c)
+        hc.hc_encode_blocks(x, B, dcb, out, off, sub, S, ws, err)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        a, b = E(enable_timing=True), E(enable_timing=True)
+        a.record()
+        hc.hc_decode_blocks(out, int(off[nb].item()), n, B, dcb, off, sub, S, y, err)
+        b.record()
+        c1, c2 = E(enable_timing=True), E(enable_timing=True)
+        C = int(off[nb].item())
+        c1.record()
+        hc.hc_walk_blocks(out, C, nb, off2, err)
+        c2.record()
+        torch.cuda.synchronize()
+        if r >= warmup:
+            tc.append(1e3 * (t1 - t0))
+            td.append(a.elapsed_time(b))
+            tw.append(c1.elapsed_time(c2))
+    if hc.read_error(err):
+        raise hc.HcError(hc.read_error(err), name)
+    assert torch.equal(y, x), f"round trip failed ({name})"
+    assert torch.equal(off2, off), f"walk differs from the encoder's offsets ({name})"
+    side = 8 * (nb + 1) + 4 * hc.hc_sub_index_entries(n, B, S)
+    pct = lambda nbytes, ms: round(100 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 1)
+    q = lambda v: {"p10": round(float(np.percentile(v, 10)), 4), "p50": round(float(np.median(v)), 4),
+                   "p90": round(float(np.percentile(v, 90)), 4)}
+    mc, md = float(np.median(tc)), float(np.median(td))
+    return {
+        "workload": name, "bytes": n, "block_size": B, "sub_block": S, "ratio": round(C / n, 5),
+        "compress_ms": q(tc), "decompress_ms": q(td),
+        "compress_GBps": round(n / (mc * 1e-3) / 1e9, 1), "decompress_GBps": round(n / (md * 1e-3) / 1e9, 1),
+        "compress_pct_hbm": pct(3 * n + C + side, mc), "decompress_pct_hbm": pct(C + n + side, md),
+        "compress_note": "wall clock: counts + read-back + host code build + table refresh + encode",
+        "walk_ms": q(tw), "walk_blocks": nb,
+    }
+
+
 def cpu_baseline(w, oracle, np):
     """The oracle on segments 0..5 (two of each kind, 384 MiB) of the same
     workload: counts, code, block encode and strict decode.  Timed twice: on
@@ -266,7 +390,9 @@ def cpu_baseline(w, oracle, np):
             y = oracle.decode(s, x.size, B, L)
             assert np.array_equal(y, x)
 
-    cores = min(16, len(os.sched_getaffinity(0)))
+    # every core in the affinity mask, up to the 16 CPUs a one-GPU job is given on the GPU machine
+    available = len(os.sched_getaffinity(0))
+    cores = min(16, available)
 
     def block_parallel(pool):
         for x in xs:
@@ -294,6 +420,7 @@ def cpu_baseline(w, oracle, np):
         "value": round(nbytes / tp / 1e9, 4),
         "unit": "GB/s",
         "cores": cores,
+        "cores_available": available,
         "cpu": model,
         "kind": "oracle",
         "sample": f"segments 0-5 (uniform, skewed, fp32, twice) of the 4 GiB mixed workload, {nbytes >> 20} MiB, "
@@ -841,6 +968,10 @@ def main():
             "k_encode": n + C + off_bytes + sub_bytes,
             "k_decode": C + n + off_bytes + sub_bytes,
         }
+        kinds = kind_kernel_times(w, synth, torch, np)
+        if hc.read_error(w.err):
+            raise hc.HcError(hc.read_error(w.err), "per-kind timing")
+        assert torch.equal(w.y, w.x), "round trip failed (per-kind timing)"
         kavg = {k: float(np.mean(v)) for k, v in kt.items()}
         kernels = {
             k: {"avg_ms": round(kavg[k], 4), "p10_ms": round(float(np.percentile(kt[k], 10)), 4),
@@ -859,7 +990,23 @@ def main():
             "ratio": round(C / n, 5),
             "count_readback_ms": round(readback_ms, 3), "host_code_build_ms": round(build_ms, 3),
         }
-        dominant = max(KERNELS, key=lambda k: kavg[k])
+        # the decode call is two launches (complete 8-bit codes by the copy
+        # form, the rest by the table decoder): each is its own kernel here,
+        # timed on the kinds it serves
+        for name, kind_set in (("k_decode_copy", ("uniform",)), ("k_decode_table", ("skewed", "fp32"))):
+            ks = [kinds[k] for k in kind_set if k in kinds]
+            if ks:
+                ms = sum(k["k_decode"]["avg_ms"] for k in ks)
+                nbytes = sum(k["bytes"] for k in ks)
+                cbytes = sum(round(k["bytes"] * k["ratio"]) for k in ks)
+                side = sum(k["segments"] for k in ks) * (8 * (w.nb + 1) + 4 * w.nsub)
+                alg[name] = nbytes + cbytes + side
+                kavg[name] = ms
+                kernels[name] = {"avg_ms": round(ms, 4), "GBps_alg": round(gb(alg[name], ms), 1),
+                                 "pct_hbm": round(100 * gb(alg[name], ms) / HBM_PEAK_GBPS, 1),
+                                 "note": "timed on its own kinds' segments (" + ", ".join(kind_set) + ")"}
+        single = [k for k in kavg if k != "k_decode"]  # single launches: the decode call is split above
+        dominant = max(single, key=lambda k: kavg[k])
         launch_ms, per_launch = kavg[dominant], alg[dominant]
         achieved = per_launch / (launch_ms * 1e-3) / 1e9
         roofline = {
@@ -878,7 +1025,7 @@ def main():
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": WORKLOAD, "bytes": n, "segments": w.nseg, "block_size": B, "sub_block": S,
                        "parallelism": "single-gpu"},
-            "phases": phases, "kernels": kernels, "roofline": roofline,
+            "phases": phases, "kernels": kernels, "roofline": roofline, "kinds": kinds,
         }
         if args.selfsync:
             print("[bench] decode without the sub-block index", file=sys.stderr, flush=True)
@@ -888,6 +1035,11 @@ def main():
             line["cpu_baseline"] = cpu_baseline(w, __import__("oracle"), np)
         del w
         torch.cuda.empty_cache()
+        if not args.sweep:
+            print("[bench] single streams: 1 MiB and 256 MiB", file=sys.stderr, flush=True)
+            line["single_stream"] = [single_stream_bench(hc, synth, torch, np, nm, S)
+                                     for nm in ("zipf1.2-1MiB-B4KiB", "zipf1.1-256MiB-B64KiB")]
+            torch.cuda.empty_cache()
         if args.batched:
             print(f"[bench] batched: {args.batched} buffers", file=sys.stderr, flush=True)
             line["batched"] = batched_bench(hc, synth, torch, np, args.batched, B, S)
