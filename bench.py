@@ -66,9 +66,9 @@ def parse():
     ap.add_argument("--per-kind", action="store_true",
                     help="the same step on segments of one data kind at a time (uniform, skewed, fp32): "
                          "per-kernel time and GB/s of each kind, one JSON line each")
-    ap.add_argument("--batched", type=int, default=0, metavar="N",
-                    help="also measure N independent buffers (log-uniform 1 KiB-64 MiB, Zipf s in [0.8,1.6]): "
-                         "one launch per phase vs one buffer per launch")
+    ap.add_argument("--batched", type=int, default=10000, metavar="N",
+                    help="N independent buffers (log-uniform 1 KiB-64 MiB, Zipf s in [0.8,1.6]): one launch per "
+                         "phase, its graph replay, and one buffer per launch (0: skip)")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="also run the serving loop on N requests (50/50 compress/decompress, log-uniform "
                          "4 KiB-256 MiB, mixed data) against one request per launch: saturation GB/s of both, "
@@ -450,37 +450,69 @@ def _loguniform_sizes(rng, count, lo, hi):
     return [int(v) for v in np.exp(rng.uniform(np.log(lo), np.log(hi), size=count))]
 
 
-def batched_bench(hc, synth, torch, np, count: int, B: int, S: int):
-    """Independent buffers with their own codebooks: one batched launch per
-    phase against one buffer per launch, same buffers, same results."""
+def batched_bench(hc, synth, torch, np, count: int, B: int, S: int, reps: int = 5):
+    """Independent buffers with their own codebooks (sizes log-uniform in
+    1 KiB-64 MiB, Zipf s ~ U[0.8, 1.6]): one batched launch per phase, the
+    same batched calls replayed from a HIP graph, and one buffer per launch,
+    on the same buffers with the same results.  Inputs, streams and decoded
+    outputs live in three arenas; if the device cannot hold them all, the
+    batch keeps as many of the buffers (in order) as fit, and says so."""
+    asked = count
     rng = np.random.default_rng(synth.derive_seed(4, 0))
     sizes = _loguniform_sizes(rng, count, 1 << 10, 64 << 20)
+    s_of = [float(rng.uniform(0.8, 1.6)) for _ in range(count)]
+    r256 = lambda v: (v + 255) // 256 * 256
+    # inputs + streams at the loosest bound (codes of <= 16 bits: 2 bytes per
+    # symbol) + decoded outputs, with room to spare for the workspace
+    free = torch.cuda.mem_get_info()[0]
+    kept, need = 0, 0
+    for n in sizes:
+        step = r256(n) * 2 + r256(2 * n + 8 * hc.num_blocks(n, B) + 64)
+        if need + step > 0.85 * free:
+            break
+        need += step
+        kept += 1
+    sizes, s_of = sizes[:kept], s_of[:kept]
+    count = kept
+    base = [0]
+    for n in sizes:
+        base.append(base[-1] + r256(n))
     total = sum(sizes)
-    xs = []
+    x_arena = torch.empty(base[-1], dtype=torch.uint8, device="cuda")
+    xs = [x_arena[base[k]:base[k] + n] for k, n in enumerate(sizes)]
     for k, n in enumerate(sizes):
-        s_k = float(rng.uniform(0.8, 1.6))
-        xs.append(synth.zipf_bytes_torch(n, s_k, synth.derive_seed(4, k + 1)))
+        synth.zipf_bytes_torch(n, s_of[k], synth.derive_seed(4, k + 1), out=xs[k])
     hist = torch.empty((count, 256), dtype=torch.int64, device="cuda")
     items = hc.make_items(count)
     for k, x in enumerate(xs):
         hc.set_item(items, k, x=x, hist=hist[k])
     hws = torch.empty(max(hc.hc_batch_workspace_bytes(items, B), 256), dtype=torch.uint8, device="cuda")
     hc.hc_histogram_batch(items, hws)
-    h = hist.cpu().numpy().view(np.uint64)
-    dcbs = [hc.DeviceCodebook(hc.hc_build_codebook(h[k])) for k in range(count)]
-    outs = [torch.empty(hc.hc_encode_bound(n, B, d.max_len) + 256, dtype=torch.uint8, device="cuda")
-            for n, d in zip(sizes, dcbs)]
-    offs = [torch.empty(hc.num_blocks(n, B) + 1, dtype=torch.int64, device="cuda") for n in sizes]
-    subs = [torch.empty(max(hc.hc_sub_index_entries(n, B, S), 1), dtype=torch.int32, device="cuda") if S else None
-            for n in sizes]
-    ys = [torch.empty(n + 16, dtype=torch.uint8, device="cuda") for n in sizes]
+    cbset = hc.CodebookSet(count)
+    dcbs = cbset.build(hist.cpu().numpy().view(np.uint64))
+    caps = [r256(hc.hc_encode_bound(n, B, d.max_len)) for n, d in zip(sizes, dcbs)]
+    obase = [0]
+    for c in caps:
+        obase.append(obase[-1] + c)
+    o_arena = torch.empty(obase[-1], dtype=torch.uint8, device="cuda")
+    outs = [o_arena[obase[k]:obase[k] + caps[k]] for k in range(count)]
+    y_arena = torch.zeros(base[-1], dtype=torch.uint8, device="cuda")
+    ys = [y_arena[base[k]:base[k] + n] for k, n in enumerate(sizes)]
+    nbs = [hc.num_blocks(n, B) for n in sizes]
+    off_arena = torch.empty(sum(nb + 1 for nb in nbs), dtype=torch.int64, device="cuda")
+    ob = np.concatenate([[0], np.cumsum([nb + 1 for nb in nbs])])
+    offs = [off_arena[ob[k]:ob[k + 1]] for k in range(count)]
+    nsub = [max(hc.hc_sub_index_entries(n, B, S), 1) if S else 0 for n in sizes]
+    sb = np.concatenate([[0], np.cumsum(nsub)])
+    sub_arena = torch.empty(max(int(sb[-1]), 1), dtype=torch.int32, device="cuda")
+    subs = [sub_arena[sb[k]:sb[k + 1]] if S else None for k in range(count)]
     enc_items = hc.make_items(count)
     for k in range(count):
         hc.set_item(enc_items, k, x=xs[k], dcb=dcbs[k], out=outs[k], block_off=offs[k], sub_idx=subs[k])
     ws = torch.empty(hc.hc_batch_workspace_bytes(enc_items, B), dtype=torch.uint8, device="cuda")
     err = torch.zeros(1, dtype=torch.int32, device="cuda")
     hc.hc_encode_batch(enc_items, B, S, ws, err)
-    C = [int(o[-1].item()) for o in offs]
+    C = [int(v) for v in off_arena[torch.from_numpy(ob[1:] - 1).cuda()].cpu()]
     dec_items = hc.make_items(count)
     for k in range(count):
         hc.set_item(dec_items, k, x=outs[k], n=sizes[k], in_bytes=C[k], dcb=dcbs[k], out=ys[k], block_off=offs[k],
@@ -498,20 +530,22 @@ def batched_bench(hc, synth, torch, np, count: int, B: int, S: int):
             hc.hc_encode_blocks(xs[k], B, dcbs[k], outs[k], offs[k], subs[k], S, single_ws, err)
             hc.hc_decode_blocks(outs[k], C[k], sizes[k], B, dcbs[k], offs[k], subs[k], S, ys[k], err)
 
-    res = {}
-    for name, fn in (("batched", batched), ("plain", plain)):
+    def timed(fn, n_reps):
         fn()
         torch.cuda.synchronize()
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
+        ts = []
+        for _ in range(n_reps):
+            t0 = time.perf_counter()
             fn()
-        torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0) / reps
-    if hc.read_error(err):
-        raise hc.HcError(hc.read_error(err), "batched bench")
-    for k in range(count):
-        assert torch.equal(ys[k][: sizes[k]], xs[k]), f"buffer {k}"
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return ts
+
+    res = {"batched": timed(batched, reps)}
+    assert hc.read_error(err) == 0 and torch.equal(y_arena, x_arena), "batched round trip"
+    y_arena.zero_()
+    res["plain"] = timed(plain, max(2, reps // 2))
+    assert hc.read_error(err) == 0 and torch.equal(y_arena, x_arena), "plain round trip"
     # the batched calls captured once in a HIP graph, then replayed
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
@@ -519,29 +553,19 @@ def batched_bench(hc, synth, torch, np, count: int, B: int, S: int):
     torch.cuda.synchronize()
     with torch.cuda.graph(g, stream=side):
         batched()
-    for y in ys:
-        y.zero_()
+    y_arena.zero_()
     torch.cuda.synchronize()
-    g.replay()
-    torch.cuda.synchronize()
-    for k in range(count):
-        assert torch.equal(ys[k][: sizes[k]], xs[k]), f"buffer {k} (graph replay)"
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g.replay()
-    torch.cuda.synchronize()
-    res["graph"] = (time.perf_counter() - t0) / reps
-    if hc.read_error(err):
-        raise hc.HcError(hc.read_error(err), "batched bench (graph)")
-    return {
-        "buffers": count, "bytes": total, "sizes": "log-uniform 1 KiB-64 MiB", "data": "Zipf s~U[0.8,1.6]",
-        "batched_GBps": round(total / res["batched"] / 1e9, 2), "plain_GBps": round(total / res["plain"] / 1e9, 2),
-        "graph_GBps": round(total / res["graph"] / 1e9, 2),
-        "batched_ms": round(res["batched"] * 1e3, 3), "plain_ms": round(res["plain"] * 1e3, 3),
-        "graph_ms": round(res["graph"] * 1e3, 3),
-        "phases": "counts + encode + decode (codebooks fixed); graph: the same three batched calls replayed",
-    }
+    res["graph"] = timed(g.replay, reps)
+    assert hc.read_error(err) == 0 and torch.equal(y_arena, x_arena), "graph replay round trip"
+    out = {"buffers": count, "buffers_asked": asked, "bytes": total, "compressed_bytes": int(sum(C)), "sizes": "log-uniform 1 KiB-64 MiB",
+           "data": "Zipf s~U[0.8,1.6], one codebook per buffer", "block_size": B, "sub_block": S,
+           "phases": "counts + encode + decode per pass (codebooks resident); graph: the same three batched calls"}
+    for name, ts in res.items():
+        med = float(np.median(ts))
+        out[f"{name}_GBps"] = round(total / med / 1e9, 2)
+        out[f"{name}_ms"] = {"p10": round(1e3 * float(np.percentile(ts, 10)), 3), "p50": round(1e3 * med, 3),
+                             "p90": round(1e3 * float(np.percentile(ts, 90)), 3)}
+    return out
 
 
 def serve_bench(hc, synth, torch, np, count: int, B: int, S: int):

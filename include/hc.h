@@ -27,7 +27,9 @@
  *   - Pointers named d_* are device memory owned by the caller; h_* are host
  *     memory owned by the caller.  The library allocates memory only in
  *     hc_codebook_upload and hc_cbset_create (freed by hc_codebook_destroy and
- *     hc_cbset_destroy); no other call allocates or frees.  Calls that wait
+ *     hc_cbset_destroy), and the pinned staging ring of the batch calls' job
+ *     tables (see hc_histogram_batch: on first use and when a table outgrows
+ *     it); no other call allocates or frees.  Calls that wait
  *     on the host: hc_codebook_upload (its copy), hc_codebook_update and
  *     hc_cbset_build (the handle's or set's own previous table copy, normally
  *     long finished), hc_codebook_destroy and hc_cbset_destroy (the same, and
@@ -313,9 +315,13 @@ typedef struct {
 uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size);
 
 /* hc_histogram for every item (uses in, n, hist).  The item table is       */
-/* written into d_ws on 'stream' by small kernels that carry the items as  */
-/* arguments (no host-to-device copy, nothing waits for the stream);       */
-/* 'items' may be reused when the call returns.                            */
+/* written into d_ws on 'stream' as one asynchronous copy from a small     */
+/* ring of pinned host buffers the library keeps for all batch calls       */
+/* (allocated on first use, grown when a table outgrows its buffer; a      */
+/* buffer is reused once its copy has left it), or, while 'stream' is      */
+/* being captured into a graph, by small kernels that carry the items as   */
+/* arguments (a replay then needs no host buffer).  Nothing waits for the  */
+/* stream; 'items' may be reused when the call returns.                    */
 /* Errors returned: INVALID_ARG, NO_SPACE, HIP.                            */
 hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes, void *stream);
 

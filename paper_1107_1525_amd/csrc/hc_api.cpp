@@ -393,15 +393,90 @@ uint64_t job_table_bytes(uint32_t count)
 // (Kraft) every code has 8 bits and decoding is a byte-swapped copy.
 bool complete8(const hc_codebook &cb) { return cb.max_len == 8 && cb.nsym == 256; }
 
+// Pinned host staging for job tables: a small ring of buffers, each with the
+// event of its last copy, so that a table travels to the device as one
+// asynchronous copy and the host never waits for the stream (a copy from
+// pageable memory would).  A slot is reused only once its previous copy has
+// left it (normally long before: eight batch calls ago); a buffer grows when
+// a table outgrows it.
+class JobStaging {
+public:
+    static JobStaging &get()
+    {
+        static JobStaging st;
+        return st;
+    }
+    // Copies 'bytes' of 'fill' output to d_dst on s; returns a HIP error or hipSuccess.
+    template <typename Fill>
+    hipError_t copy(void *d_dst, size_t bytes, hipStream_t s, const Fill &fill)
+    {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        std::lock_guard<std::mutex> g(mu_);
+        Slot &sl = slots_[next_++ % kSlots];
+        if (sl.ev) {
+            e = hipEventSynchronize(sl.ev);  // its previous copy has left the buffer
+            if (e != hipSuccess) return e;
+        }
+        if (sl.dev != dev && sl.ev) {  // events and pinned buffers are made per device
+            (void)hipEventDestroy(sl.ev);
+            sl.ev = nullptr;
+        }
+        if (!sl.ev && (e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming)) != hipSuccess) return e;
+        sl.dev = dev;
+        if (sl.cap < bytes) {
+            if (sl.host) (void)hipHostFree(sl.host);
+            sl.host = nullptr;
+            sl.cap = 0;
+            size_t cap = 64 << 10;
+            while (cap < bytes) cap *= 2;
+            if ((e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault)) != hipSuccess) return e;
+            sl.cap = cap;
+        }
+        fill(static_cast<char *>(sl.host));
+        if ((e = hipMemcpyAsync(d_dst, sl.host, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        return hipEventRecord(sl.ev, s);
+    }
+
+private:
+    static constexpr int kSlots = 8;
+    struct Slot {
+        void *host = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        int dev = -1;
+    };
+    std::mutex mu_;
+    Slot slots_[kSlots];
+    uint64_t next_ = 0;
+};
+
 // Writes a job list (and the table of job start units) into the head of the
-// caller's workspace, in stream order and without waiting for the stream (a
-// copy from pageable host memory would wait for the stream's earlier work).
+// caller's workspace, in stream order and without waiting for the stream: as
+// one asynchronous copy from the pinned staging ring, or, while the stream is
+// being captured into a graph (a replay would copy whatever the staging
+// buffer then holds), as kernels that carry the jobs in their arguments.
 hc_status upload_jobs(std::vector<Job> &jobs, uint64_t total_units, void *ws, hipStream_t s, JobList *jl)
 {
     const uint32_t count = (uint32_t)jobs.size();
     Job *d_jobs = static_cast<Job *>(ws);
-    uint64_t *d_starts = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + align256((uint64_t)count * sizeof(Job)));
-    if (launch_put_jobs(jobs.data(), count, total_units, d_jobs, d_starts, s) != hipSuccess) return HC_ERR_HIP;
+    const uint64_t starts_at = align256((uint64_t)count * sizeof(Job));
+    uint64_t *d_starts = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + starts_at);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return HC_ERR_HIP;
+    if (cs != hipStreamCaptureStatusNone) {
+        if (launch_put_jobs(jobs.data(), count, total_units, d_jobs, d_starts, s) != hipSuccess) return HC_ERR_HIP;
+    } else {
+        const size_t bytes = starts_at + 8 * ((size_t)count + 1);
+        const hipError_t e = JobStaging::get().copy(ws, bytes, s, [&](char *h) {
+            memcpy(h, jobs.data(), (size_t)count * sizeof(Job));
+            uint64_t *st = reinterpret_cast<uint64_t *>(h + starts_at);
+            for (uint32_t k = 0; k < count; ++k) st[k] = jobs[k].unit_begin;
+            st[count] = total_units;
+        });
+        if (e != hipSuccess) return HC_ERR_HIP;
+    }
     jl->jobs = d_jobs;
     jl->starts = d_starts;
     jl->count = count;
