@@ -384,9 +384,9 @@ hc_status check_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, hc_cb_h
 // of every job and the total.
 uint64_t job_table_bytes(uint32_t count)
 {
-    // + room for the alignment of a second table: the decode splits its jobs
-    // into two launches, each with its own table
-    return align256((uint64_t)count * sizeof(Job)) + align256(8 * ((uint64_t)count + 1)) + 1024;
+    // + room for the alignment of the other tables: the encode and the decode
+    // split their jobs into launches by code length, each with its own table
+    return align256((uint64_t)count * sizeof(Job)) + align256(8 * ((uint64_t)count + 1)) + 4096;
 }
 
 // A complete 8-bit code: all 256 bytes coded, none longer than 8 bits, so
@@ -582,7 +582,8 @@ extern "C" uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t coun
     if (!items || block_size == 0) return 0;
     uint64_t nb = 0;
     for (uint32_t k = 0; k < count; ++k) nb += num_blocks(items[k].n, block_size);
-    return job_table_bytes(count) + encode_scratch_bound(nb, block_size);
+    // + the 256-byte alignment of each encode class's stretch of scratch
+    return job_table_bytes(count) + encode_scratch_bound(nb, block_size) + 256 * 3;
 }
 
 extern "C" hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes,
@@ -623,26 +624,36 @@ namespace {
 // lengths, bit 1: offsets, bit 2: packing).  Every step re-derives the same
 // job table from the items, so the steps may be issued as separate calls on
 // one stream, with the same workspace.
+// Encode launch classes by longest code: the kernels' variants (codes joined
+// two or one at a time between flushes, the tile shape, 64-bit codes) change
+// at these lengths, and a launch takes the variant of its longest code, so
+// each class gets launches of its own.  Codes of <= 8 bits share the class
+// of <= 16: joining four codes instead of two gains less than the extra
+// launches' tails cost (a complete 8-bit code is copied either way).
+int encode_class(uint32_t max_len)
+{
+    return max_len <= 16 ? 0 : max_len <= (uint32_t)kPackedMaxLen ? 1 : 2;
+}
+constexpr int kEncodeClasses = 3;
+
 hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                              void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream, uint32_t steps)
 {
     if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
-    std::vector<Job> jobs(count);
-    uint64_t tiles = 0;
-    uint32_t max_len = 1;
+    std::vector<Job> jobs[kEncodeClasses];
+    uint32_t max_len[kEncodeClasses] = {1, 1, 1};
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
         hc_status st = check_encode(it.in, it.n, block_size, it.cb, it.out, it.out_cap, it.block_off, it.sub_idx,
                                     sub_block);
         if (st != HC_OK) return st;
-        if (it.n > 0 && it.cb->host.max_len > max_len) max_len = it.cb->host.max_len;
     }
-    // one tile shape for the launch, from the longest code of any job
-    const uint32_t qpt = encode_qpt(block_size, max_len);
-    const uint32_t tpb = tiles_per_block(block_size, qpt);
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
+        const uint32_t L = it.n > 0 ? it.cb->host.max_len : 1u;
+        const int c = encode_class(L);
+        max_len[c] = L > max_len[c] ? L : max_len[c];
         Job j = empty_job();
         j.in = it.in;
         j.n = it.n;
@@ -650,22 +661,43 @@ hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t bloc
         j.out = it.out;
         j.block_off = it.block_off;
         j.sub_idx = it.sub_idx;
-        j.unit_begin = tiles;
-        tiles += num_blocks(it.n, block_size) * tpb;
-        jobs[k] = j;
+        jobs[c].push_back(j);
     }
-    if (tiles > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    // per class: its tile shape (from its longest code), its tiles numbered
+    // job after job, its job table, and its own stretch of the scratch
+    uint32_t qpt[kEncodeClasses];
+    uint64_t tiles[kEncodeClasses], scratch_at[kEncodeClasses + 1];
     const uint64_t head = job_table_bytes(count);
-    if (ws_bytes < head + encode_scratch_bytes(tiles, qpt)) return HC_ERR_NO_SPACE;
+    scratch_at[0] = 0;
+    for (int c = 0; c < kEncodeClasses; ++c) {
+        qpt[c] = encode_qpt(block_size, max_len[c]);
+        const uint32_t tpb = tiles_per_block(block_size, qpt[c]);
+        tiles[c] = 0;
+        for (Job &j : jobs[c]) {
+            j.unit_begin = tiles[c];
+            tiles[c] += num_blocks(j.n, block_size) * tpb;
+        }
+        if (tiles[c] > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+        scratch_at[c + 1] = scratch_at[c] + ((encode_scratch_bytes(tiles[c], qpt[c]) + 255) & ~uint64_t(255));
+    }
+    if (ws_bytes < head + scratch_at[kEncodeClasses]) return HC_ERR_NO_SPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    JobList jl;
-    hc_status st = upload_jobs(jobs, tiles, d_ws, s, &jl);
-    if (st != HC_OK) return st;
     if (steps & kStepOffsets)
         for (uint32_t k = 0; k < count; ++k)
             if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
-    void *scratch = static_cast<char *>(d_ws) + head;
-    return hip_status(launch_encode(jl, tiles, block_size, qpt, max_len, sub_block, scratch, d_err, s, steps));
+    char *table = static_cast<char *>(d_ws);
+    for (int c = 0; c < kEncodeClasses; ++c) {
+        if (jobs[c].empty() || tiles[c] == 0) continue;
+        JobList jl;
+        hc_status st = upload_jobs(jobs[c], tiles[c], table, s, &jl);
+        if (st != HC_OK) return st;
+        table += align256(jobs[c].size() * sizeof(Job)) + align256(8 * (jobs[c].size() + 1));
+        void *scratch = static_cast<char *>(d_ws) + head + scratch_at[c];
+        const hipError_t e = launch_encode(jl, tiles[c], block_size, qpt[c], max_len[c], sub_block, scratch, d_err, s,
+                                           steps);
+        if (e != hipSuccess) return HC_ERR_HIP;
+    }
+    return HC_OK;
 }
 
 }  // namespace
@@ -697,22 +729,32 @@ extern "C" hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, 
     return encode_batch_steps(items, count, block_size, sub_block, d_ws, ws_bytes, d_err, stream, kStepPack);
 }
 
+// Decode launch classes: complete 8-bit codes (the copy form), then the
+// table decoder's variants by longest code (<= 8, 10, 12, 16, 24 bits, and
+// longer), each launch taking the variant of its longest code.
+int decode_class(const hc_codebook &cb)
+{
+    if (complete8(cb)) return 0;
+    const uint32_t L = cb.max_len;
+    return L <= 8 ? 1 : L <= 10 ? 2 : L <= 12 ? 3 : L <= 16 ? 4 : L <= (uint32_t)kPackedMaxLen ? 5 : 6;
+}
+constexpr int kDecodeClasses = 7;
+
 extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                                      void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream)
 {
     if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
     if (ws_bytes < job_table_bytes(count)) return HC_ERR_NO_SPACE;
-    // two launches: streams with a complete 8-bit code take the copy form
-    // alone (no ring in LDS, more groups per CU); the rest the ring decoder
-    std::vector<Job> jobs[2];
-    uint64_t groups[2] = {0, 0};
-    uint32_t max_len = 1;
+    std::vector<Job> jobs[kDecodeClasses];
+    uint64_t groups[kDecodeClasses] = {0, 0, 0, 0, 0, 0, 0};
+    uint32_t max_len[kDecodeClasses] = {8, 1, 1, 1, 1, 1, 1};
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
         hc_status st = check_decode(it.in, it.in_bytes, it.n, it.cb, it.block_off, it.sub_idx, sub_block, it.out);
         if (st != HC_OK) return st;
-        const int w = (it.n > 0 && complete8(it.cb->host)) ? 0 : 1;
+        if (it.n == 0) continue;  // nothing to decode
+        const int c = decode_class(it.cb->host);
         Job j = empty_job();
         j.in = it.in;
         j.in_bytes = it.in_bytes;
@@ -721,22 +763,22 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
         j.out = it.out;
         j.block_off = it.block_off;
         j.sub_idx = it.sub_idx;
-        j.unit_begin = groups[w];
-        groups[w] += it.n ? decode_groups(it.n, block_size, sub_block) : 0;
-        if (w == 1 && it.n > 0 && it.cb->host.max_len > max_len) max_len = it.cb->host.max_len;
-        jobs[w].push_back(j);
+        j.unit_begin = groups[c];
+        groups[c] += decode_groups(it.n, block_size, sub_block);
+        if (it.cb->host.max_len > max_len[c]) max_len[c] = it.cb->host.max_len;
+        jobs[c].push_back(j);
     }
-    if (groups[0] > 0x7FFFFFFFull || groups[1] > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(d_ws);
-    for (int w = 0; w < 2; ++w) {
-        if (jobs[w].empty()) continue;
+    for (int c = 0; c < kDecodeClasses; ++c) {
+        if (jobs[c].empty()) continue;
+        if (groups[c] > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
         JobList jl;
-        hc_status st = upload_jobs(jobs[w], groups[w], ws, s, &jl);
+        hc_status st = upload_jobs(jobs[c], groups[c], ws, s, &jl);
         if (st != HC_OK) return st;
-        ws += align256(jobs[w].size() * sizeof(Job)) + align256(8 * (jobs[w].size() + 1));
-        const hipError_t e = launch_decode(jl, groups[w], block_size, w == 0 ? 8u : max_len, sub_block,
-                                           sub_block != 0, d_err, s, w == 0);
+        ws += align256(jobs[c].size() * sizeof(Job)) + align256(8 * (jobs[c].size() + 1));
+        const hipError_t e = launch_decode(jl, groups[c], block_size, max_len[c], sub_block, sub_block != 0, d_err, s,
+                                           c == 0);
         if (e != hipSuccess) return HC_ERR_HIP;
     }
     return HC_OK;
