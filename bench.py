@@ -57,8 +57,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--block", type=int, default=64 * 1024)
-    ap.add_argument("--sub-block", type=int, default=128)
+    ap.add_argument("--block", type=int, default=None,
+                    help="block size B (default: the autotuner's choice among 4/16/64/256 KiB)")
+    ap.add_argument("--sub-block", type=int, default=None,
+                    help="sub-block index stride S (default: the autotuner's choice)")
+    ap.add_argument("--tile-loads", type=int, default=None,
+                    help="encode tile loads per thread, 0 (the library's rule), 1, 2 or 4 (default: autotuned)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner: B = 64 KiB, S = 128, the library's tile rule unless given")
+    ap.add_argument("--tune-segments", type=int, default=12,
+                    help="64 MiB segments of the mixed workload the autotuner measures on (default 12)")
     ap.add_argument("--segments", type=int, default=64, help="number of 64 MiB segments (64 = 4 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true")
@@ -244,6 +252,49 @@ def kernel_times(w, torch, np, reps=20, warmup=3):
             for k in KERNELS:
                 out[k].append(ev[k][0].elapsed_time(ev[k][1]))
     return out
+
+
+TUNE_CANDIDATES = ([{"block_size": B, "sub_block": 128, "encode_tile_loads": q} for B in (4096, 16384, 65536, 262144)
+                    for q in (0, 2)] +
+                   [{"block_size": B, "sub_block": 1024, "encode_tile_loads": 0} for B in (16384, 65536, 262144)])
+
+
+def autotune_step(hc, synth, torch, nseg: int, steps: int = 3):
+    """The autotuner (paper_1107_1525_amd.autotune) over block size, index
+    stride and encode tile on nseg segments of the mixed workload: each
+    candidate's whole step (counts, codes, encode, decode) timed over
+    'steps' passes after one warm-up, its round trip checked.  Cached per
+    device and workload; the winner is what the timed run uses."""
+    from paper_1107_1525_amd.autotune import Autotuner, device_key
+
+    def measure(c):
+        hc.hc_set_tuning(c["encode_tile_loads"])
+        try:
+            w = Workload(hc, synth, torch, nseg, c["block_size"], c["sub_block"])
+            w.run(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            w.run(steps)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / steps
+            if hc.read_error(w.err):
+                raise hc.HcError(hc.read_error(w.err), "autotune")
+            if not torch.equal(w.y, w.x):
+                raise RuntimeError("round trip failed")
+            del w
+            return t
+        finally:
+            torch.cuda.empty_cache()
+            hc.hc_set_tuning(0)
+
+    tuner = Autotuner()
+    dev = device_key(torch)
+    key = f"{WORKLOAD}/sample{nseg}"
+    best, table, cached = tuner.tune(dev, key, TUNE_CANDIDATES, measure)
+    n = nseg * synth.WORKLOADS[WORKLOAD]["segment"]
+    return {"best": best, "device": dev, "workload": key, "cached": cached,
+            "table": [{**r["candidate"], **({"GBps": round(n / r["seconds"] / 1e9, 1)} if "seconds" in r
+                                            else {"error": r.get("error")})} for r in table]}
 
 
 def kind_kernel_times(w, synth, torch, np, reps=10, warmup=2):
@@ -922,6 +973,18 @@ def main():
     import paper_1107_1525_amd as hc
     import synth
 
+    # the timed run tunes its launch parameters unless any of them is given
+    # (the helper modes take the defaults)
+    tune_wanted = (args.block is None and args.sub_block is None and args.tile_loads is None and not args.no_tune
+                   and not (args.sweep or args.per_kind or args.traffic_summary or args.sq_table or args.copy_probe))
+
+    def fill_defaults():
+        args.block = 64 * 1024 if args.block is None else args.block
+        args.sub_block = 128 if args.sub_block is None else args.sub_block
+        args.tile_loads = 0 if args.tile_loads is None else args.tile_loads
+
+    if not tune_wanted:
+        fill_defaults()
     if args.traffic_summary:
         traffic_summary(args.traffic_summary, args.block, args.sub_block)
         return
@@ -936,6 +999,14 @@ def main():
         per_kind_bench(hc, synth, torch, np, args)
         return
 
+    tuned = None
+    if tune_wanted:
+        print(f"[bench] autotuning on {args.tune_segments} x 64 MiB", file=sys.stderr, flush=True)
+        tuned = autotune_step(hc, synth, torch, args.tune_segments)
+        args.block, args.sub_block = tuned["best"]["block_size"], tuned["best"]["sub_block"]
+        args.tile_loads = tuned["best"]["encode_tile_loads"]
+        fill_defaults()
+    hc.hc_set_tuning(args.tile_loads)
     configs = [(args.block, args.sub_block)]
     if args.sweep:
         configs = [(B, S) for B in (4096, 16384, 65536, 262144) for S in ((0,) if B == 4096 else (0, 512, 1024, 4096))]
@@ -1048,9 +1119,12 @@ def main():
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": WORKLOAD, "bytes": n, "segments": w.nseg, "block_size": B, "sub_block": S,
+                       "encode_tile_loads": args.tile_loads,
                        "parallelism": "single-gpu"},
             "phases": phases, "kernels": kernels, "roofline": roofline, "kinds": kinds,
         }
+        if tuned is not None:
+            line["autotune"] = tuned
         if args.selfsync:
             print("[bench] decode without the sub-block index", file=sys.stderr, flush=True)
             line["selfsync_decode"] = selfsync_bench(w, hc, torch, np, kavg["k_decode"])

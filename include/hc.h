@@ -98,6 +98,23 @@ const char *hc_status_str(int status);
 /* Library version: major * 10000 + minor * 100 + patch. */
 int hc_version(void);
 
+/* Launch parameters an autotuner may set for the whole process (a         */
+/* measurement helper, not part of the method): they change how the       */
+/* kernels cut the work, never a byte of any output.                       */
+typedef struct {
+    uint32_t encode_tile_loads; /* 16-byte loads per thread of an encode tile (a tile is
+                                   4096 times as many symbols): 0 = the library's rule
+                                   (4 for blocks of >= 16 Ki symbols and codes of <= 16
+                                   bits, 2 for blocks of >= 8 Ki, else 1); 1, 2 or 4 caps it */
+} hc_tuning;
+
+/* Sets the parameters for launches made after the call (a captured graph  */
+/* keeps the ones it was captured with).  Errors: INVALID_ARG (null, or    */
+/* encode_tile_loads not 0, 1, 2 or 4).                                    */
+hc_status hc_set_tuning(const hc_tuning *t);
+/* Reads the current parameters.  Errors: INVALID_ARG (null).              */
+hc_status hc_get_tuning(hc_tuning *t);
+
 /* ---------------------------------------------------------------------- */
 /* Symbol statistics (section 2: count every distinct symbol).            */
 /* d_hist[v] = number of bytes equal to v among d_in[0 .. n-1].           */

@@ -6,6 +6,7 @@ C++).  PyTorch supplies device memory and streams.  The functions keep the
 names of the C ABI in ``include/hc.h``:
 
     hc_histogram, hc_build_codebook, hc_codebook_from_lengths,
+    hc_set_tuning, hc_get_tuning,
     hc_codebook_upload, hc_codebook_update, hc_codebook_destroy, hc_encode_bound,
     hc_encode_workspace_bytes, hc_sub_index_entries, hc_encode_blocks, hc_encode_blocks_noalloc,
     hc_walk_blocks, hc_decode_blocks, hc_status_str, hc_batch_workspace_bytes,
@@ -64,6 +65,11 @@ class hc_codebook(ctypes.Structure):
         return np.ctypeslib.as_array(self.code).astype(np.uint64).copy()
 
 
+class hc_tuning(ctypes.Structure):
+    """Process-wide launch parameters (see hc_tuning in include/hc.h)."""
+    _fields_ = [("encode_tile_loads", ctypes.c_uint32)]
+
+
 class hc_item(ctypes.Structure):
     """One buffer of a batch call (see hc_item in include/hc.h)."""
     _fields_ = [
@@ -93,6 +99,8 @@ _st = ctypes.c_int
 _sigs = {
     "hc_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "hc_version": ([], ctypes.c_int),
+    "hc_set_tuning": ([ctypes.POINTER(hc_tuning)], _st),
+    "hc_get_tuning": ([ctypes.POINTER(hc_tuning)], _st),
     "hc_histogram": ([_vp, _u64, _vp, _vp], _st),
     "hc_build_codebook": ([_vp, ctypes.POINTER(hc_codebook)], _st),
     "hc_codebook_from_lengths": ([_vp, ctypes.POINTER(hc_codebook)], _st),
@@ -134,6 +142,17 @@ def hc_status_str(status: int) -> str:
 
 def hc_version() -> int:
     return _lib.hc_version()
+
+
+def hc_set_tuning(encode_tile_loads: int = 0) -> None:
+    t = hc_tuning(encode_tile_loads)
+    _check(_lib.hc_set_tuning(ctypes.byref(t)), "hc_set_tuning")
+
+
+def hc_get_tuning() -> dict:
+    t = hc_tuning()
+    _check(_lib.hc_get_tuning(ctypes.byref(t)), "hc_get_tuning")
+    return {"encode_tile_loads": int(t.encode_tile_loads)}
 
 
 def _check(status: int, what: str):

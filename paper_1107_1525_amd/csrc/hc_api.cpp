@@ -21,6 +21,10 @@ using namespace hc;
 
 namespace {
 
+// Launch parameters the autotuner may set (hc_set_tuning): the most 16-byte
+// loads per thread of an encode tile (0: the library's rule alone).
+std::atomic<uint32_t> g_tile_loads_cap{0};
+
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 bool valid_block_size(uint32_t B) { return B >= 16 && B <= (1u << 26) && (B % 16) == 0; }
@@ -127,6 +131,22 @@ extern "C" const char *hc_status_str(int status)
 }
 
 extern "C" int hc_version(void) { return 100; }
+
+extern "C" hc_status hc_set_tuning(const hc_tuning *t)
+{
+    if (!t) return HC_ERR_INVALID_ARG;
+    const uint32_t q = t->encode_tile_loads;
+    if (q != 0 && q != 1 && q != 2 && q != 4) return HC_ERR_INVALID_ARG;
+    g_tile_loads_cap.store(q, std::memory_order_relaxed);
+    return HC_OK;
+}
+
+extern "C" hc_status hc_get_tuning(hc_tuning *t)
+{
+    if (!t) return HC_ERR_INVALID_ARG;
+    t->encode_tile_loads = g_tile_loads_cap.load(std::memory_order_relaxed);
+    return HC_OK;
+}
 
 namespace {
 
@@ -327,6 +347,16 @@ extern "C" uint64_t hc_sub_index_entries(uint64_t n, uint32_t block_size, uint32
 
 namespace {
 
+// The encode tile shape for B and a longest code: the rule of encode_qpt,
+// capped by the tuning (to 1, 2 or 4 loads per thread).
+uint32_t tuned_qpt(uint32_t B, uint32_t max_len)
+{
+    uint32_t q = encode_qpt(B, max_len);
+    const uint32_t cap = g_tile_loads_cap.load(std::memory_order_relaxed);
+    while (cap && q > cap) q >>= 1;
+    return q;
+}
+
 Job empty_job()
 {
     Job j;
@@ -519,7 +549,7 @@ hc_status hc::encode_blocks_ws(const uint8_t *d_in, uint64_t n, uint32_t block_s
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (n == 0) return hip_status(launch_encode_empty(d_block_off, s));
     const uint64_t nb = num_blocks(n, block_size);
-    const uint32_t qpt = encode_qpt(block_size, cb->host.max_len);
+    const uint32_t qpt = tuned_qpt(block_size, cb->host.max_len);
     const uint64_t tiles = nb * tiles_per_block(block_size, qpt);
     if (!d_ws || !aligned(d_ws, 8)) return HC_ERR_INVALID_ARG;
     if (ws_bytes < encode_scratch_bytes(tiles, qpt)) return HC_ERR_NO_SPACE;
@@ -670,7 +700,7 @@ hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t bloc
     const uint64_t head = job_table_bytes(count);
     scratch_at[0] = 0;
     for (int c = 0; c < kEncodeClasses; ++c) {
-        qpt[c] = encode_qpt(block_size, max_len[c]);
+        qpt[c] = tuned_qpt(block_size, max_len[c]);
         const uint32_t tpb = tiles_per_block(block_size, qpt[c]);
         tiles[c] = 0;
         for (Job &j : jobs[c]) {
