@@ -34,6 +34,7 @@ oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -77,10 +78,10 @@ def parse():
     ap.add_argument("--batched", type=int, default=10000, metavar="N",
                     help="N independent buffers (log-uniform 1 KiB-64 MiB, Zipf s in [0.8,1.6]): one launch per "
                          "phase, its graph replay, and one buffer per launch (0: skip)")
-    ap.add_argument("--serve", type=int, default=0, metavar="N",
-                    help="also run the serving loop on N requests (50/50 compress/decompress, log-uniform "
+    ap.add_argument("--serve", type=int, default=5500, metavar="N",
+                    help="the serving loop on N requests (the first 500 warm-up; 50/50 compress/decompress, log-uniform "
                          "4 KiB-256 MiB, mixed data) against one request per launch: saturation GB/s of both, "
-                         "and p50/p99 latency of both under the same Poisson arrivals")
+                         "and p50/p99 latency of both under the same Poisson arrivals at 0.5 and 0.8 load (0: skip)")
     ap.add_argument("--host-pipeline", action="store_true",
                     help="also run the workload from pinned host memory through the chunked pipeline "
                          "(copy-in, coding, copy-out overlapped; 64 MiB chunks, one code each): "
@@ -619,87 +620,149 @@ def batched_bench(hc, synth, torch, np, count: int, B: int, S: int, reps: int = 
     return out
 
 
-def serve_bench(hc, synth, torch, np, count: int, B: int, S: int):
-    """The serving loop against the plain form (one request per launch, one
-    at a time), 50/50 compress/decompress of mixed data.  Two measurements:
-    saturation (every request waiting at the start: aggregate GB/s of each
-    form) and latency under load (the same Poisson arrivals, at a fraction
-    of the plain form's capacity, fed to both: p50/p99 of completion minus
-    arrival, queueing included for both)."""
+def serve_bench(hc, synth, torch, np, count: int, B: int, S: int, warmup: int = 500, check_every: int = 8):
+    """The serving loop (paper_1107_1525_amd.serve) against the plain form
+    (one request per launch, one at a time, first come first served): 50/50
+    compress/decompress, sizes log-uniform 4 KiB-256 MiB, each request's
+    bytes of one of the mixed workload's three kinds.  Saturation (every
+    request waiting at the start: aggregate GB/s of each form), then the
+    same Poisson arrivals at 0.5 and 0.8 of the plain form's capacity fed to
+    both: p50/p99 of completion minus arrival (queueing included), over the
+    requests after the first 'warmup'.  Arrival times start once the server
+    is built and every request queued; garbage collection is off inside
+    every timed loop of both forms.  A request's input is a slice of a
+    512 MiB pool of its kind (so the inputs need no more memory than the
+    pools); decompress requests are encoded beforehand, each its own
+    stream; results are dropped as they retire except every
+    'check_every'-th, which is checked (a round trip, and the same bytes as
+    the plain form)."""
     from paper_1107_1525_amd.serve import Request, Server, percentile
 
     rng = np.random.default_rng(synth.derive_seed(5, 0))
     sizes = _loguniform_sizes(rng, count, 4 << 10, 256 << 20)
-    kinds = rng.random(count) < 0.5
-    data, encs = [], []
-    for k, n in enumerate(sizes):
-        n4 = (n + 3) // 4 * 4
-        x = synth.segment_bytes_torch(synth.mixed_kind(k), n4, synth.derive_seed(5, k + 1))[:n]
-        data.append(x)
-        encs.append(None if kinds[k] else hc.compress(x, B, sub_block=S))
+    is_comp = rng.random(count) < 0.5
+    kinds = rng.integers(0, 3, size=count)
+    pool_n = 512 << 20
+    pools = [synth.segment_bytes_torch(k, pool_n, synth.derive_seed(5, 1 + i)) for i, k in enumerate(synth.SEGMENT_KINDS)]
+    offs = [int(rng.integers(0, (pool_n - n) // 256 + 1)) * 256 for n in sizes]
+    data = [pools[kinds[k]][offs[k]:offs[k] + sizes[k]] for k in range(count)]
+    encs = [None if is_comp[k] else hc.compress(data[k], B, sub_block=S) for k in range(count)]
     torch.cuda.synchronize()
     total = sum(sizes)
+    say = lambda m: print(f"[bench] serving: {m}", file=sys.stderr, flush=True)
+    say(f"{count} requests, {total / 1e9:.1f} GB, decompress inputs encoded")
 
     def plain_one(k):
-        if kinds[k]:
-            hc.compress(data[k], B, sub_block=S)
+        if is_comp[k]:
+            e = hc.compress(data[k], B, sub_block=S)
         else:
-            hc.decompress(encs[k])
+            e = hc.decompress(encs[k])
         torch.cuda.synchronize()
+        return e
 
-    def served(srv, arrivals):
+    checks = {}
+
+    def make_server():
+        def done(r):
+            lat[r.rid] = r.latency
+            if r.rid % check_every == 0:
+                checks[r.rid] = r.result
+            elif r.kind == "compress":
+                srv.recycle(r.result)
+            r.result = None
+        lat = {}
+        srv = Server(block_size=B, sub_block=S, hbm_budget=32 << 30, tables=4096, on_done=done)
+        return srv, lat
+
+    class quiet:
+        """No garbage collection inside a timed loop (a full collection of
+        this process's objects pauses it for tens of ms): collected before,
+        re-enabled after, for both forms alike."""
+
+        def __enter__(self):
+            gc.collect()
+            gc.disable()
+
+        def __exit__(self, *exc):
+            gc.enable()
+
+    def served(gaps):
+        """Serves every request, the k-th arriving sum(gaps[:k+1]) seconds
+        after the server is built and every request queued (setup is not
+        counted as waiting)."""
+        srv, lat = make_server()
         reqs = []
         for k in range(count):
-            if kinds[k]:
-                reqs.append(srv.submit(Request("compress", data=data[k], arrival=float(arrivals[k]))))
+            req = (Request("compress", data=data[k], arrival=float("inf")) if is_comp[k] else
+                   Request("decompress", encoded=encs[k], arrival=float("inf")))
+            reqs.append(srv.submit(req))  # rid == k
+        with quiet():
+            start = time.perf_counter() + 0.01
+            for r, a in zip(reqs, start + np.cumsum(gaps)):
+                r.arrival = float(a)
+            srv.run_until_idle()
+        assert len(lat) == count
+        return srv, [lat[k] for k in range(count)], start
+
+    def verify():
+        for k, res in checks.items():
+            if is_comp[k]:
+                ref = hc.compress(data[k], B, sub_block=S)
+                assert torch.equal(res.stream, ref.stream) and torch.equal(res.block_off, ref.block_off), k
+                assert torch.equal(hc.decompress(res), data[k]), k
             else:
-                reqs.append(srv.submit(Request("decompress", encoded=encs[k], arrival=float(arrivals[k]))))
-        srv.run_until_idle()
-        for k, r in enumerate(reqs):
-            if kinds[k]:
-                assert torch.equal(hc.decompress(r.result), data[k]), k
-            else:
-                assert torch.equal(r.result, data[k]), k
-        return reqs, srv
+                assert torch.equal(res, data[k]), k
+        n = len(checks)
+        checks.clear()
+        return n
 
     # saturation
-    for k in range(min(count, 8)):
+    for k in range(min(count, 16)):
         plain_one(k)  # warm-up
-    t0 = time.perf_counter()
-    for k in range(count):
-        plain_one(k)
-    plain_s = time.perf_counter() - t0
+    with quiet():
+        t0 = time.perf_counter()
+        for k in range(count):
+            plain_one(k)
+        plain_s = time.perf_counter() - t0
     plain_rate = total / plain_s
-    # the server and its resident code tables exist before the clock starts
-    srv = Server(block_size=B, sub_block=S, hbm_budget=32 << 30)
-    t0 = time.perf_counter()
-    reqs, _ = served(srv, np.full(count, t0))
-    served_s = max(r.completed for r in reqs) - t0
-
-    # latency under load: arrivals at rho x the plain form's capacity
-    rho = 0.8
-    gaps = rng.exponential(np.mean(sizes) / (rho * plain_rate), size=count)
-    lat_plain = []
-    start = time.perf_counter() + 0.01
-    arr = start + np.cumsum(gaps)
-    for k in range(count):  # first come, first served, one at a time
-        while time.perf_counter() < arr[k]:
-            pass
-        plain_one(k)
-        lat_plain.append(time.perf_counter() - arr[k])
-    srv = Server(block_size=B, sub_block=S, hbm_budget=32 << 30)
-    start = time.perf_counter() + 0.01
-    reqs, srv = served(srv, start + np.cumsum(gaps))
-    lat = [r.latency for r in reqs]
-    ms = lambda v: round(v * 1e3, 3)
-    return {
-        "requests": count, "bytes": total, "sizes": "log-uniform 4 KiB-256 MiB", "data": "mixed (uniform/skewed/fp32)",
+    say(f"plain at saturation {plain_rate / 1e9:.1f} GB/s")
+    srv, _, t0 = served(np.zeros(count))
+    served_s = time.perf_counter() - t0
+    checked = verify()
+    say(f"served at saturation {total / served_s / 1e9:.1f} GB/s ({checked} results checked)")
+    out = {
+        "requests": count, "warmup_requests": warmup, "bytes": total, "sizes": "log-uniform 4 KiB-256 MiB",
+        "mix": "50/50 compress/decompress", "data": "each request one of uniform/skewed/fp32 bytes",
+        "block_size": B, "sub_block": S, "hbm_budget": 32 << 30,
         "saturation_GBps": {"served": round(total / served_s / 1e9, 2), "plain": round(plain_rate / 1e9, 2)},
-        "offered_load": f"{rho} x plain capacity ({rho * plain_rate / 1e9:.2f} GB/s), Poisson",
-        "served_p50_ms": ms(percentile(lat, 50)), "served_p99_ms": ms(percentile(lat, 99)),
-        "plain_p50_ms": ms(percentile(lat_plain, 50)), "plain_p99_ms": ms(percentile(lat_plain, 99)),
-        "iterations": srv.iterations, "max_inflight_requests": srv.max_inflight_requests,
+        "loads": [],
     }
+    ms = lambda v: round(v * 1e3, 3)
+    for rho in (0.5, 0.8):
+        gaps = rng.exponential(np.mean(sizes) / (rho * plain_rate), size=count)
+        lat_plain = []
+        with quiet():
+            start = time.perf_counter() + 0.01
+            arr = start + np.cumsum(gaps)
+            for k in range(count):
+                while time.perf_counter() < arr[k]:
+                    pass
+                plain_one(k)
+                lat_plain.append(time.perf_counter() - arr[k])
+        say(f"plain at {rho} of capacity done")
+        srv, lat, _ = served(gaps)
+        checked += verify()
+        lp, ls = lat_plain[warmup:], lat[warmup:]
+        say(f"served at {rho} of capacity: p99 {percentile(ls, 99) * 1e3:.2f} ms (plain {percentile(lp, 99) * 1e3:.2f} ms)")
+        out["loads"].append({
+            "offered": f"{rho} x plain capacity ({rho * plain_rate / 1e9:.2f} GB/s), Poisson",
+            "served_p50_ms": ms(percentile(ls, 50)), "served_p99_ms": ms(percentile(ls, 99)),
+            "plain_p50_ms": ms(percentile(lp, 50)), "plain_p99_ms": ms(percentile(lp, 99)),
+            "iterations": srv.iterations, "max_inflight_requests": srv.max_inflight_requests,
+            "table_growths": srv.table_growths,
+        })
+    out["checked_results"] = checked
+    return out
 
 
 def kernel_name(full: str) -> str:

@@ -30,7 +30,7 @@ def _data(rng, k):
 def test_results_same_alone_and_in_the_mix(hc, oracle):
     from paper_1107_1525_amd.serve import Request, Server
 
-    B, S = 65536, 1024
+    B, S = 65536, 128
     rng = np.random.default_rng(7)
     alone = {}
     srv = Server(block_size=B, sub_block=S, hbm_budget=512 << 20)
@@ -58,22 +58,28 @@ def test_results_same_alone_and_in_the_mix(hc, oracle):
             assert torch.equal(r.result.block_off, alone[k].block_off), k
             assert torch.equal(r.result.sub_idx, alone[k].sub_idx), k
             assert torch.equal(hc.decompress(r.result), r.data), k
-            L = r.result.codebook.host.lengths
-            blk = r.data[:B].cpu().numpy()
-            s_or, _, _ = oracle.encode(blk, B, L, oracle.canonical_codes(L))
-            assert np.array_equal(r.result.stream[: s_or.size].cpu().numpy(), s_or), k
+            # the whole stream, offsets and index against the oracle's encoding
+            # of the request's data with the oracle's own code for it
+            x = r.data.cpu().numpy()
+            L, Cw = oracle.codebook(oracle.histogram(x))
+            assert np.array_equal(r.result.codebook.host.lengths, L), k
+            s_or, off_or, _ = oracle.encode(x, B, L, Cw)
+            assert np.array_equal(r.result.stream.cpu().numpy(), s_or), k
+            assert np.array_equal(r.result.block_off.cpu().numpy().view(np.uint64), off_or), k
+            assert np.array_equal(r.result.sub_idx.cpu().numpy().view(np.uint32)[: hc.hc_sub_index_entries(x.size, B, S)],
+                                  oracle.sub_index(x, B, S, L)), k
         else:
             assert torch.equal(r.result, alone[k]), k
 
 
 def test_budget_limits_concurrency(hc):
-    from paper_1107_1525_amd.serve import Request, Server, footprint
+    from paper_1107_1525_amd.serve import Request, Server, worst_footprint
 
-    B, S = 65536, 1024
+    B, S = 65536, 128
     rng = np.random.default_rng(8)
     xs = [_data(rng, k) for k in range(12)]
-    fps = [footprint(Request("compress", data=x), B, S) for x in xs]
-    srv = Server(block_size=B, sub_block=S, hbm_budget=max(fps) + 1)
+    fps = [worst_footprint(Request("compress", data=x), B, S) for x in xs]
+    srv = Server(block_size=B, sub_block=S, hbm_budget=max(fps) + 1, tables=4)
     for x in xs:
         srv.submit(Request("compress", data=x, arrival=0.0))
     peak = 0
@@ -82,3 +88,4 @@ def test_budget_limits_concurrency(hc):
         peak = max(peak, srv.in_use)
         assert srv.in_use <= srv.adm.budget
     assert len(srv.done) == 12 and peak <= srv.adm.budget
+    assert srv.table_growths == 8  # four resident tables, twelve results held

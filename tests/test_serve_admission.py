@@ -61,3 +61,24 @@ def test_rejects_oversized_and_waits_for_arrival():
         adm.submit(Req(101, 0.0))
     adm.submit(Req(10, 5.0))
     assert adm.admit(1.0) == [] and len(adm.admit(5.0)) == 1
+
+
+def test_adjust_and_hold():
+    Admission = load_admission()
+    adm = Admission(100)
+    for k in range(4):
+        adm.submit(Req(20, 0.0), worst=60)  # admitted on its estimate, could never need more than 60
+    with pytest.raises(ValueError):
+        adm.submit(Req(20, 0.0), worst=101)  # could never run
+    got = adm.admit(0.0)
+    assert len(got) == 4 and adm.in_use == 80
+    assert not adm.adjust(got[1], 30) and adm.in_use == 80 and got[1].footprint == 20  # the growth does not fit yet
+    assert adm.adjust(got[2], -5) and adm.in_use == 75 and got[2].footprint == 15  # a shorter code gives bytes back
+    adm.release(got[0])
+    assert adm.adjust(got[1], 30) and adm.in_use == 85 and got[1].footprint == 50
+    adm.submit(Req(5, 0.0))
+    assert adm.admit(0.0, hold=True) == []  # a batch waiting for its growth holds new admissions
+    assert len(adm.admit(0.0)) == 1
+    for r in got[1:]:
+        adm.release(r)
+    assert adm.in_use == 5
