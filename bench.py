@@ -29,7 +29,7 @@ oracle timed on a bounded sample of the same workload.
   python bench.py --batched N      # + N independent buffers, batched / graph / plain
   python bench.py --serve N        # + the serving loop against one request per launch
   python bench.py --host-pipeline  # + the workload from pinned host memory, PCIe included
-  python bench.py --selfsync       # + decode without the sub-block index
+  python bench.py --no-selfsync    # without the decodes that use no sub-block index
 """
 from __future__ import annotations
 
@@ -86,9 +86,9 @@ def parse():
                     help="also run the workload from pinned host memory through the chunked pipeline "
                          "(copy-in, coding, copy-out overlapped; 64 MiB chunks, one code each): "
                          "PCIe-inclusive compress / decompress GB/s beside plain pinned copy rates")
-    ap.add_argument("--selfsync", action="store_true",
-                    help="also decode the workload's streams without their sub-block index "
-                         "(hc_decode_blocks_selfsync, one call per stream) against the indexed decode")
+    ap.add_argument("--no-selfsync", action="store_true",
+                    help="skip the decodes of the workload's streams without their sub-block index "
+                         "(batched piece decoder and batched lane-per-block decode, beside the indexed one)")
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="turn rocprofv3 --pmc runs in DIR/{fetch,write,copy_fetch,copy_write} into "
                          "profiles/traffic_*.json (HBM bytes per launch of each codec kernel)")
@@ -798,6 +798,10 @@ def traffic_summary(root: str, B: int, S: int, out_dir: str = None):
     copy_name = next((k for k in cf if "k_probe_copy" in k), None) or max(cf, key=cf.get)
     f_scale = copy_bytes / (cf[copy_name] * 1024.0)
     w_scale = copy_bytes / (cw[copy_name] * 1024.0)
+    # cross-check of the fetch scale on the read probe (1 GiB read, nothing
+    # written, another access pattern): the same factor should come out
+    read_name = next((k for k in cf if "k_probe_read" in k), None)
+    f_scale_read = copy_bytes / (cf[read_name] * 1024.0) if read_name else None
     # a decode call runs two instances of k_decode_ring (the copy form for
     # complete 8-bit codes, the ring decoder for the rest), each once per
     # call: the instances of a kernel are summed, per call
@@ -809,6 +813,7 @@ def traffic_summary(root: str, B: int, S: int, out_dir: str = None):
         rec = {
             "kernel": k, "fetch_kib_per_dispatch": round(fetch[k], 1), "write_kib_per_dispatch": round(write.get(k, 0.0), 1),
             "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+            "fetch_scale_read_probe": None if f_scale_read is None else round(f_scale_read, 4),
             "bytes_per_launch": int(fetch[k] * 1024 * f_scale + write.get(k, 0.0) * 1024 * w_scale),
             "kernel_source_hash": kernel_source_hash(), "workload": WORKLOAD, "block_size": B, "sub_block": S,
             "copy_kernel": copy_name, "copy_bytes": copy_bytes,
@@ -964,31 +969,47 @@ def host_pipeline_bench(hc, synth, torch, np, nseg: int, B: int, S: int, reps: i
 
 
 def selfsync_bench(w, hc, torch, np, indexed_ms: float, reps: int = 5):
-    """The workload's streams decoded without their sub-block index
-    (hc_decode_blocks_selfsync: each block's pieces resynchronised on the code
-    boundaries), one call per stream, against the indexed batched decode; the
-    output is checked against the input."""
-    def run():
-        for t in range(w.nseg):
-            hc.hc_decode_blocks_selfsync(w.outs(t), w.C[t], w.seg, w.B, w.dcb[t], w.off[t], w.ys(t), w.err)
-
-    w.y.zero_()
-    run()
-    torch.cuda.synchronize()
-    if hc.read_error(w.err):
-        raise hc.HcError(hc.read_error(w.err), "selfsync decode")
-    assert torch.equal(w.y, w.x), "selfsync decode round trip failed"
+    """The workload's streams decoded without their sub-block index, each
+    form one batched call over all segments: hc_decode_batch_selfsync (each
+    block's pieces resynchronised on the code boundaries, one work-group per
+    block) against hc_decode_batch with S = 0 (one lane per block, the
+    paper's own decomposition) on the same streams, and the indexed decode
+    of the timed step.  Every output is checked against the input; HIP
+    events over 'reps' calls of each."""
+    items = hc.make_items(w.nseg)
+    for t in range(w.nseg):
+        hc.set_item(items, t, x=w.outs(t), n=w.seg, in_bytes=w.C[t], dcb=w.dcb[t], out=w.ys(t), block_off=w.off[t])
+    ws = torch.empty(max(hc.hc_batch_workspace_bytes(items, w.B), 256), dtype=torch.uint8, device="cuda")
+    forms = {
+        "selfsync_batched": lambda: hc.hc_decode_batch_selfsync(items, w.B, ws, w.err),
+        "lane_per_block_batched": lambda: hc.hc_decode_batch(items, w.B, 0, ws, w.err),
+    }
     E = torch.cuda.Event
-    s, e = E(enable_timing=True), E(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        run()
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / reps
-    return {"ms": round(ms, 3), "GBps": round(w.n / ms / 1e6, 1), "indexed_decode_ms": round(indexed_ms, 3),
-            "block_size": w.B, "streams": w.nseg,
-            "note": "decode without the sub-block index, one call per stream, HIP events over all calls"}
+    out = {}
+    for name, fn in forms.items():
+        w.y.zero_()
+        fn()
+        torch.cuda.synchronize()
+        if hc.read_error(w.err):
+            raise hc.HcError(hc.read_error(w.err), name)
+        assert torch.equal(w.y, w.x), f"{name}: round trip failed"
+        s, e = E(enable_timing=True), E(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        out[name] = {"ms": round(ms, 3), "GBps": round(w.n / ms / 1e6, 1)}
+    if hc.read_error(w.err):
+        raise hc.HcError(hc.read_error(w.err), "index-free decodes (timed)")
+    assert torch.equal(w.y, w.x), "index-free decodes: round trip failed (timed)"
+    out["indexed_batched"] = {"ms": round(indexed_ms, 3), "GBps": round(w.n / indexed_ms / 1e6, 1),
+                              "sub_block": w.S}
+    out.update({"block_size": w.B, "streams": w.nseg,
+                "note": "each form one batched call over every segment, HIP events over "
+                        f"{reps} calls; GBps of decoded bytes"})
+    return out
 
 
 def copy_probe(hc, torch, quiet=False):
@@ -1188,7 +1209,7 @@ def main():
         }
         if tuned is not None:
             line["autotune"] = tuned
-        if args.selfsync:
+        if not args.no_selfsync:
             print("[bench] decode without the sub-block index", file=sys.stderr, flush=True)
             line["selfsync_decode"] = selfsync_bench(w, hc, torch, np, kavg["k_decode"])
         if not args.no_cpu_baseline and not args.sweep:

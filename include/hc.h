@@ -327,8 +327,9 @@ typedef struct {
 
 /* Device workspace (256-byte aligned, caller-owned) any of the batch      */
 /* calls needs for these items and block size: the job table (room for    */
-/* two: the decode launches complete 8-bit codes apart), then the         */
-/* encoder's per-tile (and per-thread) bit counts and positions.          */
+/* one per launch: the encode and decode calls launch each code class     */
+/* apart), then the encoder's per-tile (and per-thread) bit counts and    */
+/* positions.                                                              */
 uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t block_size);
 
 /* hc_histogram for every item (uses in, n, hist).  The item table is       */
@@ -373,9 +374,10 @@ hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, uint32_t bl
                                void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
 /* hc_decode_blocks for every item (uses in, in_bytes, n, cb, block_off,   */
-/* sub_idx, out).  At most two launches: items whose code is a complete    */
-/* 8-bit code (all 256 bytes, 8 bits each) decode as a byte-swapped copy   */
-/* in a launch of their own; the rest in one launch of the table decoder. */
+/* sub_idx, out).  One launch per code class present: items whose code is  */
+/* a complete 8-bit code (all 256 bytes, 8 bits each) decode as a          */
+/* byte-swapped copy; the rest by the table decoder, one launch for each   */
+/* longest-code class (<= 8, <= 10, <= 12, <= 16, <= 24 bits, longer).     */
 /* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: CORRUPT,         */
 /* TABLE_CHANGED.                                                           */
 /* Graph capture: the batch calls choose kernel variants and shapes from   */
@@ -410,6 +412,19 @@ hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_s
 hc_status hc_decode_blocks_selfsync(const uint8_t *d_in, uint64_t in_bytes, uint64_t n, uint32_t block_size,
                                     hc_cb_handle cb, const uint64_t *d_block_off, uint8_t *d_out, uint32_t *d_err,
                                     void *stream);
+
+/* hc_decode_blocks_selfsync for every item (uses in, in_bytes, n, cb,     */
+/* block_off, out; sub_idx is not read): the blocks of all items in one    */
+/* launch per code class, one work-group per block.  Items whose code is a */
+/* complete 8-bit code decode as a byte-swapped copy (every code 8 bits:   */
+/* no index needed) in a launch of their own.  Workspace as               */
+/* hc_decode_batch (256-byte aligned device memory of at least            */
+/* hc_batch_workspace_bytes, holding the job tables; the call copies them */
+/* asynchronously from the library's pinned staging ring).                 */
+/* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: CORRUPT,         */
+/* TABLE_CHANGED (graph replays: as hc_decode_batch).                      */
+hc_status hc_decode_batch_selfsync(const hc_item *items, uint32_t count, uint32_t block_size, void *d_ws,
+                                   uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Streaming copy by a kernel of one work-group per CU, for moves between  */

@@ -11,7 +11,8 @@ names of the C ABI in ``include/hc.h``:
     hc_encode_workspace_bytes, hc_sub_index_entries, hc_encode_blocks, hc_encode_blocks_noalloc,
     hc_walk_blocks, hc_decode_blocks, hc_status_str, hc_batch_workspace_bytes,
     hc_histogram_batch, hc_encode_batch, hc_encode_lengths_batch, hc_encode_offsets_batch,
-    hc_encode_pack_batch, hc_decode_batch, hc_cbset_create,
+    hc_encode_pack_batch, hc_decode_batch, hc_decode_blocks_selfsync, hc_decode_batch_selfsync,
+    hc_cbset_create,
     hc_cbset_handle, hc_cbset_build, hc_cbset_destroy (as CodebookSet)
 
 and add two conveniences, ``compress`` and ``decompress``, that chain them.
@@ -126,6 +127,7 @@ _sigs = {
     "hc_encode_pack_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_decode_batch": ([ctypes.POINTER(hc_item), _u32, _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_decode_blocks_selfsync": ([_vp, _u64, _u64, _u32, _vp, _vp, _vp, _vp, _vp], _st),
+    "hc_decode_batch_selfsync": ([ctypes.POINTER(hc_item), _u32, _u32, _vp, _u64, _vp, _vp], _st),
     "hc_copy": ([_vp, _vp, _u64, _vp], _st),
     "hc_probe_copy": ([_vp, _vp, _u64, _vp], _st),
     "hc_probe_read": ([_vp, _u64, _vp, _vp], _st),
@@ -481,6 +483,12 @@ def hc_decode_batch(items, block_size: int, sub_block: int, ws: torch.Tensor, er
                     stream=None) -> None:
     _check(_lib.hc_decode_batch(items, len(items), block_size, sub_block, _ptr(ws), ws.numel(), _ptr(err),
                                 _stream(stream)), "hc_decode_batch")
+
+
+def hc_decode_batch_selfsync(items, block_size: int, ws: torch.Tensor, err: torch.Tensor, stream=None) -> None:
+    """Every item's blocks decoded without the sub-block index (items' sub_idx unused)."""
+    _check(_lib.hc_decode_batch_selfsync(items, len(items), block_size, _ptr(ws), ws.numel(), _ptr(err),
+                                         _stream(stream)), "hc_decode_batch_selfsync")
 
 
 def hc_probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:

@@ -374,9 +374,11 @@ JobList single(const Job &j)
     return jl;
 }
 
-uint64_t decode_groups(uint64_t n, uint32_t B, uint32_t S)
+// Work-groups of a decode launch: one lane per chunk (decode_chunk symbols).
+uint64_t decode_groups(uint64_t n, uint32_t B, uint32_t S, bool with_index, bool complete8)
 {
-    const uint64_t lanes = num_blocks(n, B) * (S ? (B + S - 1) / S : 1);
+    const uint32_t chunk = decode_chunk(B, S, with_index, complete8);
+    const uint64_t lanes = num_blocks(n, B) * ((B + chunk - 1) / chunk);
     return (lanes + kDecThreads - 1) / kDecThreads;
 }
 
@@ -580,7 +582,7 @@ extern "C" hc_status hc_decode_blocks(const uint8_t *d_in, uint64_t in_bytes, ui
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
     hc_status st = check_decode(d_in, in_bytes, n, cb, d_block_off, d_sub_idx, sub_block, d_out);
     if (st != HC_OK || n == 0) return st;
-    const uint64_t groups = decode_groups(n, block_size, sub_block);
+    const uint64_t groups = decode_groups(n, block_size, sub_block, d_sub_idx != nullptr, complete8(cb->host));
     if (groups > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
     Job j = empty_job();
     j.in = d_in;
@@ -601,9 +603,17 @@ extern "C" hc_status hc_decode_blocks_selfsync(const uint8_t *d_in, uint64_t in_
     if (!valid_block_size(block_size)) return HC_ERR_INVALID_ARG;
     hc_status st = check_decode(d_in, in_bytes, n, cb, d_block_off, nullptr, 0, d_out);
     if (st != HC_OK || n == 0) return st;
-    if (num_blocks(n, block_size) > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
-    return hip_status(launch_decode_sync(d_in, in_bytes, n, block_size, cb->d_tables, cb->host.max_len, d_block_off,
-                                         d_out, d_err, static_cast<hipStream_t>(stream)));
+    const uint64_t nb = num_blocks(n, block_size);
+    if (nb > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+    Job j = empty_job();
+    j.in = d_in;
+    j.in_bytes = in_bytes;
+    j.n = n;
+    j.tb = cb->d_tables;
+    j.out = d_out;
+    j.block_off = const_cast<uint64_t *>(d_block_off);
+    return hip_status(launch_decode_sync(single(j), nb, block_size, cb->host.max_len, d_err,
+                                         static_cast<hipStream_t>(stream)));
 }
 
 // ---------------------------------------------------------------------- batches
@@ -794,7 +804,7 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
         j.block_off = it.block_off;
         j.sub_idx = it.sub_idx;
         j.unit_begin = groups[c];
-        groups[c] += decode_groups(it.n, block_size, sub_block);
+        groups[c] += decode_groups(it.n, block_size, sub_block, sub_block != 0, c == 0);
         if (it.cb->host.max_len > max_len[c]) max_len[c] = it.cb->host.max_len;
         jobs[c].push_back(j);
     }
@@ -809,6 +819,52 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
         ws += align256(jobs[c].size() * sizeof(Job)) + align256(8 * (jobs[c].size() + 1));
         const hipError_t e = launch_decode(jl, groups[c], block_size, max_len[c], sub_block, sub_block != 0, d_err, s,
                                            c == 0);
+        if (e != hipSuccess) return HC_ERR_HIP;
+    }
+    return HC_OK;
+}
+
+extern "C" hc_status hc_decode_batch_selfsync(const hc_item *items, uint32_t count, uint32_t block_size, void *d_ws,
+                                              uint64_t ws_bytes, uint32_t *d_err, void *stream)
+{
+    if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
+    if (!valid_block_size(block_size)) return HC_ERR_INVALID_ARG;
+    if (ws_bytes < job_table_bytes(count)) return HC_ERR_NO_SPACE;
+    // the classes of hc_decode_batch: complete 8-bit codes by the copy form
+    // (which needs no index), the others by the piece decoder, one launch per
+    // class (its payload copy sized for the class's longest code)
+    std::vector<Job> jobs[kDecodeClasses];
+    uint64_t units[kDecodeClasses] = {0, 0, 0, 0, 0, 0, 0};
+    uint32_t max_len[kDecodeClasses] = {8, 1, 1, 1, 1, 1, 1};
+    for (uint32_t k = 0; k < count; ++k) {
+        const hc_item &it = items[k];
+        hc_status st = check_decode(it.in, it.in_bytes, it.n, it.cb, it.block_off, nullptr, 0, it.out);
+        if (st != HC_OK) return st;
+        if (it.n == 0) continue;  // nothing to decode
+        const int c = decode_class(it.cb->host);
+        Job j = empty_job();
+        j.in = it.in;
+        j.in_bytes = it.in_bytes;
+        j.n = it.n;
+        j.tb = it.cb->d_tables;
+        j.out = it.out;
+        j.block_off = it.block_off;
+        j.unit_begin = units[c];
+        units[c] += c == 0 ? decode_groups(it.n, block_size, 0, false, true) : num_blocks(it.n, block_size);
+        if (it.cb->host.max_len > max_len[c]) max_len[c] = it.cb->host.max_len;
+        jobs[c].push_back(j);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(d_ws);
+    for (int c = 0; c < kDecodeClasses; ++c) {
+        if (jobs[c].empty()) continue;
+        if (units[c] > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
+        JobList jl;
+        hc_status st = upload_jobs(jobs[c], units[c], ws, s, &jl);
+        if (st != HC_OK) return st;
+        ws += align256(jobs[c].size() * sizeof(Job)) + align256(8 * (jobs[c].size() + 1));
+        const hipError_t e = c == 0 ? launch_decode(jl, units[c], block_size, 8, 0, false, d_err, s, true)
+                                    : launch_decode_sync(jl, units[c], block_size, max_len[c], d_err, s);
         if (e != hipSuccess) return HC_ERR_HIP;
     }
     return HC_OK;

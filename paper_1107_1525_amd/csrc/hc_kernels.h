@@ -42,6 +42,17 @@ struct JobList {
 };
 
 inline uint64_t num_blocks(uint64_t n, uint32_t B) { return (n + B - 1) / B; }
+// Symbols of a decode lane's chunk: the sub-block stride S with an index;
+// without one, kCopyChunkSyms for a complete 8-bit code (every code has 8
+// bits, so chunk c of a block starts at payload bit 8 * S_eff * c and needs
+// no index), else the whole block.
+constexpr uint32_t kCopyChunkSyms = 128;
+inline uint32_t decode_chunk(uint32_t B, uint32_t S, bool with_index, bool complete8)
+{
+    if (with_index) return S;
+    if (complete8) return B < kCopyChunkSyms ? B : kCopyChunkSyms;
+    return B;
+}
 // Loads (16 symbols each) per encode thread: a tile is qpt * 4096 symbols.
 // Large tiles give each work-group more bytes to pack per fixed set-up cost
 // (tables, the tile's position, the next tile's first symbols); they need
@@ -99,9 +110,10 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t
 hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s);
 hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64_t *block_off,
                        uint32_t *err, hipStream_t s);
-// Decode without the sub-block index: one work-group per block (grid = nb).
-hipError_t launch_decode_sync(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
-                              uint32_t max_len, const uint64_t *block_off, uint8_t *out, uint32_t *err, hipStream_t s);
+// Decode without the sub-block index: one work-group per block of every job
+// (grid = blocks, the jobs' total; max_len: their longest code).
+hipError_t launch_decode_sync(const JobList &jl, uint64_t blocks, uint32_t B, uint32_t max_len, uint32_t *err,
+                              hipStream_t s);
 // complete8: every job has a complete 8-bit code (all 256 bytes coded with 8
 // bits), decoded by the copy form alone.
 hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_t max_len, uint32_t S,

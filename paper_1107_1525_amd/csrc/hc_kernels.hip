@@ -1065,11 +1065,13 @@ __device__ __forceinline__ void sync_block(Ptr src, uint32_t nwords, uint32_t hd
     for (; k < c; ++k) dst[k] = (uint8_t)next();
 }
 
-// stage_words: the LDS words the launch gives the payload copy (a block whose
-// payload is longer is read from global memory)
-__global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in32_, uint64_t in_bytes, uint64_t n,
-                                                               uint32_t B, const DevTables *tb_, const uint64_t *off_,
-                                                               uint8_t *out_, uint32_t stage_words, uint32_t *err)
+// Work-group u decodes block u - unit_begin of the job that owns unit u (one
+// unit per block: a batch of streams is one launch).  stage_words: the LDS
+// words the launch gives the payload copy (a block whose payload is longer
+// is read from global memory); shape_len: the longest code the launch was
+// shaped for.
+__global__ __launch_bounds__(kSyncThreads) void k_decode_sync(JobList jl, uint32_t B, uint32_t stage_words,
+                                                               uint32_t shape_len, uint32_t *err)
 {
     extern __shared__ uint32_t s_pay[];
     __shared__ uint16_t s_lut[1 << kLutBits];
@@ -1079,14 +1081,25 @@ __global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in
     __shared__ uint32_t s_sorted[kNumSym];
     __shared__ uint64_t s_end[kSyncThreads];  // where lane j's codes end
     __shared__ uint32_t s_scan[kSyncThreads / 64];
+    __shared__ Job s_job;
 
-    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)tb_;
-    const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)in32_;
-    const HC_G uint64_t *__restrict__ off = (const HC_G uint64_t *)off_;
-    HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)out_;
     const uint32_t tid = threadIdx.x;
+    if (tid < 64) {
+        const uint32_t k = wave_job_of_unit(jl, blockIdx.x);
+        if (tid == 0) s_job = job_at(jl, k);
+    }
+    __syncthreads();
+    const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
+    const HC_G uint32_t *__restrict__ in32 = (const HC_G uint32_t *)s_job.in;
+    const HC_G uint64_t *__restrict__ off = (const HC_G uint64_t *)s_job.block_off;
+    HC_G uint8_t *__restrict__ out = (HC_G uint8_t *)s_job.out;
+    const uint64_t in_bytes = s_job.in_bytes, n = s_job.n;
     const uint32_t K = tb->lut_bits;
     const uint32_t max_len = tb->max_len;
+    if (max_len > shape_len) {  // the tables changed since the launch was shaped (the same in every lane)
+        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+        return;
+    }
     for (uint32_t k = tid; k < (1u << K); k += kSyncThreads) s_lut[k] = tb->lut[k];
     for (uint32_t k = tid; k <= (uint32_t)kMaxLen; k += kSyncThreads) {
         s_first[k] = tb->first[k];
@@ -1098,7 +1111,7 @@ __global__ __launch_bounds__(kSyncThreads) void k_decode_sync(const uint32_t *in
     // the block and its checks (the same values in every lane: the group
     // leaves together or not at all)
     const uint64_t nb = num_blocks_dev(n, B);
-    const uint64_t i = blockIdx.x;
+    const uint64_t i = blockIdx.x - s_job.unit_begin;
     const uint64_t blk_start = i * (uint64_t)B;
     const uint32_t cnt = (uint32_t)(n - blk_start < B ? n - blk_start : B);
     const uint64_t o = off[i], o1 = off[i + 1];
@@ -1257,6 +1270,9 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         if (sub_idx) {
             p0 = sub_idx[i * cpb + c];
             if (s1 < cnt) p1 = sub_idx[i * cpb + c + 1];
+        } else if (fixed8) {  // chunks of a code whose lengths are all 8: at bit 8 s0 without an index
+            p0 = 8ull * s0;
+            if (s1 < cnt) p1 = 8ull * s1;
         }
         if (p0 > p1 || p1 > hdr) {
             report(err, HC_ERR_CORRUPT);
@@ -2078,16 +2094,14 @@ hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_decode_sync(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t B, const DevTables *tb,
-                              uint32_t max_len, const uint64_t *block_off, uint8_t *out, uint32_t *err, hipStream_t s)
+hipError_t launch_decode_sync(const JobList &jl, uint64_t blocks, uint32_t B, uint32_t max_len, uint32_t *err,
+                              hipStream_t s)
 {
-    const uint64_t nb = num_blocks(n, B);
-    if (nb == 0) return hipSuccess;
+    if (blocks == 0) return hipSuccess;
     // the longest payload a block can have (B codes of max_len bits), up to the LDS copy's limit
     const uint64_t need = ((uint64_t)B * max_len + 31) / 32;
     const uint32_t stage = (uint32_t)(need < kSyncStageWords ? need : kSyncStageWords);
-    k_decode_sync<<<dim3((uint32_t)nb), kSyncThreads, (size_t)stage * 4, s>>>(
-        (const uint32_t *)in, in_bytes, n, B, tb, block_off, out, stage, err);
+    k_decode_sync<<<dim3((uint32_t)blocks), kSyncThreads, (size_t)stage * 4, s>>>(jl, B, stage, max_len, err);
     return hipGetLastError();
 }
 
@@ -2095,8 +2109,8 @@ hipError_t launch_decode(const JobList &jl, uint64_t groups, uint32_t B, uint32_
                          bool with_index, uint32_t *err, hipStream_t s, bool complete8)
 {
     if (groups == 0) return hipSuccess;
-    const uint32_t S_eff = with_index ? S : B;
-    const uint32_t cpb = with_index ? (B + S - 1) / S : 1;
+    const uint32_t S_eff = decode_chunk(B, S, with_index, complete8);
+    const uint32_t cpb = (B + S_eff - 1) / S_eff;
     const dim3 grid((uint32_t)groups);
     if (complete8) {  // every job a complete 8-bit code: the copy form, no ring, no table
         k_decode_ring<16, 4, false, true><<<grid, kDecThreads, 0, s>>>(jl, B, S_eff, cpb, max_len, err);

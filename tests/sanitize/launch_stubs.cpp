@@ -23,8 +23,7 @@ hipError_t launch_walk(const uint8_t *, uint64_t, uint64_t, uint64_t *, uint32_t
 {
     return hipErrorInvalidValue;
 }
-hipError_t launch_decode_sync(const uint8_t *, uint64_t, uint64_t, uint32_t, const DevTables *, uint32_t,
-                              const uint64_t *, uint8_t *, uint32_t *, hipStream_t)
+hipError_t launch_decode_sync(const JobList &, uint64_t, uint32_t, uint32_t, uint32_t *, hipStream_t)
 {
     return hipErrorInvalidValue;
 }
