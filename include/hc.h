@@ -361,8 +361,9 @@ hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_s
 /* from the second to the third, and for tiles of more than 4096 symbols  */
 /* the bit count of each of the tile's 256 threads from the first to the  */
 /* third).  Together they equal hc_encode_batch.                           */
-/*   lengths: per tile of the input, the sum of its code lengths;           */
-/*            in *d_err: SYMBOL_ABSENT.                                    */
+/*   lengths: per tile of the input, the sum of its code lengths (items    */
+/*            with a complete 8-bit code are left out: the offsets step    */
+/*            counts 8 bits a symbol for them); in *d_err: SYMBOL_ABSENT.  */
 /*   offsets: block_off of every item (C = block_off[nb]);                  */
 /*            in *d_err: BLOCK_OVERFLOW.                                   */
 /*   pack:    the stream (headers, code words, zero pad) and sub_idx.      */
@@ -383,10 +384,10 @@ hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, uint32_t bl
 /* Graph capture: the batch calls choose kernel variants and shapes from   */
 /* every item's code (longest code, complete 8-bit code or not) when they  */
 /* are called.  A captured graph therefore stays valid only while no       */
-/* item's longest code grows and no complete 8-bit code of a decode stops  */
-/* being one; the kernels of a replay that meet such tables leave at once  */
-/* and report TABLE_CHANGED in *d_err (outputs unspecified, as after any   */
-/* error); shorter codes are fine.                                         */
+/* item's longest code grows and no complete 8-bit code stops being one    */
+/* (encode and decode launch them apart); the kernels of a replay that     */
+/* meet such tables leave at once and report TABLE_CHANGED in *d_err       */
+/* (outputs unspecified, as after any error); shorter codes are fine.      */
 hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 

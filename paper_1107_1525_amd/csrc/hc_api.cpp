@@ -484,36 +484,146 @@ private:
     uint64_t next_ = 0;
 };
 
-// Writes a job list (and the table of job start units) into the head of the
-// caller's workspace, in stream order and without waiting for the stream: as
-// one asynchronous copy from the pinned staging ring, or, while the stream is
-// being captured into a graph (a replay would copy whatever the staging
-// buffer then holds), as kernels that carry the jobs in their arguments.
-hc_status upload_jobs(std::vector<Job> &jobs, uint64_t total_units, void *ws, hipStream_t s, JobList *jl)
+// Side by side launches of one call's classes.  A batch call's code classes
+// are independent launches; in stream order a memory-bound one (the copy of
+// complete 8-bit codes) and a latency-bound one (the table decoder, the
+// packing of short codes) leave each other's idle resources unused.  Fork
+// hands the caller's stream and up to kSideStreams library-owned streams
+// (non-blocking, default priority, one set per device, created on first
+// use) that wait for all the caller's stream holds; join makes the caller's
+// stream wait for all of them again, so the call stays one step in the
+// caller's stream order.  Not used while the stream is captured into a
+// graph (a forked stream would stay in the capture): the launches then run
+// in stream order.  One call forks at a time (the events are shared).
+class SideStreams {
+public:
+    static constexpr int kSideStreams = 3;
+
+    static SideStreams &get()
+    {
+        static SideStreams st;
+        return st;
+    }
+
+    // Streams for 'want' launches: out[0] = s, out[1..] side streams (fewer
+    // when s is being captured or on any error: then every entry is s).
+    // Holds the fork lock until join.
+    void fork(hipStream_t s, int want, hipStream_t *out)
+    {
+        for (int k = 0; k < want; ++k) out[k] = s;
+        forked_ = 0;
+        mu_.lock();
+        if (want < 2) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
+        Dev &d = dev_[dev];
+        if (!d.ready) {
+            for (int k = 0; k < kSideStreams; ++k)
+                if (hipStreamCreateWithFlags(&d.side[k], hipStreamNonBlocking) != hipSuccess ||
+                    hipEventCreateWithFlags(&d.joined[k], hipEventDisableTiming) != hipSuccess)
+                    return;
+            if (hipEventCreateWithFlags(&d.start, hipEventDisableTiming) != hipSuccess) return;
+            d.ready = true;
+        }
+        if (hipEventRecord(d.start, s) != hipSuccess) return;
+        const int n = want - 1 < kSideStreams ? want - 1 : kSideStreams;
+        for (int k = 0; k < n; ++k) {
+            if (hipStreamWaitEvent(d.side[k], d.start, 0) != hipSuccess) break;
+            forked_ = k + 1;
+        }
+        cur_ = &d;
+        for (int k = 1; k < want; ++k) out[k] = forked_ ? d.side[(k - 1) % forked_] : s;
+    }
+
+    // The caller's stream waits for every side stream fork used; releases the
+    // fork lock.  Returns false if a wait could not be enqueued.
+    bool join(hipStream_t s)
+    {
+        bool ok = true;
+        for (int k = 0; k < forked_; ++k)
+            ok = ok && hipEventRecord(cur_->joined[k], cur_->side[k]) == hipSuccess &&
+                 hipStreamWaitEvent(s, cur_->joined[k], 0) == hipSuccess;
+        forked_ = 0;
+        cur_ = nullptr;
+        mu_.unlock();
+        return ok;
+    }
+
+private:
+    static constexpr int kMaxDevices = 64;
+    struct Dev {
+        bool ready = false;
+        hipStream_t side[kSideStreams] = {};
+        hipEvent_t joined[kSideStreams] = {};
+        hipEvent_t start = nullptr;
+    };
+    std::mutex mu_;
+    Dev dev_[kMaxDevices];
+    Dev *cur_ = nullptr;
+    int forked_ = 0;
+};
+
+// Writes the job lists of a call's launches (each list's jobs, then the
+// table of their start units and the total, each 256-byte aligned, list
+// after list) into the head of the caller's workspace, in stream order and
+// without waiting for the stream: all of them in one asynchronous copy from
+// the pinned staging ring, or, while the stream is being captured into a
+// graph (a replay would copy whatever the staging buffer then holds), by
+// kernels that carry the jobs in their arguments.  An empty list gets no
+// table (its JobList is left as it is).
+hc_status upload_job_lists(std::vector<Job> *lists, const uint64_t *totals, int nlists, void *ws, hipStream_t s,
+                           JobList *jl)
 {
-    const uint32_t count = (uint32_t)jobs.size();
-    Job *d_jobs = static_cast<Job *>(ws);
-    const uint64_t starts_at = align256((uint64_t)count * sizeof(Job));
-    uint64_t *d_starts = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + starts_at);
+    char *base = static_cast<char *>(ws);
+    std::vector<uint64_t> at(nlists), starts_at(nlists);
+    uint64_t end = 0, used = 0;
+    for (int c = 0; c < nlists; ++c) {
+        if (lists[c].empty()) continue;
+        const uint64_t count = lists[c].size();
+        at[c] = end;
+        starts_at[c] = at[c] + align256(count * sizeof(Job));
+        used = starts_at[c] + 8 * (count + 1);
+        end = starts_at[c] + align256(8 * (count + 1));
+    }
+    if (used == 0) return HC_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) return HC_ERR_HIP;
     if (cs != hipStreamCaptureStatusNone) {
-        if (launch_put_jobs(jobs.data(), count, total_units, d_jobs, d_starts, s) != hipSuccess) return HC_ERR_HIP;
+        for (int c = 0; c < nlists; ++c) {
+            if (lists[c].empty()) continue;
+            if (launch_put_jobs(lists[c].data(), (uint32_t)lists[c].size(), totals[c],
+                                reinterpret_cast<Job *>(base + at[c]), reinterpret_cast<uint64_t *>(base + starts_at[c]),
+                                s) != hipSuccess)
+                return HC_ERR_HIP;
+        }
     } else {
-        const size_t bytes = starts_at + 8 * ((size_t)count + 1);
-        const hipError_t e = JobStaging::get().copy(ws, bytes, s, [&](char *h) {
-            memcpy(h, jobs.data(), (size_t)count * sizeof(Job));
-            uint64_t *st = reinterpret_cast<uint64_t *>(h + starts_at);
-            for (uint32_t k = 0; k < count; ++k) st[k] = jobs[k].unit_begin;
-            st[count] = total_units;
+        const hipError_t e = JobStaging::get().copy(ws, used, s, [&](char *h) {
+            for (int c = 0; c < nlists; ++c) {
+                if (lists[c].empty()) continue;
+                const size_t count = lists[c].size();
+                memcpy(h + at[c], lists[c].data(), count * sizeof(Job));
+                uint64_t *st = reinterpret_cast<uint64_t *>(h + starts_at[c]);
+                for (size_t k = 0; k < count; ++k) st[k] = lists[c][k].unit_begin;
+                st[count] = totals[c];
+            }
         });
         if (e != hipSuccess) return HC_ERR_HIP;
     }
-    jl->jobs = d_jobs;
-    jl->starts = d_starts;
-    jl->count = count;
-    jl->one = empty_job();
+    for (int c = 0; c < nlists; ++c) {
+        if (lists[c].empty()) continue;
+        jl[c].jobs = reinterpret_cast<const Job *>(base + at[c]);
+        jl[c].starts = reinterpret_cast<const uint64_t *>(base + starts_at[c]);
+        jl[c].count = (uint32_t)lists[c].size();
+        jl[c].one = empty_job();
+    }
     return HC_OK;
+}
+
+hc_status upload_jobs(std::vector<Job> &jobs, uint64_t total_units, void *ws, hipStream_t s, JobList *jl)
+{
+    return upload_job_lists(&jobs, &total_units, 1, ws, s, jl);
 }
 
 }  // namespace
@@ -564,7 +674,7 @@ hc_status hc::encode_blocks_ws(const uint8_t *d_in, uint64_t n, uint32_t block_s
     j.block_off = d_block_off;
     j.sub_idx = d_sub_idx;
     return hip_status(launch_encode(single(j), tiles, block_size, qpt, cb->host.max_len, sub_block,
-                                    d_ws, d_err, s, kStepAll));
+                                    d_ws, d_err, s, kStepAll, complete8(cb->host)));
 }
 
 extern "C" hc_status hc_walk_blocks(const uint8_t *d_in, uint64_t in_bytes, uint64_t nb, uint64_t *d_block_off,
@@ -623,7 +733,7 @@ extern "C" uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t coun
     uint64_t nb = 0;
     for (uint32_t k = 0; k < count; ++k) nb += num_blocks(items[k].n, block_size);
     // + the 256-byte alignment of each encode class's stretch of scratch
-    return job_table_bytes(count) + encode_scratch_bound(nb, block_size) + 256 * 3;
+    return job_table_bytes(count) + encode_scratch_bound(nb, block_size) + 256 * 4;
 }
 
 extern "C" hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes,
@@ -664,17 +774,18 @@ namespace {
 // lengths, bit 1: offsets, bit 2: packing).  Every step re-derives the same
 // job table from the items, so the steps may be issued as separate calls on
 // one stream, with the same workspace.
-// Encode launch classes by longest code: the kernels' variants (codes joined
-// two or one at a time between flushes, the tile shape, 64-bit codes) change
-// at these lengths, and a launch takes the variant of its longest code, so
-// each class gets launches of its own.  Codes of <= 8 bits share the class
-// of <= 16: joining four codes instead of two gains less than the extra
-// launches' tails cost (a complete 8-bit code is copied either way).
-int encode_class(uint32_t max_len)
+// Encode launch classes: complete 8-bit codes (copied, no length pass),
+// then by longest code: the kernels' variants (codes joined two or one at a
+// time between flushes, the tile shape, 64-bit codes) change at these
+// lengths, and a launch takes the variant of its longest code, so each class
+// gets launches of its own.  Other codes of <= 8 bits share the class of
+// <= 16: joining four codes instead of two gains less than the extra
+// launches' tails cost.
+int encode_class(uint32_t max_len, bool c8)
 {
-    return max_len <= 16 ? 0 : max_len <= (uint32_t)kPackedMaxLen ? 1 : 2;
+    return c8 ? 0 : max_len <= 16 ? 1 : max_len <= (uint32_t)kPackedMaxLen ? 2 : 3;
 }
-constexpr int kEncodeClasses = 3;
+constexpr int kEncodeClasses = 4;
 
 hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                              void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream, uint32_t steps)
@@ -682,7 +793,7 @@ hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t bloc
     if (!items || count == 0 || !d_ws || !aligned(d_ws, 256)) return HC_ERR_INVALID_ARG;
     if (!valid_block_size(block_size) || !valid_sub_block(sub_block)) return HC_ERR_INVALID_ARG;
     std::vector<Job> jobs[kEncodeClasses];
-    uint32_t max_len[kEncodeClasses] = {1, 1, 1};
+    uint32_t max_len[kEncodeClasses] = {8, 1, 1, 1};
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
         hc_status st = check_encode(it.in, it.n, block_size, it.cb, it.out, it.out_cap, it.block_off, it.sub_idx,
@@ -692,7 +803,7 @@ hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t bloc
     for (uint32_t k = 0; k < count; ++k) {
         const hc_item &it = items[k];
         const uint32_t L = it.n > 0 ? it.cb->host.max_len : 1u;
-        const int c = encode_class(L);
+        const int c = encode_class(L, it.n > 0 && complete8(it.cb->host));
         max_len[c] = L > max_len[c] ? L : max_len[c];
         Job j = empty_job();
         j.in = it.in;
@@ -725,19 +836,28 @@ hc_status encode_batch_steps(const hc_item *items, uint32_t count, uint32_t bloc
     if (steps & kStepOffsets)
         for (uint32_t k = 0; k < count; ++k)
             if (items[k].n == 0 && launch_encode_empty(items[k].block_off, s) != hipSuccess) return HC_ERR_HIP;
-    char *table = static_cast<char *>(d_ws);
-    for (int c = 0; c < kEncodeClasses; ++c) {
-        if (jobs[c].empty() || tiles[c] == 0) continue;
-        JobList jl;
-        hc_status st = upload_jobs(jobs[c], tiles[c], table, s, &jl);
-        if (st != HC_OK) return st;
-        table += align256(jobs[c].size() * sizeof(Job)) + align256(8 * (jobs[c].size() + 1));
+    for (int c = 0; c < kEncodeClasses; ++c)
+        if (tiles[c] == 0) jobs[c].clear();  // nothing to launch (only empty items)
+    JobList jl[kEncodeClasses];
+    hc_status st = upload_job_lists(jobs, tiles, kEncodeClasses, d_ws, s, jl);
+    if (st != HC_OK) return st;
+    int classes = 0;
+    for (int c = 0; c < kEncodeClasses; ++c) classes += jobs[c].empty() ? 0 : 1;
+    hipStream_t on[kEncodeClasses];
+    SideStreams &side = SideStreams::get();
+    side.fork(s, classes, on);
+    // the copy class (0) last: the other classes' launches are resident
+    // first and the copy's groups fill what they leave of each CU
+    int used = 0;
+    hipError_t e = hipSuccess;
+    for (int c = kEncodeClasses - 1; c >= 0 && e == hipSuccess; --c) {
+        if (jobs[c].empty()) continue;
         void *scratch = static_cast<char *>(d_ws) + head + scratch_at[c];
-        const hipError_t e = launch_encode(jl, tiles[c], block_size, qpt[c], max_len[c], sub_block, scratch, d_err, s,
-                                           steps);
-        if (e != hipSuccess) return HC_ERR_HIP;
+        e = launch_encode(jl[c], tiles[c], block_size, qpt[c], max_len[c], sub_block, scratch, d_err, on[used++],
+                          steps, c == 0);
     }
-    return HC_OK;
+    const bool joined = side.join(s);
+    return e == hipSuccess && joined ? HC_OK : HC_ERR_HIP;
 }
 
 }  // namespace
@@ -808,20 +928,27 @@ extern "C" hc_status hc_decode_batch(const hc_item *items, uint32_t count, uint3
         if (it.cb->host.max_len > max_len[c]) max_len[c] = it.cb->host.max_len;
         jobs[c].push_back(j);
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char *ws = static_cast<char *>(d_ws);
-    for (int c = 0; c < kDecodeClasses; ++c) {
-        if (jobs[c].empty()) continue;
+    for (int c = 0; c < kDecodeClasses; ++c)
         if (groups[c] > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
-        JobList jl;
-        hc_status st = upload_jobs(jobs[c], groups[c], ws, s, &jl);
-        if (st != HC_OK) return st;
-        ws += align256(jobs[c].size() * sizeof(Job)) + align256(8 * (jobs[c].size() + 1));
-        const hipError_t e = launch_decode(jl, groups[c], block_size, max_len[c], sub_block, sub_block != 0, d_err, s,
-                                           c == 0);
-        if (e != hipSuccess) return HC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    JobList jl[kDecodeClasses];
+    hc_status st = upload_job_lists(jobs, groups, kDecodeClasses, d_ws, s, jl);
+    if (st != HC_OK) return st;
+    int classes = 0;
+    for (int c = 0; c < kDecodeClasses; ++c) classes += jobs[c].empty() ? 0 : 1;
+    hipStream_t on[kDecodeClasses];
+    SideStreams &side = SideStreams::get();
+    side.fork(s, classes, on);
+    // the copy class (0) last, as in the encode
+    int used = 0;
+    hipError_t e = hipSuccess;
+    for (int c = kDecodeClasses - 1; c >= 0 && e == hipSuccess; --c) {
+        if (jobs[c].empty()) continue;
+        e = launch_decode(jl[c], groups[c], block_size, max_len[c], sub_block, sub_block != 0, d_err, on[used++],
+                          c == 0);
     }
-    return HC_OK;
+    const bool joined = side.join(s);
+    return e == hipSuccess && joined ? HC_OK : HC_ERR_HIP;
 }
 
 extern "C" hc_status hc_decode_batch_selfsync(const hc_item *items, uint32_t count, uint32_t block_size, void *d_ws,
@@ -854,18 +981,25 @@ extern "C" hc_status hc_decode_batch_selfsync(const hc_item *items, uint32_t cou
         if (it.cb->host.max_len > max_len[c]) max_len[c] = it.cb->host.max_len;
         jobs[c].push_back(j);
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char *ws = static_cast<char *>(d_ws);
-    for (int c = 0; c < kDecodeClasses; ++c) {
-        if (jobs[c].empty()) continue;
+    for (int c = 0; c < kDecodeClasses; ++c)
         if (units[c] > 0x7FFFFFFFull) return HC_ERR_INVALID_ARG;
-        JobList jl;
-        hc_status st = upload_jobs(jobs[c], units[c], ws, s, &jl);
-        if (st != HC_OK) return st;
-        ws += align256(jobs[c].size() * sizeof(Job)) + align256(8 * (jobs[c].size() + 1));
-        const hipError_t e = c == 0 ? launch_decode(jl, units[c], block_size, 8, 0, false, d_err, s, true)
-                                    : launch_decode_sync(jl, units[c], block_size, max_len[c], d_err, s);
-        if (e != hipSuccess) return HC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    JobList jl[kDecodeClasses];
+    hc_status st = upload_job_lists(jobs, units, kDecodeClasses, d_ws, s, jl);
+    if (st != HC_OK) return st;
+    int classes = 0;
+    for (int c = 0; c < kDecodeClasses; ++c) classes += jobs[c].empty() ? 0 : 1;
+    hipStream_t on[kDecodeClasses];
+    SideStreams &side = SideStreams::get();
+    side.fork(s, classes, on);
+    int used = 0;
+    hipError_t e = hipSuccess;
+    for (int c = kDecodeClasses - 1; c >= 0 && e == hipSuccess; --c) {  // the copy class last
+        if (jobs[c].empty()) continue;
+        hipStream_t sc = on[used++];
+        e = c == 0 ? launch_decode(jl[c], units[c], block_size, 8, 0, false, d_err, sc, true)
+                   : launch_decode_sync(jl[c], units[c], block_size, max_len[c], d_err, sc);
     }
-    return HC_OK;
+    const bool joined = side.join(s);
+    return e == hipSuccess && joined ? HC_OK : HC_ERR_HIP;
 }

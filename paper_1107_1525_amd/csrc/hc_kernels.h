@@ -105,8 +105,10 @@ hipError_t launch_put_jobs(const Job *jobs, uint32_t count, uint64_t total, Job 
 hipError_t launch_histogram(const JobList &jl, uint64_t units, uint64_t chunk, hipStream_t s);
 // Encode steps (bit mask): the length pass, the offset scan, the packing.
 constexpr uint32_t kStepLengths = 1, kStepOffsets = 2, kStepPack = 4, kStepAll = 7;
+// complete8: every job has a complete 8-bit code (the length pass is left
+// out: each symbol costs 8 bits).
 hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t qpt, uint32_t max_len, uint32_t S,
-                         void *scratch, uint32_t *err, hipStream_t s, uint32_t steps);
+                         void *scratch, uint32_t *err, hipStream_t s, uint32_t steps, bool complete8);
 hipError_t launch_encode_empty(uint64_t *block_off, hipStream_t s);
 hipError_t launch_walk(const uint8_t *in, uint64_t in_bytes, uint64_t nb, uint64_t *block_off,
                        uint32_t *err, hipStream_t s);

@@ -392,14 +392,25 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
 constexpr uint32_t kOffThreads = 256;
 constexpr uint32_t kOffBlocks = 16;
 
+// c8_tile_syms > 0: every job of the launch has a complete 8-bit code and
+// tiles of c8_tile_syms symbols, so a tile's bit count is 8 times its
+// symbols and no length pass ran (a job whose table no longer has such a
+// code reports TABLE_CHANGED).
 __global__ __launch_bounds__(kOffThreads) void k_offsets(JobList jl, uint32_t B, uint32_t tpb,
                                                          const uint32_t *tile_bits, uint32_t *tile_pos,
-                                                         uint32_t *err)
+                                                         uint32_t c8_tile_syms, uint32_t *err)
 {
     __shared__ uint64_t s_scan[kOffThreads / 64];
     const Job jb = job_at(jl, blockIdx.x);
     if (jb.n == 0) return;  // the empty stream's table is written on its own
     const uint32_t tid = threadIdx.x;
+    if (c8_tile_syms) {
+        const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)jb.tb;
+        if (!(tb->fixed_len == 8 && tb->count[8] == (uint32_t)kNumSym)) {  // the same in every lane
+            if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+            return;
+        }
+    }
     const uint64_t nb = num_blocks_dev(jb.n, B);
     const HC_G uint32_t *tbits = (const HC_G uint32_t *)tile_bits + jb.unit_begin;
     HC_G uint32_t *tpos = (HC_G uint32_t *)tile_pos + jb.unit_begin;
@@ -415,9 +426,19 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(JobList jl, uint32_t B,
             bytes[i] = 0;
             if (b < nb) {
                 uint64_t bits = 0;
-                for (uint32_t j = 0; j < tpb; ++j) {
-                    tpos[b * tpb + j] = (uint32_t)bits;
-                    bits += tbits[b * tpb + j];
+                if (c8_tile_syms) {
+                    const uint64_t left = jb.n - b * (uint64_t)B;
+                    const uint32_t cnt = (uint32_t)(left < B ? left : B);
+                    for (uint32_t j = 0; j < tpb; ++j) {
+                        tpos[b * tpb + j] = (uint32_t)bits;
+                        const uint32_t ts = j * c8_tile_syms;
+                        bits += ts < cnt ? 8ull * (cnt - ts < c8_tile_syms ? cnt - ts : c8_tile_syms) : 0ull;
+                    }
+                } else {
+                    for (uint32_t j = 0; j < tpb; ++j) {
+                        tpos[b * tpb + j] = (uint32_t)bits;
+                        bits += tbits[b * tpb + j];
+                    }
                 }
                 if (bits > 0xFFFFFFFFull) report(err, HC_ERR_BLOCK_OVERFLOW);
                 bytes[i] = (uint32_t)(4 + 4 * ((bits + 31) / 32));
@@ -447,7 +468,7 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(JobList jl, uint32_t B,
 template <bool kPacked, uint32_t FPS, uint32_t QPT>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_encode(
     JobList jl, uint32_t B, uint32_t tpb, const uint32_t *tile_pos, const uint16_t *thread_bits, uint32_t S,
-    uint32_t cpb, uint32_t lds_words, uint32_t shape_len, uint32_t *err)
+    uint32_t cpb, uint32_t lds_words, uint32_t shape_len, uint32_t copy_only, uint32_t *err)
 {
     constexpr uint32_t kSyms = kQuadSyms * QPT;  // symbols per thread
     constexpr bool kHanded = QPT >= 2;           // bit counts from the length pass
@@ -488,7 +509,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
 
     const bool last_tile = tl.te == tl.cnt;
-    if (tb->fixed_len == 8 && tb->count[8] == (uint32_t)kNumSym) {
+    const bool c8 = tb->fixed_len == 8 && tb->count[8] == (uint32_t)kNumSym;
+    if (copy_only && !c8) {  // a launch shaped for complete 8-bit codes only (no length pass ran)
+        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+        return;
+    }
+    if (c8) {
         // A complete 8-bit code (uniform over the group): every symbol is its
         // own code, a tile starts on a whole word (P is 8 times a multiple of
         // 4096) and shares no word with the next tile, so the tile's payload
@@ -500,9 +526,31 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         HC_G uint32_t *payload = out32 + (O >> 2) + 1 + (P >> 5);
         const HC_G uint8_t *src8 = in + tl.blk_start + tl.ts;  // 16-byte aligned: B and the tile are multiples of 16
         const HC_G uint32_t *src = (const HC_G uint32_t *)src8;
-        const uint32_t nsym = tl.te - tl.ts, nfull = nsym / 4;
-#pragma unroll 4
-        for (uint32_t k = tid; k < nfull; k += kTileThreads) payload[k] = __builtin_bswap32(src[k]);
+        const uint32_t nsym = tl.te - tl.ts, nfull = nsym / 4, nvec = nsym / 16;
+        // 16-byte pieces, four in flight per thread (a tile of 4096 * QPT
+        // symbols is QPT rounds); each piece's four words go to the payload,
+        // which sits on any word (so a thread's words are four stores, the
+        // wave's stores covering a contiguous 1 KiB together)
+        for (uint32_t v0 = 0; v0 < nvec; v0 += 4 * kTileThreads) {
+            v4u x[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t v = v0 + u * kTileThreads + tid;
+                if (v < nvec) x[u] = ((const HC_G v4u *)src8)[v];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t v = v0 + u * kTileThreads + tid;
+                if (v < nvec) {
+                    HC_G uint32_t *d = payload + 4 * v;
+                    d[0] = __builtin_bswap32(x[u].x);
+                    d[1] = __builtin_bswap32(x[u].y);
+                    d[2] = __builtin_bswap32(x[u].z);
+                    d[3] = __builtin_bswap32(x[u].w);
+                }
+            }
+        }
+        if (tid < nfull - 4 * nvec) payload[4 * nvec + tid] = __builtin_bswap32(src[4 * nvec + tid]);  // < 4 whole words
         if ((nsym & 3) && tid == 0) {
             uint32_t part = 0;
             for (uint32_t b = 0; b < (nsym & 3); ++b) part |= (uint32_t)src8[4 * nfull + b] << (8 * b);
@@ -2034,11 +2082,12 @@ hipError_t launch_put_jobs(const Job *jobs, uint32_t count, uint64_t total, Job 
 }
 
 hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t qpt, uint32_t max_len, uint32_t S,
-                         void *scratch, uint32_t *err, hipStream_t s, uint32_t steps)
+                         void *scratch, uint32_t *err, hipStream_t s, uint32_t steps, bool complete8)
 {
     if (tiles == 0) return hipSuccess;
     const uint32_t tpb = tiles_per_block(B, qpt);
-    const uint32_t lds_words = (uint32_t)(((uint64_t)kTileSyms * qpt * max_len + 31ull) / 32ull + 2);
+    // the packing's LDS words (none for complete 8-bit codes: tiles are copied)
+    const uint32_t lds_words = complete8 ? 0u : (uint32_t)(((uint64_t)kTileSyms * qpt * max_len + 31ull) / 32ull + 2);
     const uint32_t cpb = S ? (B + S - 1) / S : 1;
     uint32_t *tile_bits = static_cast<uint32_t *>(scratch);
     uint32_t *tile_pos = tile_bits + tiles;
@@ -2046,8 +2095,8 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t
     const dim3 grid((uint32_t)tiles);
     const size_t lds = lds_words * 4;
     const bool packed = max_len <= (uint32_t)kPackedMaxLen;
-    // 1. lengths
-    if (!(steps & kStepLengths))
+    // 1. lengths (none for complete 8-bit codes: 8 bits a symbol)
+    if (!(steps & kStepLengths) || complete8)
         ;
     else if (qpt == 4)
         k_count<4><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, max_len, err);
@@ -2056,9 +2105,11 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t
     else
         k_count<1><<<grid, kTileThreads, 0, s>>>(jl, B, tpb, tile_bits, thread_bits, max_len, err);
     // 2. offsets
-    if (steps & kStepOffsets) k_offsets<<<dim3(jl.count), kOffThreads, 0, s>>>(jl, B, tpb, tile_bits, tile_pos, err);
+    if (steps & kStepOffsets)
+        k_offsets<<<dim3(jl.count), kOffThreads, 0, s>>>(jl, B, tpb, tile_bits, tile_pos,
+                                                         complete8 ? kTileSyms * qpt : 0u, err);
     // 3. packing
-#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tile_pos, thread_bits, S, cpb, lds_words, max_len, err)
+#define HC_ENC(P, F, Q) k_encode<P, F, Q><<<grid, kTileThreads, lds, s>>>(jl, B, tpb, tile_pos, thread_bits, S, cpb, lds_words, max_len, complete8 ? 1u : 0u, err)
     if (!(steps & kStepPack)) {
     } else if (!packed) {
         HC_ENC(false, 1, 1);

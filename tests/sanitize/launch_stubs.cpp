@@ -14,7 +14,7 @@ hipError_t launch_put_jobs(const Job *, uint32_t, uint64_t, Job *, uint64_t *, h
 }
 hipError_t launch_histogram(const JobList &, uint64_t, uint64_t, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_encode(const JobList &, uint64_t, uint32_t, uint32_t, uint32_t, uint32_t, void *, uint32_t *,
-                         hipStream_t, uint32_t)
+                         hipStream_t, uint32_t, bool)
 {
     return hipErrorInvalidValue;
 }

@@ -48,13 +48,14 @@ def _setup(hc, B, S):
     torch.cuda.synchronize()
     assert hc.read_error(err) == 0
     assert all(torch.equal(y, x) for y, x in zip(ys, xd))
-    return xs, xd, dcbs, outs, ys, e_items, d_items, ws, err
+    # the items hold raw pointers: every buffer they name lives as long as they do
+    return xs, xd, dcbs, outs, ys, e_items, d_items, ws, err, (offs, subs)
 
 
 @pytest.mark.parametrize("change", ["longer", "not_complete8"])
 def test_replay_with_changed_tables(hc, change):
     B, S = 16384, 128
-    xs, xd, dcbs, outs, ys, e_items, d_items, ws, err = _setup(hc, B, S)
+    xs, xd, dcbs, outs, ys, e_items, d_items, ws, err, keep = _setup(hc, B, S)
     g, gd = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()  # encode + decode, and decode alone
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -90,7 +91,13 @@ def test_replay_with_changed_tables(hc, change):
     torch.cuda.synchronize()
     err.zero_()
     # the longer code is met first by the encode's length pass; the incomplete
-    # code by the decode's copy launch (the encode would see uncoded symbols)
+    # code by the decode's copy launch, and by the encode's launches for
+    # complete 8-bit codes (which run no length pass)
     (g if change == "longer" else gd).replay()
     torch.cuda.synchronize()
     assert hc.read_error(err) == hc.HC_ERR_TABLE_CHANGED
+    if change == "not_complete8":
+        err.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert hc.read_error(err) == hc.HC_ERR_TABLE_CHANGED
