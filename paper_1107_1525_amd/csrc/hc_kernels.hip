@@ -35,6 +35,17 @@ typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 namespace hc {
 
 // ---------------------------------------------------------------- helpers
+// Streaming accesses marked non-temporal (kept out of the caches' reuse
+// sets).  On MI355X this lifts a plain streaming copy from about 5.7 to
+// 6.2 TB/s, but within the codec it pays only in the histogram's input reads
+// (0.79 -> 0.67 ms over 4 GiB): the length pass, the packing and the copy
+// forms ran slower with it, the staged decoder no faster.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const HC_G T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
 __device__ __forceinline__ void report(uint32_t *err, uint32_t code)
 {
     // the plain read first: once the word holds an error, the many lanes of a
@@ -179,16 +190,16 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(JobList jl, uint64_t chun
 
     uint64_t v = threadIdx.x;
     for (; v + 3 * kHistThreads < nvec; v += 4 * kHistThreads) {
-        v4u a = p[v];
-        v4u b = p[v + kHistThreads];
-        v4u c = p[v + 2 * kHistThreads];
-        v4u d = p[v + 3 * kHistThreads];
+        v4u a = ld_nt(p + v);
+        v4u b = ld_nt(p + v + kHistThreads);
+        v4u c = ld_nt(p + v + 2 * kHistThreads);
+        v4u d = ld_nt(p + v + 3 * kHistThreads);
         add_vec(a);
         add_vec(b);
         add_vec(c);
         add_vec(d);
     }
-    for (; v < nvec; v += kHistThreads) add_vec(p[v]);
+    for (; v < nvec; v += kHistThreads) add_vec(ld_nt(p + v));
     for (uint64_t j = beg + (nvec << 4) + threadIdx.x; j < end; j += kHistThreads)
         atomicAdd(&sh[(uint32_t)in[j] * 64 + lane], 1u);
     __syncthreads();

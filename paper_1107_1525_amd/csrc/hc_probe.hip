@@ -1,11 +1,13 @@
 // Roofline probes: a streaming copy and a streaming read of device memory.
 // They give the achievable side of the HBM roofline the codec kernels are
 // measured against: the rate plain, fully coalesced 16-byte accesses reach on
-// this device (each wave instruction covers 1 KiB of contiguous memory).  The
-// shapes (a 16 KiB tile per copy group; 1024 reading groups with 16 loads in
-// flight per thread, each over a contiguous range) were the fastest of a
-// sweep over loads in flight, group counts and strided or contiguous ranges
-// on MI355X.  They are measurement helpers, not part of the coding path.
+// this device (each wave instruction covers 1 KiB of contiguous memory),
+// marked non-temporal.  The shapes (a 32 KiB tile per copy group; 1024
+// reading groups with 16 loads in flight per thread, each over a contiguous
+// range) and the cache policy were the fastest of sweeps over loads in
+// flight, group counts, strided or contiguous ranges and non-temporal or
+// plain accesses on MI355X.  They are measurement helpers, not part of the
+// coding path.
 #include <hip/hip_runtime.h>
 
 #include "hc.h"
@@ -14,7 +16,7 @@ namespace {
 
 typedef uint32_t pv4 __attribute__((ext_vector_type(4)));
 constexpr uint32_t kProbeThreads = 256;
-constexpr uint32_t kCopyUnroll = 4;            // a copy group moves one 16 KiB tile: 4 loads per thread
+constexpr uint32_t kCopyUnroll = 8;            // a copy group moves one 32 KiB tile: 8 loads per thread
 constexpr uint32_t kReadUnroll = 16;           // 16 loads in flight per reading thread
 constexpr uint32_t kReadMaxGroups = 1024;      // 4 per CU, each streaming a contiguous range
 constexpr uint64_t kCopyTile = (uint64_t)kProbeThreads * kCopyUnroll;  // vectors per copy group
@@ -28,9 +30,9 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_copy(const pv4 *__restr
     if (base + (kCopyUnroll - 1) * kProbeThreads < nvec) {
         pv4 v[kCopyUnroll];
 #pragma unroll
-        for (uint32_t u = 0; u < kCopyUnroll; ++u) v[u] = src[base + u * kProbeThreads];
+        for (uint32_t u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(&src[base + u * kProbeThreads]);
 #pragma unroll
-        for (uint32_t u = 0; u < kCopyUnroll; ++u) dst[base + u * kProbeThreads] = v[u];
+        for (uint32_t u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], &dst[base + u * kProbeThreads]);
     } else {
         for (uint32_t u = 0; u < kCopyUnroll; ++u)
             if (base + u * kProbeThreads < nvec) dst[base + u * kProbeThreads] = src[base + u * kProbeThreads];
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_read(const pv4 *__restr
     for (; i + (kReadUnroll - 1) * kProbeThreads < end; i += kReadUnroll * kProbeThreads) {
         pv4 v[kReadUnroll];
 #pragma unroll
-        for (uint32_t u = 0; u < kReadUnroll; ++u) v[u] = src[i + u * kProbeThreads];
+        for (uint32_t u = 0; u < kReadUnroll; ++u) v[u] = __builtin_nontemporal_load(&src[i + u * kProbeThreads]);
 #pragma unroll
         for (uint32_t u = 0; u < kReadUnroll; ++u) x ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
     }
