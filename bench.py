@@ -49,8 +49,14 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, vendor figure
 METRIC = "compress/decompress GB/s (uncompressed) and % HBM peak; batched p50/p99 latency"
 WORKLOAD = "mixed-4GiB-64x64MiB"
 # the device function each timed launch runs (rocprofv3 names)
+# the device function of each single launch the bench times (its rocprofv3
+# name without template arguments); the packing has one instance per class
+# in every call (the copy and the packing proper), so its traffic summary
+# (instances summed per call) is not that of one launch
 KERNEL_SYMBOL = {"k_hist": "k_hist", "k_count": "k_count", "k_offsets": "k_offsets", "k_encode": "k_encode",
-                 "k_decode": "k_decode_stage", "k_decode_copy": "k_decode_ring", "k_decode_table": "k_decode_stage"}
+                 "k_encode_copy": "k_encode", "k_encode_pack": "k_encode", "k_decode": "k_decode_stage",
+                 "k_decode_copy": "k_decode_ring", "k_decode_table": "k_decode_stage"}
+SINGLE_INSTANCE = ("k_hist", "k_count", "k_decode_copy", "k_decode_table")
 
 
 def parse():
@@ -70,6 +76,10 @@ def parse():
                     help="64 MiB segments of the mixed workload the autotuner measures on (default 12)")
     ap.add_argument("--segments", type=int, default=64, help="number of 64 MiB segments (64 = 4 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-step", action="store_true",
+                    help="the timed step, its per-kernel and per-launch times and the probes only (no per-kind "
+                         "split, single streams, batches, serving, index-free decodes or CPU baseline): the "
+                         "command the kernel-trace and counter profiles run")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--per-kind", action="store_true",
@@ -92,6 +102,9 @@ def parse():
     ap.add_argument("--traffic-summary", metavar="DIR",
                     help="turn rocprofv3 --pmc runs in DIR/{fetch,write,copy_fetch,copy_write} into "
                          "profiles/traffic_*.json (HBM bytes per launch of each codec kernel)")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="print the codec kernels' durations from a rocprofv3 --kernel-trace run of --only-step "
+                         "(all dispatches, and those no other codec kernel overlapped)")
     ap.add_argument("--sq-table", metavar="DIR",
                     help="turn rocprofv3 --pmc runs of --per-kind under DIR (any number of counter sets) into "
                          "a per-kind table of SQ counters per symbol and per wave cycle of each codec kernel")
@@ -298,6 +311,65 @@ def autotune_step(hc, synth, torch, nseg: int, steps: int = 3):
                                             else {"error": r.get("error")})} for r in table]}
 
 
+def subset_times(w, segs, torch, np, reps=10, warmup=2):
+    """The encoder's three steps and the decode of the segments 'segs' alone,
+    through the batched calls on that subset (same buffers), HIP events
+    around every call: mean ms per call."""
+    hc = w.hc
+    E = torch.cuda.Event
+    e_it, d_it = hc.make_items(len(segs)), hc.make_items(len(segs))
+    for j, t in enumerate(segs):
+        hc.set_item(e_it, j, x=w.xs(t), dcb=w.dcb[t], out=w.outs(t), block_off=w.off[t], sub_idx=w.subs(t))
+        hc.set_item(d_it, j, x=w.outs(t), n=w.seg, in_bytes=w.C[t], dcb=w.dcb[t], out=w.ys(t),
+                    block_off=w.off[t], sub_idx=w.subs(t))
+    steps = (("k_count", lambda: hc.hc_encode_lengths_batch(e_it, w.B, w.S, w.ws, w.err)),
+             ("k_offsets", lambda: hc.hc_encode_offsets_batch(e_it, w.B, w.S, w.ws, w.err)),
+             ("k_encode", lambda: hc.hc_encode_pack_batch(e_it, w.B, w.S, w.ws, w.err)),
+             ("k_decode", lambda: hc.hc_decode_batch(d_it, w.B, w.S, w.ws, w.err)))
+    t = {k: [] for k, _ in steps}
+    for r in range(warmup + reps):
+        ev = {k: (E(enable_timing=True), E(enable_timing=True)) for k, _ in steps}
+        for k, fn in steps:
+            ev[k][0].record()
+            fn()
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        if r >= warmup:
+            for k, _ in steps:
+                t[k].append(ev[k][0].elapsed_time(ev[k][1]))
+    return {k: float(np.mean(v)) for k, v in t.items()}
+
+
+def subset_bytes(w, segs, np):
+    """Algorithmic bytes of each step over the segments 'segs'."""
+    n = w.seg * len(segs)
+    C = sum(w.C[j] for j in segs)
+    side = (8 * (w.nb + 1) + 4 * w.nsub) * len(segs)
+    complete8 = all(bool(np.all(np.asarray(w.dcb[j].host.lengths) == 8)) for j in segs)
+    return n, C, complete8, {"k_count": 0 if complete8 else n, "k_offsets": 8 * (w.nb + 1) * len(segs),
+                             "k_encode": n + C + side, "k_decode": C + n + side}
+
+
+def class_launch_times(w, torch, np):
+    """The mixed workload's two launch classes apart, each one call over its
+    own segments: the complete 8-bit codes (uniform segments: the encoder's
+    and the decoder's copy forms) and the rest (skewed and fp32 segments,
+    whose codes fall in one class: one length pass, one packing launch, one
+    table-decoder launch, the very launches of the whole step).  Each call is
+    then a single kernel launch, so these are per-launch times that a
+    kernel trace of the whole step reproduces."""
+    c8 = [t for t in range(w.nseg) if bool(np.all(np.asarray(w.dcb[t].host.lengths) == 8))]
+    rest = [t for t in range(w.nseg) if t not in set(c8)]
+    out = {}
+    for name, segs in (("copy", c8), ("table", rest)):
+        if not segs:
+            continue
+        ms = subset_times(w, segs, torch, np)
+        n, C, _, alg = subset_bytes(w, segs, np)
+        out[name] = {"segments": len(segs), "bytes": n, "compressed": C, "ms": ms, "alg": alg}
+    return out
+
+
 def kind_kernel_times(w, synth, torch, np, reps=10, warmup=2):
     """The same workload's segments of one kind at a time, through the
     batched calls on that subset (same buffers): the encoder's three launches
@@ -305,40 +377,13 @@ def kind_kernel_times(w, synth, torch, np, reps=10, warmup=2):
     decode of the uniform segments (complete 8-bit codes) is the decoder's
     copy launch, that of the others its table-decode launch, so this also
     times the two launches of the whole workload's decode call apart."""
-    hc = w.hc
-    E = torch.cuda.Event
     out = {}
     for kind in synth.SEGMENT_KINDS:
         segs = [t for t in range(w.nseg) if synth.mixed_kind(t) == kind]
         if not segs:
             continue
-        e_it, d_it = hc.make_items(len(segs)), hc.make_items(len(segs))
-        for j, t in enumerate(segs):
-            hc.set_item(e_it, j, x=w.xs(t), dcb=w.dcb[t], out=w.outs(t), block_off=w.off[t], sub_idx=w.subs(t))
-            hc.set_item(d_it, j, x=w.outs(t), n=w.seg, in_bytes=w.C[t], dcb=w.dcb[t], out=w.ys(t),
-                        block_off=w.off[t], sub_idx=w.subs(t))
-        steps = (("k_count", lambda: hc.hc_encode_lengths_batch(e_it, w.B, w.S, w.ws, w.err)),
-                 ("k_offsets", lambda: hc.hc_encode_offsets_batch(e_it, w.B, w.S, w.ws, w.err)),
-                 ("k_encode", lambda: hc.hc_encode_pack_batch(e_it, w.B, w.S, w.ws, w.err)),
-                 ("k_decode", lambda: hc.hc_decode_batch(d_it, w.B, w.S, w.ws, w.err)))
-        t = {k: [] for k, _ in steps}
-        for r in range(warmup + reps):
-            ev = {k: (E(enable_timing=True), E(enable_timing=True)) for k, _ in steps}
-            for k, fn in steps:
-                ev[k][0].record()
-                fn()
-                ev[k][1].record()
-            torch.cuda.synchronize()
-            if r >= warmup:
-                for k, _ in steps:
-                    t[k].append(ev[k][0].elapsed_time(ev[k][1]))
-        n = w.seg * len(segs)
-        C = sum(w.C[j] for j in segs)
-        side = (8 * (w.nb + 1) + 4 * w.nsub) * len(segs)
-        complete8 = all(bool(np.all(np.asarray(w.dcb[j].host.lengths) == 8)) for j in segs)
-        alg = {"k_count": 0 if complete8 else n, "k_offsets": 8 * (w.nb + 1) * len(segs),
-               "k_encode": n + C + side, "k_decode": C + n + side}
-        ms = {k: float(np.mean(v)) for k, v in t.items()}
+        ms = subset_times(w, segs, torch, np, reps=reps, warmup=warmup)
+        n, C, complete8, alg = subset_bytes(w, segs, np)
         out[kind] = {
             "segments": len(segs), "bytes": n, "ratio": round(C / n, 5),
             "max_len": max(int(w.dcb[j].max_len) for j in segs),
@@ -819,9 +864,9 @@ def traffic_summary(root: str, B: int, S: int, out_dir: str = None):
             "copy_kernel": copy_name, "copy_bytes": copy_bytes,
             "commands": [
                 f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- "
-                f"python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --block {B} --sub-block {S}",
+                f"python -u bench.py --only-step --steps 1 --warmup 1 --block {B} --sub-block {S} --tile-loads 0",
                 f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- "
-                f"python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --block {B} --sub-block {S}",
+                f"python -u bench.py --only-step --steps 1 --warmup 1 --block {B} --sub-block {S} --tile-loads 0",
                 "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/copy_fetch -o run -- "
                 "python -u bench.py --copy-probe",
                 "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/copy_write -o run -- "
@@ -842,6 +887,44 @@ def traffic_summary(root: str, B: int, S: int, out_dir: str = None):
             json.dump(rec, f, indent=1)
     print(json.dumps(out, indent=1))
     return out
+
+
+def trace_summary(root: str, B: int, S: int):
+    """Markdown table of the codec kernels in a rocprofv3 kernel trace of
+    `bench.py --only-step`: calls and duration per kernel instance over all
+    dispatches, and over the dispatches no other codec kernel overlapped
+    (the launches the bench times one at a time; in the step itself a call's
+    class launches run side by side and stretch each other)."""
+    import csv
+    import glob
+
+    def codec(name):
+        return kernel_name(name).split("::")[-1].startswith(("k_", "hc::k_")) or "hc::k_" in name
+
+    rows = []
+    for f in glob.glob(os.path.join(root, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if codec(r["Kernel_Name"]):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), kernel_name(r["Kernel_Name"])))
+    rows.sort()
+    alone, running = [], -1  # running: the latest end among earlier-starting dispatches
+    for i, (a, b, nm) in enumerate(rows):
+        nxt = rows[i + 1][0] if i + 1 < len(rows) else 1 << 62  # sorted by start: the next start is the earliest
+        alone.append(running <= a and nxt >= b)
+        running = max(running, b)
+    by = {}
+    for (a, b, nm), al in zip(rows, alone):
+        d = by.setdefault(nm, {"all": [], "alone": []})
+        d["all"].append((b - a) / 1e3)
+        if al:
+            d["alone"].append((b - a) / 1e3)
+    lines = [f"| kernel | calls | avg us | min us | max us | alone calls | alone avg us |", "|---|---|---|---|---|---|---|"]
+    for nm, d in sorted(by.items(), key=lambda kv: -sum(kv[1]["all"])):
+        al = d["alone"]
+        lines.append(f"| `{nm.replace('hc::', '')}` | {len(d['all'])} | {sum(d['all']) / len(d['all']):.2f} | "
+                     f"{min(d['all']):.2f} | {max(d['all']):.2f} | {len(al)} | "
+                     f"{(sum(al) / len(al)) if al else float('nan'):.2f} |")
+    print("\n".join(lines))
 
 
 def sq_table(root: str, synth, args):
@@ -1060,7 +1143,8 @@ def main():
     # the timed run tunes its launch parameters unless any of them is given
     # (the helper modes take the defaults)
     tune_wanted = (args.block is None and args.sub_block is None and args.tile_loads is None and not args.no_tune
-                   and not (args.sweep or args.per_kind or args.traffic_summary or args.sq_table or args.copy_probe))
+                   and not (args.sweep or args.per_kind or args.traffic_summary or args.sq_table or args.trace_summary
+                            or args.copy_probe))
 
     def fill_defaults():
         args.block = 64 * 1024 if args.block is None else args.block
@@ -1074,6 +1158,9 @@ def main():
         return
     if args.sq_table:
         sq_table(args.sq_table, synth, args)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.block, args.sub_block)
         return
     torch.cuda.set_device(0)
     if args.copy_probe:
@@ -1147,7 +1234,7 @@ def main():
             "k_encode": n + C + off_bytes + sub_bytes,
             "k_decode": C + n + off_bytes + sub_bytes,
         }
-        kinds = kind_kernel_times(w, synth, torch, np)
+        kinds = None if args.only_step else kind_kernel_times(w, synth, torch, np)
         if hc.read_error(w.err):
             raise hc.HcError(hc.read_error(w.err), "per-kind timing")
         assert torch.equal(w.y, w.x), "round trip failed (per-kind timing)"
@@ -1169,29 +1256,42 @@ def main():
             "ratio": round(C / n, 5),
             "count_readback_ms": round(readback_ms, 3), "host_code_build_ms": round(build_ms, 3),
         }
-        # the decode call is two launches (complete 8-bit codes by the copy
-        # form, the rest by the table decoder): each is its own kernel here,
-        # timed on the kinds it serves
-        for name, kind_set in (("k_decode_copy", ("uniform",)), ("k_decode_table", ("skewed", "fp32"))):
-            ks = [kinds[k] for k in kind_set if k in kinds]
-            if ks:
-                ms = sum(k["k_decode"]["avg_ms"] for k in ks)
-                nbytes = sum(k["bytes"] for k in ks)
-                cbytes = sum(round(k["bytes"] * k["ratio"]) for k in ks)
-                side = sum(k["segments"] for k in ks) * (8 * (w.nb + 1) + 4 * w.nsub)
-                alg[name] = nbytes + cbytes + side
+        # the encode and decode calls launch each code class apart, side by
+        # side (complete 8-bit codes by the copy forms, the rest by the length
+        # pass, the packing and the table decoder), so k_encode and k_decode
+        # above are calls; their launches are timed here one at a time, on
+        # the segments each serves
+        classes = class_launch_times(w, torch, np)
+        if hc.read_error(w.err):
+            raise hc.HcError(hc.read_error(w.err), "launch-class timing")
+        assert torch.equal(w.y, w.x), "round trip failed (launch-class timing)"
+        for name, cls, step in (("k_encode_copy", "copy", "k_encode"), ("k_decode_copy", "copy", "k_decode"),
+                                ("k_encode_pack", "table", "k_encode"), ("k_decode_table", "table", "k_decode")):
+            if cls in classes:
+                c = classes[cls]
+                ms, nbytes = c["ms"][step], c["alg"][step]
+                alg[name] = nbytes
                 kavg[name] = ms
-                kernels[name] = {"avg_ms": round(ms, 4), "GBps_alg": round(gb(alg[name], ms), 1),
-                                 "pct_hbm": round(100 * gb(alg[name], ms) / HBM_PEAK_GBPS, 1),
-                                 "note": "timed on its own kinds' segments (" + ", ".join(kind_set) + ")"}
-        single = [k for k in kavg if k != "k_decode"]  # single launches: the decode call is split above
+                kernels[name] = {"avg_ms": round(ms, 4), "GBps_alg": round(gb(nbytes, ms), 1),
+                                 "pct_hbm": round(100 * gb(nbytes, ms) / HBM_PEAK_GBPS, 1),
+                                 "note": f"one launch: {c['segments']} segments ({cls} class) alone"}
+        # single launches only (a call's launches overlap; the offset pass is
+        # one launch per class and too short to matter)
+        single = [k for k in ("k_hist", "k_count", "k_encode_copy", "k_encode_pack", "k_decode_copy",
+                              "k_decode_table") if k in kavg]
         dominant = max(single, key=lambda k: kavg[k])
+        staged = 0 < S <= 128  # the table decoder is k_decode_stage; else a k_decode_ring instance beside the copy's
+        symbol = KERNEL_SYMBOL[dominant] if (dominant != "k_decode_table" or staged) else "k_decode_ring"
+        one_instance = dominant in SINGLE_INSTANCE and (dominant != "k_decode_table" or staged)
+        for k, what in (("k_encode", "encode"), ("k_decode", "decode")):
+            kernels[k]["note"] = f"the {what} call: its class launches side by side"
         launch_ms, per_launch = kavg[dominant], alg[dominant]
         achieved = per_launch / (launch_ms * 1e-3) / 1e9
         roofline = {
-            "bound": "hbm", "kernel": KERNEL_SYMBOL[dominant], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "bound": "hbm", "kernel": symbol, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": load_traffic(KERNEL_SYMBOL[dominant], B, S),
+            "traffic": load_traffic(symbol, B, S) if one_instance else None,
+            "launch": dominant,
             "bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4),
             # what the library's streaming copy probe reaches on this device
             # (1 GiB, read + write), and its streaming read alone
@@ -1209,6 +1309,10 @@ def main():
         }
         if tuned is not None:
             line["autotune"] = tuned
+        if args.only_step:
+            args.no_selfsync = args.no_cpu_baseline = True
+            args.batched = args.serve = 0
+            args.host_pipeline = False
         if not args.no_selfsync:
             print("[bench] decode without the sub-block index", file=sys.stderr, flush=True)
             line["selfsync_decode"] = selfsync_bench(w, hc, torch, np, kavg["k_decode"])
@@ -1217,7 +1321,7 @@ def main():
             line["cpu_baseline"] = cpu_baseline(w, __import__("oracle"), np)
         del w
         torch.cuda.empty_cache()
-        if not args.sweep:
+        if not args.sweep and not args.only_step:
             print("[bench] single streams: 1 MiB and 256 MiB", file=sys.stderr, flush=True)
             line["single_stream"] = [single_stream_bench(hc, synth, torch, np, nm, S)
                                      for nm in ("zipf1.2-1MiB-B4KiB", "zipf1.1-256MiB-B64KiB")]

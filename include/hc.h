@@ -27,13 +27,17 @@
  *   - Pointers named d_* are device memory owned by the caller; h_* are host
  *     memory owned by the caller.  The library allocates memory only in
  *     hc_codebook_upload and hc_cbset_create (freed by hc_codebook_destroy and
- *     hc_cbset_destroy), and the pinned staging ring of the batch calls' job
+ *     hc_cbset_destroy), the pinned staging ring of the batch calls' job
  *     tables (see hc_histogram_batch: on first use and when a table outgrows
- *     it); no other call allocates or frees.  Calls that wait
- *     on the host: hc_codebook_upload (its copy), hc_codebook_update and
- *     hc_cbset_build (the handle's or set's own previous table copy, normally
- *     long finished), hc_codebook_destroy and hc_cbset_destroy (the same, and
- *     the runtime's free).  The coding calls never wait.
+ *     it), and, once per device, the batch calls' side streams and events
+ *     (see hc_decode_batch), all kept until the process ends; no other call
+ *     allocates or frees.  Calls that wait on the host: hc_codebook_upload
+ *     (its copy), hc_codebook_update and hc_cbset_build (the handle's or
+ *     set's own previous table copy, normally long finished),
+ *     hc_codebook_destroy and hc_cbset_destroy (the same, and the runtime's
+ *     free), and a batch call whose staging buffer (used again every eighth
+ *     call) still holds a copy that has not left it (normally long
+ *     finished).  The other coding calls never wait.
  *   - 'stream' is a hipStream_t passed as void* (NULL = the null stream).
  *     Device work is enqueued on it and the call returns without waiting.
  *   - Errors that the host can see (bad sizes, null or misaligned pointers,
@@ -379,6 +383,13 @@ hc_status hc_encode_pack_batch(const hc_item *items, uint32_t count, uint32_t bl
 /* a complete 8-bit code (all 256 bytes, 8 bits each) decode as a          */
 /* byte-swapped copy; the rest by the table decoder, one launch for each   */
 /* longest-code class (<= 8, <= 10, <= 12, <= 16, <= 24 bits, longer).     */
+/* Side by side: with more than one class, the launches after the first   */
+/* go to library-owned streams (default priority, created once per device) */
+/* that wait for everything 'stream' holds when the call is made, and     */
+/* 'stream' then waits for them, so the call is still one step in the     */
+/* caller's stream order.  While 'stream' is captured into a graph the    */
+/* launches run in stream order instead.  The batch encode calls do the   */
+/* same with their classes.                                                */
 /* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: CORRUPT,         */
 /* TABLE_CHANGED.                                                           */
 /* Graph capture: the batch calls choose kernel variants and shapes from   */
