@@ -180,5 +180,17 @@ def test_host_argument_errors(hc):
                                 None) == hc.HC_ERR_INVALID_ARG
     assert lib.hc_decode_blocks(vp(16), 64, 100, 16, vp(16), vp(16), None, 24, vp(16), None,
                                 None) == hc.HC_ERR_INVALID_ARG
+    # no offset table: refused (the decode neither walks nor allocates; hc_walk_blocks first)
+    assert lib.hc_decode_blocks(vp(16), 64, 100, 16, vp(16), None, None, 0, vp(16), None,
+                                None) == hc.HC_ERR_INVALID_ARG
+    lib.hc_decode_batch_selfsync.argtypes = [vp, u32, u32, vp, u64, vp, vp]
+    assert lib.hc_decode_batch_selfsync(None, 1, 4096, vp(256), 1 << 20, None, None) == hc.HC_ERR_INVALID_ARG
+    items = hc.make_items(1)
+    assert lib.hc_decode_batch_selfsync(ctypes.cast(items, vp), 1, 24, vp(256), 1 << 20, None,
+                                        None) == hc.HC_ERR_INVALID_ARG  # block size not a multiple of 16
+    assert lib.hc_decode_batch_selfsync(ctypes.cast(items, vp), 1, 4096, vp(8), 1 << 20, None,
+                                        None) == hc.HC_ERR_INVALID_ARG  # misaligned workspace
+    assert lib.hc_decode_batch_selfsync(ctypes.cast(items, vp), 1, 4096, vp(256), 16, None,
+                                        None) == hc.HC_ERR_NO_SPACE  # workspace too small for the job table
     lib.hc_walk_blocks.argtypes = [vp, u64, u64, vp, vp, vp]
     assert lib.hc_walk_blocks(vp(16), 10, 1, vp(16), None, None) == hc.HC_ERR_INVALID_ARG  # size % 4
