@@ -643,32 +643,40 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             auto pack = [&](auto mask_tag) {
                 constexpr bool kMask = decltype(mask_tag)::value;
                 uint32_t run = 0;  // the thread's bits so far
+                // groups of FPS codes inside each 16-symbol load (FPS = 3
+                // leaves a last group of one), so that a load's first symbol
+                // always starts a group (the sub-block index positions)
+                constexpr uint32_t kGroups = (kQuadSyms + FPS - 1) / FPS;
 #pragma unroll
-                for (uint32_t k = 0; k < kSyms; k += FPS) {
-                    if ((k & (kQuadSyms - 1)) == 0) {
-                        if (k) __builtin_amdgcn_sched_barrier(0);
-                        const uint32_t i = k / 4;
-                        asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]));
-                        if (kHanded) qbits[k / kQuadSyms] = run;
-                    }
-                    uint32_t gc = 0, gsum = 0;
+                for (uint32_t q = 0; q < QPT; ++q) {
+                    if (q) __builtin_amdgcn_sched_barrier(0);
+                    asm volatile("" : "+v"(w[4 * q]), "+v"(w[4 * q + 1]), "+v"(w[4 * q + 2]), "+v"(w[4 * q + 3]));
+                    if (kHanded) qbits[q] = run;
 #pragma unroll
-                    for (uint32_t j = 0; j < FPS; ++j) {
-                        const uint32_t e0 = s_packed[sym_at(w, k + j)];
-                        const uint32_t e = (!kMask || k + j < m) ? e0 : 0u;
-                        gc = (gc << (e & 31u)) | (e >> 8);
-                        gsum += e;  // the low byte sums the lengths (<= 32)
+                    for (uint32_t g = 0; g < kGroups; ++g) {
+                        const uint32_t k = kQuadSyms * q + FPS * g;
+                        const uint32_t G = g + 1 < kGroups ? FPS : kQuadSyms - FPS * g;  // codes in this group
+                        uint32_t gc = 0, gsum = 0;
+#pragma unroll
+                        for (uint32_t j = 0; j < FPS; ++j) {
+                            if (j < G) {
+                                const uint32_t e0 = s_packed[sym_at(w, k + j)];
+                                const uint32_t e = (!kMask || k + j < m) ? e0 : 0u;
+                                gc = (gc << (e & 31u)) | (e >> 8);
+                                gsum += e;  // the low byte sums the lengths (<= 32)
+                            }
+                        }
+                        const uint32_t gl = gsum & 255u;
+                        run += gl;
+                        acc = (acc << gl) | gc;
+                        nacc += gl;
+                        const uint32_t need = nacc >= 32 ? 1u : 0u;
+                        const uint32_t word = (uint32_t)(acc >> ((nacc - 32) & 63u));
+                        atomicOr(&words[widx], need ? word : 0u);
+                        nacc -= need << 5;
+                        acc &= (1ull << nacc) - 1ull;
+                        widx += need;
                     }
-                    const uint32_t gl = gsum & 255u;
-                    run += gl;
-                    acc = (acc << gl) | gc;
-                    nacc += gl;
-                    const uint32_t need = nacc >= 32 ? 1u : 0u;
-                    const uint32_t word = (uint32_t)(acc >> ((nacc - 32) & 63u));
-                    atomicOr(&words[widx], need ? word : 0u);
-                    nacc -= need << 5;
-                    acc &= (1ull << nacc) - 1ull;
-                    widx += need;
                 }
             };
             if (wave_full)
@@ -2126,11 +2134,14 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t
         HC_ENC(false, 1, 1);
     } else {
         // FPS codes between accumulator flushes: FPS * max_len <= 32
-        const uint32_t fps = max_len <= 8 ? 4 : max_len <= 16 ? 2 : 1;
+        const uint32_t fps = max_len <= 8 ? 4 : max_len <= 10 ? 3 : max_len <= 16 ? 2 : 1;
         switch (fps * 8 + qpt) {
         case 4 * 8 + 4: HC_ENC(true, 4, 4); break;
         case 4 * 8 + 2: HC_ENC(true, 4, 2); break;
         case 4 * 8 + 1: HC_ENC(true, 4, 1); break;
+        case 3 * 8 + 4: HC_ENC(true, 3, 4); break;
+        case 3 * 8 + 2: HC_ENC(true, 3, 2); break;
+        case 3 * 8 + 1: HC_ENC(true, 3, 1); break;
         case 2 * 8 + 4: HC_ENC(true, 2, 4); break;
         case 2 * 8 + 2: HC_ENC(true, 2, 2); break;
         case 2 * 8 + 1: HC_ENC(true, 2, 1); break;
