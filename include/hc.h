@@ -348,11 +348,13 @@ uint64_t hc_batch_workspace_bytes(const hc_item *items, uint32_t count, uint32_t
 hc_status hc_histogram_batch(const hc_item *items, uint32_t count, void *d_ws, uint64_t ws_bytes, void *stream);
 
 /* hc_encode_blocks for every item (uses in, n, cb, out, out_cap,          */
-/* block_off, sub_idx) with block size B and sub-block stride S.  One      */
-/* launch: tiles of all items are packed by the same kernel; each item's   */
-/* offsets start at 0 in its own stream.                                   */
+/* block_off, sub_idx) with block size B and sub-block stride S.  Per code */
+/* class present (complete 8-bit codes, which need no length pass; then    */
+/* longest codes <= 16, <= 24 bits, longer) one launch of each step over   */
+/* the tiles of all its items; the classes side by side as in             */
+/* hc_decode_batch.  Each item's offsets start at 0 in its own stream.     */
 /* Errors returned: INVALID_ARG, NO_SPACE, HIP; in *d_err: SYMBOL_ABSENT,   */
-/* BLOCK_OVERFLOW.                                                          */
+/* BLOCK_OVERFLOW, TABLE_CHANGED (graph replays: see hc_decode_batch).     */
 hc_status hc_encode_batch(const hc_item *items, uint32_t count, uint32_t block_size, uint32_t sub_block,
                           void *d_ws, uint64_t ws_bytes, uint32_t *d_err, void *stream);
 
