@@ -1711,21 +1711,41 @@ __device__ __forceinline__ void wave_lds_sync()
 // bits from bit position p on (at least 33 of them the chunk's: two words
 // shifted by p mod 32); the table entries decoded since the last refill are
 // summed in esum, whose low byte is then their total length (refills come
-// after at most SPR codes, SPR * max_len <= 33).
+// after at most SPR codes, SPR * max_len <= 32).  So the next window starts
+// at most one word after this one: x0, x1 are this window's two area words
+// and x2 the one after, read at the last refill, and a refill takes its
+// words from them and reads only the next word ahead, so that no refill
+// waits on LDS inside the chain of table reads.  kAhead false: each refill
+// reads its two words (the two-chain kernels, whose registers the three
+// words would overflow).
+template <bool kAhead>
 struct StageBits {
     uint64_t buf;
     uint32_t p, esum;
+    uint32_t x0, x1, x2;
 
     __device__ __forceinline__ void window(const uint32_t *area)
     {
         const uint32_t w = p >> 5;
-        buf = (((uint64_t)area[w] << 32) | area[w + 1]) << (p & 31u);
+        x0 = area[w];
+        x1 = area[w + 1];
+        if (kAhead) x2 = area[w + 2];
+        buf = (((uint64_t)x0 << 32) | x1) << (p & 31u);
     }
     __device__ __forceinline__ void refill(const uint32_t *area)
     {
+        const uint32_t p0 = p;
         p += esum & 255u;
         esum = 0;
-        window(area);
+        if (!kAhead) {
+            window(area);
+            return;
+        }
+        const bool step = (p >> 5) != (p0 >> 5);  // at most 32 bits passed: the next word at most
+        x0 = step ? x1 : x0;
+        x1 = step ? x2 : x1;
+        buf = (((uint64_t)x0 << 32) | x1) << (p & 31u);
+        x2 = area[(p >> 5) + 2];
     }
 };
 
@@ -1733,8 +1753,8 @@ struct StageBits {
 // invalid prefix reads as a 1-bit code flagged kLutBadFlag (or-ed into bad).
 // kLong: codes longer than the table take the canonical-range search on the
 // buffered bits (which hold >= max_len bits whenever a code starts).
-template <bool kLong>
-__device__ __forceinline__ uint32_t stage_entry(StageBits &b, const uint16_t *lut, uint32_t lut_shift, uint32_t K,
+template <bool kLong, bool kAhead>
+__device__ __forceinline__ uint32_t stage_entry(StageBits<kAhead> &b, const uint16_t *lut, uint32_t lut_shift, uint32_t K,
                                                 uint32_t max_len, const uint32_t *s_first, const uint32_t *s_count,
                                                 const uint32_t *s_base, const uint32_t *s_sorted, uint32_t &bad)
 {
@@ -1938,7 +1958,7 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
         for (uint32_t h = 0; h < kChains; ++h) whole = whole && ok[h] && s1[h] - s0[h] == S_eff;
         const bool coalesce = __all(whole) && S_eff * kChains == kStageMaxS;
         if (take) {
-            StageBits rd[kChains];
+            StageBits<kChains == 1> rd[kChains];
 #pragma unroll
             for (uint32_t h = 0; h < kChains; ++h) {
                 rd[h].p = 32 * (uint32_t)(fw[h] - 4 * bq) + (uint32_t)(p0[h] & 31);
@@ -1946,8 +1966,8 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
                 if (ok[h]) rd[h].window(area);
             }
             auto entry = [&](uint32_t h) -> uint32_t {
-                return stage_entry<kLong>(rd[h], s_lut, lut_shift, K, max_len, s_first, s_count, s_base, s_sorted,
-                                          bad);
+                return stage_entry<kLong, kChains == 1>(rd[h], s_lut, lut_shift, K, max_len, s_first, s_count, s_base,
+                                                        s_sorted, bad);
             };
             uint32_t ow[kChains * kChainWords];
 #pragma unroll
