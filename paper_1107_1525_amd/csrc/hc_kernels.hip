@@ -329,52 +329,72 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     }
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
-    if (tb->max_len > shape_len) {  // the same in every lane: the group leaves together
-        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
-        return;
-    }
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
     const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
     const uint32_t s = tl.ts + kSyms * tid;
+    // The input and the length words are requested before the table is
+    // checked, so that their latency overlaps the check's reads instead of
+    // following them (a group's whole life is a few of these latencies).
+    uint32_t w[4 * QPT];
+    const uint32_t m = load_syms<QPT>(in, tl, s, w);  // 0 past the end of the tile
+    const v4u x = ((const HC_G v4u *)tb->len4)[tid >> 4];
+    if (tb->max_len > shape_len) {  // the same in every lane: the group leaves together
+        // (the loads' results are named on this path too, so that they stay
+        // ahead of the check rather than being sunk past it)
+        asm volatile("" ::"v"(w[0]), "v"(x.x));
+        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+        return;
+    }
     if (tb->fixed_len == 8 && tb->count[8] == (uint32_t)kNumSym) {
         // A complete 8-bit code (uniform over the group: one job per tile):
-        // every symbol has a code of 8 bits, so the input need not be read;
-        // the packing pass copies such tiles without per-thread counts.
+        // every symbol has a code of 8 bits, so the count needs no input; the
+        // packing pass copies such tiles without per-thread counts.  (Launches
+        // are shaped so that such codes run no length pass at all.)
         if (tid == 0) tile_bits[t] = tl.ts < tl.te ? 8 * (tl.te - tl.ts) : 0u;
         return;
     }
-    uint32_t w[4 * QPT];
-    const uint32_t m = load_syms<QPT>(in, tl, s, w);  // 0 past the end of the tile
     {
         // thread t holds words 4q..4q+3 (q = t / 16) and writes each into
         // replicas 4g..4g+3 (g = t mod 16): one 16-byte load, four 16-byte LDS
         // writes, and each write instruction covers all banks evenly
         static_assert(kWords == 64 && kTileThreads == 256, "one length word group per 16 threads");
         const uint32_t q = tid >> 4, g = tid & 15u;
-        const v4u x = ((const HC_G v4u *)tb->len4)[q];
         const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j)
             *(v4u *)(s_len4 + 64 * (4 * q + j) + 4 * g) = v4u{xs[j], xs[j], xs[j], xs[j]};
     }
     __syncthreads();
-    const uint32_t *my = s_len4 + lane;
+    // Symbol v's length is byte 256 (v >> 2) + 4 lane + (v & 3) of the
+    // replicas: one byte read, its address one byte permute per symbol from two
+    // words made once per four symbols, (v >> 2) in each byte of one and
+    // 4 lane + (v & 3) in each byte of the other.  The length pass is bound by
+    // VALU issue, and this takes the per-symbol address and extract work from
+    // six instructions to one.
+    const uint8_t *len8 = (const uint8_t *)s_len4;
+    const uint32_t lane4 = (lane * 4u) * 0x01010101u;
     uint32_t bits = 0, mn = 255u;  // mn: the smallest code length met, 0 = a symbol without a code
     // Only the wave holding a block's ragged end masks symbols past m.
     auto count = [&](auto mask_tag) {
         constexpr bool kMask = decltype(mask_tag)::value;
 #pragma unroll
-        for (uint32_t k = 0; k < kSyms; ++k) {
-            if ((k & (kQuadSyms - 1)) == 0 && k) {
+        for (uint32_t i = 0; i < 4 * QPT; ++i) {
+            if ((i & 3u) == 0 && i) {
                 // one load's lookups at a time: bounds the registers held by reads in flight
                 __builtin_amdgcn_sched_barrier(0);
-                const uint32_t i = k / 4;
                 asm volatile("" : "+v"(w[i]), "+v"(w[i + 1]), "+v"(w[i + 2]), "+v"(w[i + 3]), "+v"(bits), "+v"(mn));
             }
-            const uint32_t v = sym_at(w, k);
-            const uint32_t L = (my[64 * (v >> 2)] >> (8 * (v & 3u))) & 255u;
-            bits += (!kMask || k < m) ? L : 0u;
-            mn = min(mn, (!kMask || k < m) ? L : 255u);
+            const uint32_t hi = (w[i] >> 2) & 0x3F3F3F3Fu;
+            const uint32_t lo = (w[i] & 0x03030303u) | lane4;
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t k = 4 * i + j;
+                // byte 0 <- byte j of lo, byte 1 <- byte j of hi, bytes 2-3 <- 0
+                const uint32_t a = __builtin_amdgcn_perm(hi, lo, 0x0C0C0000u | ((4u + j) << 8) | j);
+                const uint32_t L = len8[a];
+                bits += (!kMask || k < m) ? L : 0u;
+                mn = min(mn, (!kMask || k < m) ? L : 255u);
+            }
         }
     };
     if (__all(m == kSyms))
@@ -484,7 +504,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     constexpr uint32_t kSyms = kQuadSyms * QPT;  // symbols per thread
     constexpr bool kHanded = QPT >= 2;           // bit counts from the length pass
     static_assert(!kHanded || kPacked, "tiles of more than 4096 symbols hold codes of <= 24 bits");
-    extern __shared__ uint32_t words[];  // the tile's code bits from bit 0, MSB first
+    extern __shared__ __attribute__((aligned(16))) uint32_t words[];  // the tile's code bits from bit 0, MSB first
     __shared__ uint32_t s_packed[kNumSym];
     __shared__ uint64_t s_code[kPacked ? 1 : kNumSym];
     __shared__ uint32_t s_len[kPacked ? 1 : kNumSym];
@@ -502,21 +522,34 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     }
     __syncthreads();
     const HC_G DevTables *__restrict__ tb = (const HC_G DevTables *)s_job.tb;
-    if (tb->max_len > shape_len) {  // the same in every lane: the group leaves together
-        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
-        return;
-    }
-    if (kPacked) {
-        s_packed[tid] = tb->enc_packed[tid];
-    } else {
-        s_code[tid] = tb->enc_code[tid];
-        s_len[tid] = tb->enc_len[tid];
-    }
-
     const HC_G uint8_t *__restrict__ in = (const HC_G uint8_t *)s_job.in;
     HC_G uint32_t *__restrict__ out32 = (HC_G uint32_t *)s_job.out;
     HC_G uint32_t *__restrict__ sub_idx = (HC_G uint32_t *)s_job.sub_idx;
     const Tile tl = tile_of(s_job.n, B, tpb, kTileSyms * QPT, t - s_job.unit_begin);
+    // The thread's symbols and bit count are requested before the table is
+    // checked, so that their latency overlaps the check's reads instead of
+    // following them.  Launches for complete 8-bit codes copy the tile
+    // instead and request nothing here.
+    const uint32_t s = tl.ts + kSyms * tid;
+    uint32_t w[4 * QPT];
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * QPT; ++i) w[i] = 0;
+    uint32_t m = copy_only ? 0u : load_syms<QPT>(in, tl, s, w);
+    uint32_t bits = (kHanded && !copy_only) ? (uint32_t)thread_bits[t * kTileThreads + tid] : 0u;
+    const uint32_t packed = kPacked ? tb->enc_packed[tid] : 0u;
+    if (tb->max_len > shape_len) {  // the same in every lane: the group leaves together
+        // (the loads' results are named on this path too, so that they stay
+        // ahead of the check rather than being sunk past it)
+        asm volatile("" ::"v"(w[0]), "v"(bits), "v"(packed));
+        if (tid == 0) report(err, HC_ERR_TABLE_CHANGED);
+        return;
+    }
+    if (kPacked) {
+        s_packed[tid] = packed;
+    } else {
+        s_code[tid] = tb->enc_code[tid];
+        s_len[tid] = tb->enc_len[tid];
+    }
     if (tl.ts >= tl.te) return;  // empty tile past a short last block (uniform over the group)
 
     const bool last_tile = tl.te == tl.cnt;
@@ -579,18 +612,14 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         return;
     }
     // the tile's words start at zero (ordered before the packing's ors by the
-    // barrier below)
-    for (uint32_t k = tid; k < lds_words; k += kTileThreads) words[k] = 0;
+    // barrier below), 16 bytes per write: lds_words is a multiple of 4
+    for (uint32_t k = 4 * tid; k < lds_words; k += 4 * kTileThreads) *(v4u *)(words + k) = v4u{0u, 0u, 0u, 0u};
     const uint32_t avail = last_tile ? 0u : (tl.cnt - tl.te < 32 ? tl.cnt - tl.te : 32u);
     if (tid < 32) s_next[tid] = tid < avail ? in[tl.blk_start + tl.te + tid] : 0u;
     if (tid == 32) {  // where the tile's bits go: from the offset pass
         s_P = tile_pos[t];
         s_O = ((const HC_G uint64_t *)s_job.block_off)[tl.blk];
     }
-    const uint32_t s = tl.ts + kSyms * tid;
-    uint32_t w[4 * QPT];
-    uint32_t m = load_syms<QPT>(in, tl, s, w);
-    uint32_t bits = kHanded ? (uint32_t)thread_bits[t * kTileThreads + tid] : 0u;
     __syncthreads();  // code tables and the next tile's first symbols are in LDS
 
     // Without handed counts the thread's symbols are coded twice from the LDS
@@ -638,11 +667,14 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         if (kPacked) {
             // FPS codes of <= 32/FPS bits are first joined in a 32-bit group
             // code (the entry's low 5 bits are the length, so one shift-or per
-            // code), then appended to the accumulator, which never exceeds 63
-            // bits; one flush retires at most one word.
+            // code), then appended to the accumulator, whose pending bits never
+            // exceed 63; one flush retires at most one word.  The bits above
+            // the pending ones are left in place, not cleared: every word taken
+            // out of the accumulator is 32 bits ending at its last pending bit,
+            // so they never reach one.
+            const uint32_t pos0 = q;  // the thread's first bit in the tile
             auto pack = [&](auto mask_tag) {
                 constexpr bool kMask = decltype(mask_tag)::value;
-                uint32_t run = 0;  // the thread's bits so far
                 // groups of FPS codes inside each 16-symbol load (FPS = 3
                 // leaves a last group of one), so that a load's first symbol
                 // always starts a group (the sub-block index positions)
@@ -651,7 +683,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
                 for (uint32_t q = 0; q < QPT; ++q) {
                     if (q) __builtin_amdgcn_sched_barrier(0);
                     asm volatile("" : "+v"(w[4 * q]), "+v"(w[4 * q + 1]), "+v"(w[4 * q + 2]), "+v"(w[4 * q + 3]));
-                    if (kHanded) qbits[q] = run;
+                    if (kHanded) qbits[q] = 32 * widx + nacc - pos0;  // the thread's bits so far
 #pragma unroll
                     for (uint32_t g = 0; g < kGroups; ++g) {
                         const uint32_t k = kQuadSyms * q + FPS * g;
@@ -666,16 +698,18 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
                                 gsum += e;  // the low byte sums the lengths (<= 32)
                             }
                         }
-                        const uint32_t gl = gsum & 255u;
-                        run += gl;
-                        acc = (acc << gl) | gc;
-                        nacc += gl;
-                        const uint32_t need = nacc >= 32 ? 1u : 0u;
-                        const uint32_t word = (uint32_t)(acc >> ((nacc - 32) & 63u));
-                        atomicOr(&words[widx], need ? word : 0u);
-                        nacc -= need << 5;
-                        acc &= (1ull << nacc) - 1ull;
-                        widx += need;
+                        // gsum's low byte is the group's length (<= 32); what
+                        // it holds above that only reaches bits >= 8 of nacc,
+                        // which the flush clears before they are read
+                        acc = (acc << (gsum & 63u)) | gc;
+                        nacc += gsum;
+                        // bit 5 of nacc: a whole word is pending (nacc <= 63);
+                        // it is the 32 bits ending at the last pending bit
+                        const uint32_t full = (uint32_t)((int32_t)(nacc << 26) >> 31);  // all ones or zero
+                        const uint32_t word = __builtin_amdgcn_alignbit((uint32_t)(acc >> 32), (uint32_t)acc, nacc);
+                        atomicOr(&words[widx], word & full);
+                        widx -= full;  // one word on when one was retired
+                        nacc &= 31u;
                     }
                 }
             };
@@ -745,11 +779,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const uint32_t e_bits = a + tile_total;
         const uint32_t k_last = (e_bits - 1) >> 5;
         const uint32_t fill = (!last_tile && (e_bits & 31u)) ? (s_lead >> (e_bits & 31u)) : 0u;
-        for (uint32_t k = (a ? 1u : 0u) + tid; k <= k_last; k += kTileThreads) {
-            uint32_t v = a ? ((words[k - 1] << (32 - a)) | (words[k] >> a)) : words[k];
-            if (k == k_last) v |= fill;
-            payload[k] = v;
-        }
+        const uint32_t k0 = a ? 1u : 0u;  // word 0 is the previous tile's when a > 0
+        auto word_at = [&](uint32_t k) { return a ? ((words[k - 1] << (32 - a)) | (words[k] >> a)) : words[k]; };
+        for (uint32_t k = k0 + tid; k < k_last; k += kTileThreads) payload[k] = word_at(k);
+        if (k_last >= k0 && tid == (k_last - k0) % kTileThreads) payload[k_last] = word_at(k_last) | fill;
     }
     const uint32_t blk_bits = (uint32_t)P + tile_total;  // the block's bit count, for its last tile
     if (last_tile && tid == 0) out32[O >> 2] = blk_bits;
@@ -1708,8 +1741,8 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 // The bit reader of one chunk in its wave's area: 'buf' holds the 64 area
-// bits from bit position p on (at least 33 of them the chunk's: two words
-// shifted by p mod 32); the table entries decoded since the last refill are
+// bits from the reader's position on (at least 33 of them the chunk's: two
+// words shifted by the bit offset); the table entries decoded since the last refill are
 // summed in esum, whose low byte is then their total length (refills come
 // after at most SPR codes, SPR * max_len <= 32).  So the next window starts
 // at most one word after this one: x0, x1 are this window's two area words
@@ -1721,68 +1754,101 @@ __device__ __forceinline__ void wave_lds_sync()
 template <bool kAhead>
 struct StageBits {
     uint64_t buf;
-    uint32_t p, esum;
+    uint32_t esum;
+    uint32_t sh;         // the window's first bit inside x0 (0..31)
+    const uint32_t *wp;  // the area word x0 is
     uint32_t x0, x1, x2;
 
-    __device__ __forceinline__ void window(const uint32_t *area)
+    // p: the chunk's first bit, counted from the area's first word
+    __device__ __forceinline__ void start(const uint32_t *area, uint32_t p, bool read)
     {
-        const uint32_t w = p >> 5;
-        x0 = area[w];
-        x1 = area[w + 1];
-        if (kAhead) x2 = area[w + 2];
-        buf = (((uint64_t)x0 << 32) | x1) << (p & 31u);
-    }
-    __device__ __forceinline__ void refill(const uint32_t *area)
-    {
-        const uint32_t p0 = p;
-        p += esum & 255u;
+        wp = area + (p >> 5);
+        sh = p & 31u;
         esum = 0;
+        if (read) window();
+    }
+    __device__ __forceinline__ void window()
+    {
+        x0 = wp[0];
+        x1 = wp[1];
+        if (kAhead) x2 = wp[2];
+        buf = (((uint64_t)x0 << 32) | x1) << sh;
+    }
+    // The word pointer and the bit offset are kept apart, so that a refill
+    // needs no address arithmetic beyond one add: the read-ahead word is
+    // wp[2] (an immediate offset) and the window shift is sh itself.
+    __device__ __forceinline__ void refill()
+    {
+        sh += esum & 255u;
+        esum = 0;
+        const uint32_t step = sh >> 5;  // whole words passed: at most one unless the chunk is corrupt
+        sh &= 31u;
+        wp += step;
         if (!kAhead) {
-            window(area);
+            window();
             return;
         }
-        const bool step = (p >> 5) != (p0 >> 5);  // at most 32 bits passed: the next word at most
-        x0 = step ? x1 : x0;
-        x1 = step ? x2 : x1;
-        buf = (((uint64_t)x0 << 32) | x1) << (p & 31u);
-        x2 = area[(p >> 5) + 2];
+        const bool adv = step != 0;
+        x0 = adv ? x1 : x0;
+        x1 = adv ? x2 : x1;
+        buf = (((uint64_t)x0 << 32) | x1) << sh;
+        x2 = wp[2];
     }
+    // the reader's bit position, counted from the area's first word
+    __device__ __forceinline__ uint32_t position(const uint32_t *area) const { return 32u * (uint32_t)(wp - area) + sh; }
 };
 
-// One code from the reader, as its table entry (symbol << 8) | length; an
-// invalid prefix reads as a 1-bit code flagged kLutBadFlag (or-ed into bad).
-// kLong: codes longer than the table take the canonical-range search on the
-// buffered bits (which hold >= max_len bits whenever a code starts).
+// One code from the reader: its symbol is returned (in byte 1 with kLong,
+// else byte 0) and its length taken from the bit buffer.  Where every code fits the table (!kLong) it is kept
+// as two byte tables, lengths and symbols, so that the chain from one code to
+// the next (length read, shift of the buffer, next index) uses the index
+// itself as the read address, and the symbol read is off that chain.  kLong:
+// the table holds (symbol << 8) | length (length 0: a longer code), and codes
+// longer than the table take the canonical-range search on the buffered bits
+// (which hold >= max_len bits whenever a code starts); these launches keep
+// the one table, whose registers fit them.  An invalid prefix reads as a
+// 1-bit code flagged kLutBadFlag (or-ed into bad).
 template <bool kLong, bool kAhead>
-__device__ __forceinline__ uint32_t stage_entry(StageBits<kAhead> &b, const uint16_t *lut, uint32_t lut_shift, uint32_t K,
+__device__ __forceinline__ uint32_t stage_entry(StageBits<kAhead> &b, const uint16_t *lut16, const uint8_t *lut_len,
+                                                const uint8_t *lut_sym, uint32_t lut_shift, uint32_t K,
                                                 uint32_t max_len, const uint32_t *s_first, const uint32_t *s_count,
                                                 const uint32_t *s_base, const uint32_t *s_sorted, uint32_t &bad)
 {
-    uint32_t e = lut[(uint32_t)(b.buf >> 32) >> lut_shift];
-    if (kLong && (e & 255u) == 0) {
-        uint32_t L = 0, sym = 0;
-        for (uint32_t l = K + 1; l <= max_len; ++l) {
-            const uint32_t cv = (uint32_t)(b.buf >> (64 - l));
-            const uint32_t d = cv - s_first[l];
-            if (d < s_count[l]) {
-                L = l;
-                sym = s_sorted[s_base[l] + d];
-                break;
+    const uint32_t i = (uint32_t)(b.buf >> 32) >> lut_shift;
+    // kLong: the entry, symbol in byte 1; otherwise the length, and the symbol in byte 0
+    uint32_t e, ret;
+    if (kLong) {
+        e = lut16[i];
+        if ((e & 255u) == 0) {
+            e = kLutBadFlag | 1u;
+            for (uint32_t l = K + 1; l <= max_len; ++l) {
+                const uint32_t cv = (uint32_t)(b.buf >> (64 - l));
+                const uint32_t d = cv - s_first[l];
+                if (d < s_count[l]) {
+                    e = (s_sorted[s_base[l] + d] << 8) | l;
+                    break;
+                }
             }
         }
-        e = L ? (sym << 8) | L : (kLutBadFlag | 1u);
+        ret = e;
+    } else {
+        e = lut_len[i];
+        ret = lut_sym[i];
     }
     bad |= e;
     b.buf <<= (e & 63u);
     b.esum += e;
-    return e;
+    return ret;
 }
 
-// The entry's byte 1 (the symbol) into byte q & 3 of a word, the other bytes kept.
-__device__ __forceinline__ uint32_t put_sym(uint32_t e, uint32_t word, uint32_t q)
+// The symbol (byte kB of s) into byte q & 3 of a word, the other bytes kept.
+template <uint32_t kB>
+__device__ __forceinline__ uint32_t put_sym(uint32_t s, uint32_t word, uint32_t q)
 {
-    constexpr uint32_t kSel[4] = {0x03020105u, 0x03020500u, 0x03050100u, 0x05020100u};
-    return __builtin_amdgcn_perm(e, word, kSel[q & 3]);
+    constexpr uint32_t x = 4 + kB;  // byte kB of the first operand
+    constexpr uint32_t kSel[4] = {0x03020100u & ~0xFFu | x, 0x03020100u & ~0xFF00u | (x << 8),
+                                  0x03020100u & ~0xFF0000u | (x << 16), 0x03020100u & ~0xFF000000u | (x << 24)};
+    return __builtin_amdgcn_perm(s, word, kSel[q & 3]);
 }
 
 // R symbols per round (16, or 8 for codes of 17..24 bits); refills follow
@@ -1804,7 +1870,10 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
     constexpr uint32_t kRoundWords = R / 4;
     constexpr uint32_t kChainRounds = kChainSyms / R;
     static_assert(kChainSyms % 16 == 0 && kChainSyms % R == 0, "whole 16-byte pieces per chunk");
-    __shared__ __attribute__((aligned(16))) uint16_t s_lut[1u << kLutB];
+    constexpr uint32_t kLutN = 1u << kLutB;
+    __shared__ __attribute__((aligned(16))) uint16_t s_lut16[kLong ? kLutN : 8];    // kLong: the table as it is
+    __shared__ __attribute__((aligned(16))) uint8_t s_lut_len[kLong ? 16 : kLutN];  // otherwise its length bytes
+    __shared__ __attribute__((aligned(16))) uint8_t s_lut_sym[kLong ? 16 : kLutN];  // and symbol bytes
     __shared__ __attribute__((aligned(16))) uint32_t s_area[kWaves * kStageWords + kStageSlackWords];
     __shared__ uint32_t s_first[kPackedMaxLen + 1];
     __shared__ uint32_t s_count[kPackedMaxLen + 1];
@@ -1832,9 +1901,20 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
         return;
     }
     {
-        // the table, 8 entries (16 bytes) per load
+        // the table, 8 entries (16 bytes) per load; without kLong split into
+        // its length bytes (byte 0 of each entry) and symbol bytes (byte 1)
         const uint32_t nq = (1u << K) >= 8 ? (1u << K) / 8 : 1u;
-        for (uint32_t k = tid; k < nq; k += kThreads) ((v4u *)s_lut)[k] = ((const HC_G v4u *)tb->lut)[k];
+        for (uint32_t k = tid; k < nq; k += kThreads) {
+            const v4u v = ((const HC_G v4u *)tb->lut)[k];
+            if (kLong) {
+                ((v4u *)s_lut16)[k] = v;
+            } else {
+                *(v2u *)(s_lut_len + 8 * k) =
+                    v2u{__builtin_amdgcn_perm(v.y, v.x, 0x06040200u), __builtin_amdgcn_perm(v.w, v.z, 0x06040200u)};
+                *(v2u *)(s_lut_sym + 8 * k) =
+                    v2u{__builtin_amdgcn_perm(v.y, v.x, 0x07050301u), __builtin_amdgcn_perm(v.w, v.z, 0x07050301u)};
+            }
+        }
     }
     if (tid <= (uint32_t)kPackedMaxLen) {
         s_first[tid] = (uint32_t)tb->first[tid];
@@ -1961,12 +2041,10 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
             StageBits<kChains == 1> rd[kChains];
 #pragma unroll
             for (uint32_t h = 0; h < kChains; ++h) {
-                rd[h].p = 32 * (uint32_t)(fw[h] - 4 * bq) + (uint32_t)(p0[h] & 31);
-                rd[h].esum = 0;
-                if (ok[h]) rd[h].window(area);
+                rd[h].start(area, 32 * (uint32_t)(fw[h] - 4 * bq) + (uint32_t)(p0[h] & 31), ok[h]);
             }
             auto entry = [&](uint32_t h) -> uint32_t {
-                return stage_entry<kLong, kChains == 1>(rd[h], s_lut, lut_shift, K, max_len, s_first, s_count, s_base,
+                return stage_entry<kLong, kChains == 1>(rd[h], s_lut16, s_lut_len, s_lut_sym, lut_shift, K, max_len, s_first, s_count, s_base,
                                                         s_sorted, bad);
             };
             uint32_t ow[kChains * kChainWords];
@@ -1990,10 +2068,10 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
 #pragma unroll
                         for (uint32_t q = 0; q < R; ++q) {
 #pragma unroll
-                            for (uint32_t h = 0; h < kChains; ++h) o4[h][q >> 2] = put_sym(entry(h), o4[h][q >> 2], q);
+                            for (uint32_t h = 0; h < kChains; ++h) o4[h][q >> 2] = put_sym<kLong ? 1 : 0>(entry(h), o4[h][q >> 2], q);
                             if ((q + 1) % SPR == 0 || q + 1 == R)
 #pragma unroll
-                                for (uint32_t h = 0; h < kChains; ++h) rd[h].refill(area);
+                                for (uint32_t h = 0; h < kChains; ++h) rd[h].refill();
                         }
 #pragma unroll
                         for (uint32_t h = 0; h < kChains; ++h)
@@ -2019,8 +2097,8 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
                                 for (uint32_t q = 0; q < kRoundWords; ++q) o4[q] = 0;
 #pragma unroll
                                 for (uint32_t q = 0; q < R; ++q) {
-                                    o4[q >> 2] = put_sym(entry(h), o4[q >> 2], q);
-                                    if ((q + 1) % SPR == 0 || q + 1 == R) rd[h].refill(area);
+                                    o4[q >> 2] = put_sym<kLong ? 1 : 0>(entry(h), o4[q >> 2], q);
+                                    if ((q + 1) % SPR == 0 || q + 1 == R) rd[h].refill();
                                 }
 #pragma unroll
                                 for (uint32_t q = 0; q < kRoundWords; ++q) ow[h * kChainWords + kRoundWords * r + q] = o4[q];
@@ -2029,8 +2107,8 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
                         done[h] = nfull * R;
                         HC_G uint8_t *const dst = out + blk_start[h] + s0[h];
                         for (uint32_t q = done[h]; q < s1[h] - s0[h]; ++q) {  // the ragged end of a block's last chunk
-                            dst[q] = (uint8_t)(entry(h) >> 8);
-                            rd[h].refill(area);
+                            dst[q] = (uint8_t)(entry(h) >> (kLong ? 8 : 0));
+                            rd[h].refill();
                         }
                     }
                 }
@@ -2082,7 +2160,7 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
                     }
                 }
                 if (ok[h]) {
-                    const uint64_t pos = 128 * bq + rd[h].p - 32 * pw0[h];  // payload bits consumed
+                    const uint64_t pos = 128 * bq + rd[h].position(area) - 32 * pw0[h];  // payload bits consumed
                     if (pos != p1[h]) report(err, HC_ERR_CORRUPT);
                     if (s1[h] == cnt[h] && (hdr[h] & 31u)) {
                         const uint32_t mask = (1u << (32 - (hdr[h] & 31u))) - 1u;
@@ -2126,7 +2204,9 @@ hipError_t launch_encode(const JobList &jl, uint64_t tiles, uint32_t B, uint32_t
     if (tiles == 0) return hipSuccess;
     const uint32_t tpb = tiles_per_block(B, qpt);
     // the packing's LDS words (none for complete 8-bit codes: tiles are copied)
-    const uint32_t lds_words = complete8 ? 0u : (uint32_t)(((uint64_t)kTileSyms * qpt * max_len + 31ull) / 32ull + 2);
+    // a multiple of 4: the packing clears the words 16 bytes at a time
+    const uint32_t lds_words =
+        complete8 ? 0u : (uint32_t)((((uint64_t)kTileSyms * qpt * max_len + 31ull) / 32ull + 2 + 3) & ~3ull);
     const uint32_t cpb = S ? (B + S - 1) / S : 1;
     uint32_t *tile_bits = static_cast<uint32_t *>(scratch);
     uint32_t *tile_pos = tile_bits + tiles;
