@@ -1403,6 +1403,35 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
         const uint64_t src_w = pw0 + (s0 >> 2);                  // stream word of the chunk's first symbol
         const uint64_t dst_a = (uint64_t)(out + blk_start + s0);  // 16-byte aligned
         const uint32_t okns = ok ? s1 - s0 : 0u;                  // symbols to copy (0: none)
+        {
+            // The usual case: the wave's 64 chunks whole and in one block, so
+            // its payload words and its output are each one contiguous range
+            // (consecutive chunks of a block are consecutive in both).  Lane l
+            // then copies words l + 64 m, every load and store instruction a
+            // contiguous 256 bytes, with all of the lane's words (32 at
+            // S = 128) in flight at once and no per-piece lane exchange.
+            const uint32_t i_lo = (uint32_t)i, i0 = __shfl(i_lo, 0, 64);
+            if (__all(ok && okns == S_eff && i_lo == i0 && (uint32_t)(i >> 32) == 0u)) {
+                const uint64_t s_w0 =
+                    ((uint64_t)__shfl((uint32_t)(src_w >> 32), 0, 64) << 32) | __shfl((uint32_t)src_w, 0, 64);
+                const uint64_t d_a0 =
+                    ((uint64_t)__shfl((uint32_t)(dst_a >> 32), 0, 64) << 32) | __shfl((uint32_t)dst_a, 0, 64);
+                const HC_G uint32_t *src = in32 + s_w0 + lane;
+                HC_G uint32_t *dst = (HC_G uint32_t *)d_a0 + lane;
+                const uint32_t per_lane = S_eff / 4;  // words of the wave / 64
+                constexpr uint32_t kU = 32;
+                for (uint32_t m0 = 0; m0 < per_lane; m0 += kU) {
+                    uint32_t v[kU];
+#pragma unroll
+                    for (uint32_t u = 0; u < kU; ++u)
+                        if (m0 + u < per_lane) v[u] = src[64 * (m0 + u)];
+#pragma unroll
+                    for (uint32_t u = 0; u < kU; ++u)
+                        if (m0 + u < per_lane) dst[64 * (m0 + u)] = __builtin_bswap32(v[u]);
+                }
+                return;
+            }
+        }
         const uint32_t pc = S_eff / 16;                           // 16-symbol pieces of a full chunk
         const uint32_t total = 64 * pc;                           // pieces of the wave's chunks
         for (uint32_t base = 0; base < total; base += 4 * 64) {
