@@ -787,11 +787,18 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const uint32_t blk_bits = (uint32_t)P + tile_total;  // the block's bit count, for its last tile
     if (last_tile && tid == 0) out32[O >> 2] = blk_bits;
     if (sub_idx) {
-        // S is a multiple of 16: entries fall on the first symbol of a load
+        // S and s are multiples of 16, so entries fall on the first symbol of
+        // a load: e is the first entry at or after symbol s, 'at' its offset
+        // from s, and each load's start is compared with it (one division
+        // per thread rather than a remainder and a quotient per load)
+        uint32_t e = (s + S - 1) / S, at = e * S - s;
 #pragma unroll
         for (uint32_t j = 0; j < QPT; ++j) {
-            const uint32_t sj = s + kQuadSyms * j;
-            if (m > kQuadSyms * j && (sj % S) == 0) sub_idx[tl.blk * cpb + sj / S] = (uint32_t)P + q + qbits[j];
+            if (m > kQuadSyms * j && at == kQuadSyms * j) {
+                sub_idx[tl.blk * cpb + e] = (uint32_t)P + q + qbits[j];
+                ++e;
+                at += S;
+            }
         }
         if (last_tile && tid == 0)
             for (uint32_t c = (tl.cnt + S - 1) / S; c < cpb; ++c) sub_idx[tl.blk * cpb + c] = blk_bits;
