@@ -471,7 +471,9 @@ def test_complete_8bit_code(hc, oracle):
     Any payload byte is a valid code, so a flipped payload byte decodes as
     the oracle decodes it; header, index and pad corruptions are rejected."""
     x = synth.uniform_bytes(70_003, 32)  # n % 4 != 0: pad bits in the last block
-    for B, S in ((4096, 0), (16384, 1024), (65536, 4096)):
+    # S = 128 with B >= 8 KiB: waves whose 64 chunks lie in one whole block take
+    # the contiguous copy, the others (the ragged last block) the general one
+    for B, S in ((4096, 0), (16384, 1024), (65536, 4096), (16384, 128), (65536, 128)):
         enc = check_full(hc, oracle, x, B, S, "complete 8-bit code")
         L = enc.codebook.host.lengths
         assert np.all(L == 8)
