@@ -12,11 +12,19 @@
 //                  OR-ed into LDS words, stored coalesced at the block's offset
 //                  in the stream with the header and zero pad
 //   k_walk         offset table rebuilt from the length delimiters
-//   k_decode_ring  table decode (sections 2.1 and 3.2) of codes <= 24 bits:
-//                  one lane per chunk of S symbols (or per block), whole
-//                  128-byte lines in from HBM through an LDS ring per lane and
-//                  out from registers
-//   k_decode       the same decode for codes of up to 64 bits
+//   k_decode_stage table decode (sections 2.1 and 3.2) with the sub-block
+//                  index, S <= 128, codes <= 24 bits: a wave stages its 64
+//                  chunks' words in LDS with coalesced loads, one lane decodes
+//                  each chunk, output stored through LDS
+//   k_decode_ring  the same decode for larger S or none, one lane per chunk
+//                  of S symbols (or per block), whole 128-byte lines in from
+//                  HBM through an LDS ring per lane; and the copy form of
+//                  complete 8-bit codes
+//   k_decode_sync  decode without the index: a block's pieces decoded in
+//                  parallel from their first bits, then again from where the
+//                  left neighbour's codes end until every piece starts on a
+//                  code boundary
+//   k_decode       the table decode for codes of up to 64 bits
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -781,8 +789,28 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         const uint32_t fill = (!last_tile && (e_bits & 31u)) ? (s_lead >> (e_bits & 31u)) : 0u;
         const uint32_t k0 = a ? 1u : 0u;  // word 0 is the previous tile's when a > 0
         auto word_at = [&](uint32_t k) { return a ? ((words[k - 1] << (32 - a)) | (words[k] >> a)) : words[k]; };
-        for (uint32_t k = k0 + tid; k < k_last; k += kTileThreads) payload[k] = word_at(k);
-        if (k_last >= k0 && tid == (k_last - k0) % kTileThreads) payload[k_last] = word_at(k_last) | fill;
+        // words k0 .. k_last - 1: four per thread per round, 256 apart, so
+        // that each store instruction still writes 256 contiguous bytes while
+        // the round's addresses are immediate offsets of one base
+        const uint32_t nk = k_last > k0 ? k_last - k0 : 0u;
+        if (a) {
+            for (uint32_t g = tid; g < nk; g += 4 * kTileThreads) {
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    const uint32_t i = g + u * kTileThreads;  // stream word 1 + i
+                    if (i < nk) payload[1 + i] = __builtin_amdgcn_alignbit(words[i], words[i + 1], a);
+                }
+            }
+        } else {
+            for (uint32_t g = tid; g < nk; g += 4 * kTileThreads) {
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    const uint32_t i = g + u * kTileThreads;
+                    if (i < nk) payload[i] = words[i];
+                }
+            }
+        }
+        if (k_last >= k0 && tid == kTileThreads - 1) payload[k_last] = word_at(k_last) | fill;
     }
     const uint32_t blk_bits = (uint32_t)P + tile_total;  // the block's bit count, for its last tile
     if (last_tile && tid == 0) out32[O >> 2] = blk_bits;
