@@ -430,9 +430,14 @@ class Server:
             elif self.clock() - last > stall_seconds:
                 raise RuntimeError("serving loop made no progress (budget too small for the admitted requests)")
             if not self.inflight and not self.counting and self.waiting:
+                # idle until the next arrival: sleep only to within 0.5 ms of
+                # it and poll from there, so that an oversleeping timer never
+                # adds to a request's latency (an iteration with nothing on
+                # the device is cheap)
                 wait = self.waiting[0].arrival - self.clock()
+                if wait > 0.001:
+                    time.sleep(min(wait - 0.0005, 0.002))
                 if wait > 0:
-                    time.sleep(min(wait, 0.002))
                     last = self.clock()
         return self.done
 
