@@ -1775,25 +1775,39 @@ constexpr uint32_t kStageWords = 64 * kStageMaxS / 4 + 16;
 static_assert(kStageWords >= 32 * 36, "half a wave's output lines fit the area");
 static_assert(kStageWords % 4 == 0 && kStageWords >= (kStageMaxS * kPackedMaxLen) / 32 + 16, "area too small");
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+// The minimum (maximum) of a 64-bit value over all 64 lanes, the same in
+// every lane.  Data-parallel moves (DPP) instead of lane exchanges through
+// the LDS unit: an inclusive scan within each row of 16 lanes (shifts by 1,
+// 2, 4, 8), then row 0's result into row 1 and row 2's into row 3 (the
+// broadcast of lane 15), then rows 0-1 into rows 2-3 (the broadcast of lane
+// 31); lane 63 ends with the wave's result, read out as a scalar.  Every step
+// is a VALU move, where each step of a lane exchange waited on an LDS round
+// trip.  All 64 lanes must be active.
+template <bool kMin>
+__device__ __forceinline__ uint64_t wave_reduce_u64(uint64_t v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint64_t o = __shfl_xor(v, d, 64);
-        v = o < v ? o : v;
-    }
-    return v;
+    auto step = [&](auto ctrl, auto rows) {
+        constexpr int kCtrl = decltype(ctrl)::value, kRows = decltype(rows)::value;
+        // lanes without a source in range keep their own value
+        const uint32_t lo = __builtin_amdgcn_update_dpp((uint32_t)v, (uint32_t)v, kCtrl, kRows, 0xF, false);
+        const uint32_t hi =
+            __builtin_amdgcn_update_dpp((uint32_t)(v >> 32), (uint32_t)(v >> 32), kCtrl, kRows, 0xF, false);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = kMin ? (o < v ? o : v) : (o > v ? o : v);
+    };
+    using std::integral_constant;
+    step(integral_constant<int, 0x111>(), integral_constant<int, 0xF>());  // row_shr:1
+    step(integral_constant<int, 0x112>(), integral_constant<int, 0xF>());  // row_shr:2
+    step(integral_constant<int, 0x114>(), integral_constant<int, 0xF>());  // row_shr:4
+    step(integral_constant<int, 0x118>(), integral_constant<int, 0xF>());  // row_shr:8
+    step(integral_constant<int, 0x142>(), integral_constant<int, 0xA>());  // row_bcast:15 into rows 1, 3
+    step(integral_constant<int, 0x143>(), integral_constant<int, 0xC>());  // row_bcast:31 into rows 2, 3
+    return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), 63) << 32) |
+           __builtin_amdgcn_readlane((uint32_t)v, 63);
 }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint64_t o = __shfl_xor(v, d, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) { return wave_reduce_u64<true>(v); }
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) { return wave_reduce_u64<false>(v); }
 
 // LDS written by some lanes of a wave, then read by others: the writes are
 // complete before any lane reads.
@@ -2076,7 +2090,9 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
             }
             continue;
         }
-        const uint32_t nq = (uint32_t)(eq - bq);  // <= area_quads
+        // <= area_quads by the choice of 'take'; clamped all the same, so that
+        // the copy below never writes past the wave's area
+        const uint32_t nq = (uint32_t)(eq - bq < area_quads ? eq - bq : area_quads);
         {
             constexpr uint32_t kU = 8;  // loads in flight per lane: 8 KiB per wave
             for (uint32_t q0 = 0; q0 < nq; q0 += 64 * kU) {
