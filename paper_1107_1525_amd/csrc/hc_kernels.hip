@@ -61,24 +61,66 @@ __device__ __forceinline__ void report(uint32_t *err, uint32_t code)
     if (err && *(volatile uint32_t *)err == 0u) atomicCAS(err, 0u, code);
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_scan(T x)
+// Inclusive scan of 32-bit values over the 64 lanes with data-parallel moves
+// (DPP), every lane active: within each row of 16 lanes by shifts of 1, 2, 4
+// and 8, then the total of row 0 into row 1 and of row 2 into row 3 (lane 15's
+// broadcast), then that of rows 0-1 into rows 2-3 (lane 31's).  Each step is
+// a VALU move, where a lane exchange through the LDS unit waits on a round
+// trip.  Op: + or |, identity 0 (a lane with no source in range adds 0).
+template <bool kOr>
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t x)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        T y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    auto step = [&](auto ctrl, auto rows) {
+        const uint32_t y =
+            __builtin_amdgcn_update_dpp(0u, x, decltype(ctrl)::value, decltype(rows)::value, 0xF, false);
+        x = kOr ? (x | y) : (x + y);
+    };
+    using std::integral_constant;
+    step(integral_constant<int, 0x111>(), integral_constant<int, 0xF>());  // row_shr:1
+    step(integral_constant<int, 0x112>(), integral_constant<int, 0xF>());  // row_shr:2
+    step(integral_constant<int, 0x114>(), integral_constant<int, 0xF>());  // row_shr:4
+    step(integral_constant<int, 0x118>(), integral_constant<int, 0xF>());  // row_shr:8
+    step(integral_constant<int, 0x142>(), integral_constant<int, 0xA>());  // row_bcast:15 into rows 1, 3
+    step(integral_constant<int, 0x143>(), integral_constant<int, 0xC>());  // row_bcast:31 into rows 2, 3
     return x;
 }
 
+// Every caller runs it with all 64 lanes of the wave active.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x)
+{
+    if constexpr (std::is_same<T, uint32_t>::value) {
+        return wave_scan_dpp<false>(x);
+    } else {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            T y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        return x;
+    }
+}
+
+// Every caller runs it with all 64 lanes of the wave active.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x)
 {
+    if constexpr (std::is_same<T, uint32_t>::value)
+        return (uint32_t)__builtin_amdgcn_readlane(wave_scan_dpp<false>(x), 63);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
     return x;
+}
+
+// Lane 'l''s 64-bit value in every lane, as a scalar.  The lane read
+// returns a signed int: each half is taken as uint32_t before widening, or
+// the low half would be sign-extended into the high one.
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int l)
+{
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((uint32_t)v, l);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Exclusive scan across the work-group; 'scratch' holds one entry per wave.
@@ -753,10 +795,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
             const uint32_t L = e & 255u;
             const uint32_t pos = wave_inclusive_scan(L) - L;
             // L <= 24: the code fits the 64-bit window when it starts in the first 32 bits
-            uint64_t v = (L && pos < 32) ? ((uint64_t)(e >> 8) << (64 - pos - L)) : 0ull;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
-            if (l == 0) s_lead = (uint32_t)(v >> 32);
+            const uint64_t v = (L && pos < 32) ? ((uint64_t)(e >> 8) << (64 - pos - L)) : 0ull;
+            // the first 32 bits: the OR of every lane's high word (lane 63 holds it)
+            const uint32_t lead = (uint32_t)__builtin_amdgcn_readlane(wave_scan_dpp<true>((uint32_t)(v >> 32)), 63);
+            if (l == 0) s_lead = lead;
         }
     } else if (tid == 64) {
         uint64_t lead = 0;
@@ -1445,12 +1487,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_ring(JobList jl, uint32_
             // then copies words l + 64 m, every load and store instruction a
             // contiguous 256 bytes, with all of the lane's words (32 at
             // S = 128) in flight at once and no per-piece lane exchange.
-            const uint32_t i_lo = (uint32_t)i, i0 = __shfl(i_lo, 0, 64);
+            // (every lane of the wave is here: lane 0's values are read directly)
+            const uint32_t i_lo = (uint32_t)i, i0 = (uint32_t)__builtin_amdgcn_readlane(i_lo, 0);
             if (__all(ok && okns == S_eff && i_lo == i0 && (uint32_t)(i >> 32) == 0u)) {
-                const uint64_t s_w0 =
-                    ((uint64_t)__shfl((uint32_t)(src_w >> 32), 0, 64) << 32) | __shfl((uint32_t)src_w, 0, 64);
-                const uint64_t d_a0 =
-                    ((uint64_t)__shfl((uint32_t)(dst_a >> 32), 0, 64) << 32) | __shfl((uint32_t)dst_a, 0, 64);
+                const uint64_t s_w0 = read_lane_u64(src_w, 0);
+                const uint64_t d_a0 = read_lane_u64(dst_a, 0);
                 const HC_G uint32_t *src = in32 + s_w0 + lane;
                 HC_G uint32_t *dst = (HC_G uint32_t *)d_a0 + lane;
                 const uint32_t per_lane = S_eff / 4;  // words of the wave / 64
@@ -1802,8 +1843,7 @@ __device__ __forceinline__ uint64_t wave_reduce_u64(uint64_t v)
     step(integral_constant<int, 0x118>(), integral_constant<int, 0xF>());  // row_shr:8
     step(integral_constant<int, 0x142>(), integral_constant<int, 0xA>());  // row_bcast:15 into rows 1, 3
     step(integral_constant<int, 0x143>(), integral_constant<int, 0xC>());  // row_bcast:31 into rows 2, 3
-    return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), 63) << 32) |
-           __builtin_amdgcn_readlane((uint32_t)v, 63);
+    return read_lane_u64(v, 63);
 }
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) { return wave_reduce_u64<true>(v); }
@@ -2201,7 +2241,7 @@ __global__ __launch_bounds__(kDecThreads / kChains) __attribute__((amdgpu_waves_
                 // writes a contiguous 1 KiB instead of touching 64 lines
                 const uint64_t a0 = (uint64_t)(out + blk_start[0] + s0[0]);
                 HC_G uint8_t *const base =
-                    (HC_G uint8_t *)((((uint64_t)__shfl((uint32_t)(a0 >> 32), 0, 64)) << 32) | __shfl((uint32_t)a0, 0, 64));
+                    (HC_G uint8_t *)read_lane_u64(a0, 0);
                 wave_lds_sync();  // the decode's reads of the area are done
 #pragma unroll
                 for (uint32_t half = 0; half < 2; ++half) {
